@@ -1,0 +1,247 @@
+"""Benchmark of the neural six-way lightmaps hot path on one MI355X.
+
+One step = one frame of the whole path through lnm_frame: guiding-map march
+of a 128^3 smoke grid (24 blobs + value noise) seen by a 60-degree perspective
+camera at 256x256 with a 4-voxel step, the 4-level base-32 U-Net, and six-way
+shading for one light.  Inputs (grid, weights, buffers) are resident in HBM
+before the timed region.  The same frame is timed with the fp32 network
+(`value`) and the bf16 network (`modes.bf16`).  Prints one JSON line.
+
+Usage: python bench.py [--steps K] [--warmup W] [--dtype fp32|bf16] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "lightmap frames/s at 128³ grid/256² view, FP32 vs BF16; served p50/p99 latency"
+# published dense matrix peaks of MI355X (TFLOP/s) and HBM bandwidth (GB/s)
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    sys.stderr.write(msg + "\n")
+    sys.stderr.flush()
+
+
+def cpu_baseline(wl, params, light, seconds):
+    """Time the fp64 oracle on whole frames of the same workload."""
+    import oracle
+
+    vol = wl.volume()
+    n, t_total = 0, 0.0
+    while True:
+        t0 = time.perf_counter()
+        g, _, _ = oracle.march(vol, 8.0, wl.camera, wl.step_voxels, seed=0, frame=n)
+        lm, _ = oracle.unet_forward(params, wl.levels, wl.base, g)
+        oracle.composite(lm, g, wl.camera, [light])
+        t_total += time.perf_counter() - t0
+        n += 1
+        log(f"cpu oracle frame {n}: {t_total / n:.2f} s/frame")
+        if t_total >= seconds or n >= 8:
+            break
+    return {"value": round(n / t_total, 4), "unit": "frames/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n} whole frame(s) (march + U-Net + shading) of the same 128^3 / 256x256 workload in fp64, "
+                      f"{t_total:.1f} s"}
+
+
+def measure(lnm, ctx, net, dens, wl, light, steps, warmup, stream):
+    import torch
+
+    H, W = wl.camera.height, wl.camera.width
+    dev = dens.device
+    guide = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+    lm = torch.empty((H, W, 6), dtype=torch.float32, device=dev)
+    rgba = torch.empty((H, W, 4), dtype=torch.float32, device=dev)
+    ws = net.workspace(1, H, W)
+    prm = lnm.make_params(wl.step_voxels, seed=0)
+
+    def step(i):
+        prm.frame = i
+        net.frame(dens, 8.0, wl.camera, prm, lights=[light], guide=guide, lightmaps=lm, rgba=rgba, workspace=ws,
+                  stream=stream)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    # per-kernel durations: HIP events the library records around each launch
+    nprof = max(20, min(steps, 200))
+    ctx.profile(True)
+    for i in range(nprof):
+        step(i)
+    torch.cuda.synchronize()
+    stage = {}
+    for name, k in (("march", lnm.K_MARCH), ("conv3x3", lnm.K_CONV), ("head", lnm.K_HEAD),
+                    ("composite", lnm.K_COMPOSITE)):
+        n, ms = ctx.profile_read(k)
+        stage[name] = {"launches_per_frame": n / nprof, "us_per_frame": 1e3 * ms / nprof,
+                       "us_per_launch": 1e3 * ms / max(n, 1)}
+    ctx.profile(False)
+    return {"fps": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "stage": stage}
+
+
+def served(lnm, ctx, params, seconds, warmup_s, rate_hz=2000.0, budget_gb=64.0, n_instances=64, seed=7):
+    """Continuous-batching server: n_instances smoke instances (grids
+    {64,96,128,192,256}^3, views {128,256,512}^2, own seeded blobs + noise and
+    light), Poisson arrivals at rate_hz, bf16 network, HBM budget."""
+    import torch
+
+    from paper_2604_03748_amd.serve import Backend, Instance, Scheduler, poisson_requests
+    from synth.rng import substream
+    from synth.scene import light_direction, make_volume_torch
+
+    grids, views = (64, 96, 128, 192, 256), (128, 256, 512)
+    pick = substream(seed, "instances").uniform(2 * n_instances).reshape(n_instances, 2)
+    insts = {}
+    for k in range(n_instances):
+        n = grids[int(pick[k, 0] * len(grids))]
+        res = views[int(pick[k, 1] * len(views))]
+        insts[k] = Instance(k, make_volume_torch(n, 24, 1000 + k, 0.3, device="cuda"), res,
+                            start_deg=(37.0 * k) % 360.0, seed=1000 + k,
+                            light=(tuple(light_direction(1000 + k)), (1.0, 1.0, 1.0)))
+    torch.cuda.synchronize()
+    net = lnm.Net(ctx, 4, 32, params, precision=lnm.BF16)
+    be = Backend(ctx, net, n_streams=4)
+    budget = int(budget_gb * 2**30)
+    if warmup_s > 0:
+        Scheduler(be, insts, budget, max_batch=16).run(poisson_requests(n_instances, rate_hz, warmup_s, seed + 1))
+    reqs = poisson_requests(n_instances, rate_hz, seconds, seed)
+    sch = Scheduler(be, insts, budget, max_batch=16)
+    st = sch.run(reqs)
+    st.update({"offered_rate_fps": rate_hz, "instances": n_instances, "duration_s": seconds,
+               "grids": sorted({v.density.shape[0] for v in insts.values()}), "views": list(views),
+               "dtype": "bf16", "budget_gb": budget_gb})
+    return st
+
+
+def precision_report(lnm, ctx, wl, params, dens):
+    """Max / mean abs error per lightmap channel of fp32, bf16 and fp8
+    against the fp64 oracle, on one frame's guiding map."""
+    import numpy as np
+    import torch
+
+    import oracle
+
+    prm = lnm.make_params(wl.step_voxels, seed=0)
+    g = ctx.march(dens, 8.0, wl.camera, prm)
+    gh = g.cpu().numpy().astype(np.float64)
+    ref, _ = oracle.unet_forward(params, wl.levels, wl.base, gh)
+    n32 = lnm.Net(ctx, wl.levels, wl.base, params)
+    calib = [ctx.march(dens, 8.0, wl.camera, lnm.make_params(wl.step_voxels, seed=0, frame=f)) for f in range(1, 5)]
+    amax = np.max([n32.calibrate_amax(c) for c in calib], axis=0)
+    nets = {"fp32": n32, "bf16": lnm.Net(ctx, wl.levels, wl.base, params, precision=lnm.BF16),
+            "fp8": lnm.Net(ctx, wl.levels, wl.base, params, precision=lnm.FP8_E4M3, act_scales=amax)}
+    out = {}
+    for k, net in nets.items():
+        lm = net.infer(g)
+        torch.cuda.synchronize()
+        d = np.abs(lm.cpu().numpy().astype(np.float64) - ref).reshape(-1, 6)
+        out[k] = {"max_abs": [round(float(x), 6) for x in d.max(axis=0)],
+                  "mean_abs": [round(float(x), 7) for x in d.mean(axis=0)]}
+    out["weights"] = "He-normal seed 0 (untrained)"
+    return out, amax
+
+
+def conv_roofline(wl, stage, dtype):
+    from synth.weights import unet_flops, unet_layers
+
+    H, W = wl.camera.height, wl.camera.width
+    n_conv = sum(1 for l in unet_layers(wl.levels, wl.base) if l[3] == 3)
+    conv_flops = unet_flops(wl.levels, wl.base, 1, H, W) - 2.0 * H * W * 6 * wl.base  # 3x3 layers only
+    per_launch = conv_flops / n_conv
+    us = stage["conv3x3"]["us_per_launch"]
+    achieved = per_launch / (us * 1e-6) / 1e12
+    kern = {"fp32": "conv3x3_f32 (v_mfma_f32_16x16x4_f32)", "bf16": "conv3x3_bf16 (v_mfma_f32_16x16x32_bf16)",
+            "fp8": "conv3x3_fp8 (v_mfma_f32_16x16x32_fp8_fp8)"}[dtype]
+    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_TFLOPS[dtype], 5), "traffic": None, "kernel": kern,
+            "flops_per_launch": round(per_launch), "us_per_launch": round(us, 3), "launches_per_frame": n_conv}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--only", action="store_true", help="time only --dtype")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: frames and smoke instances are "
+              f"independent, so the path shards by frame or instance with no exchange", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2604_03748_amd import lnm
+    from synth.scene import headline, light_direction
+    from synth.weights import he_normal_params
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    wl = headline()
+    params = he_normal_params(wl.levels, wl.base, seed=0)
+    light = (tuple(light_direction(0)), (1.0, 1.0, 1.0))
+    ctx = lnm.Context(0)
+    dens = torch.as_tensor(wl.volume(), device=dev)
+    stream = torch.cuda.current_stream()
+    prec = {"fp32": lnm.FP32, "bf16": lnm.BF16}
+    order = [args.dtype] + ([] if args.only else [d for d in ("fp32", "bf16") if d != args.dtype])
+    res = {}
+    for dt in order:
+        net = lnm.Net(ctx, wl.levels, wl.base, params, precision=prec[dt])
+        r = measure(lnm, ctx, net, dens, wl, light, args.steps, args.warmup, stream)
+        r["roofline"] = conv_roofline(wl, r["stage"], dt)
+        res[dt] = r
+        stages = ", ".join("%s: %.1f us" % (k, v["us_per_frame"]) for k, v in r["stage"].items())
+        log(f"{dt}: {r['ms_per_step']:.4f} ms/frame, {r['fps']:.1f} frames/s, stages {stages}")
+        del net
+
+    main_r = res[args.dtype]
+    H, W = wl.camera.height, wl.camera.width
+    out = {
+        "metric": METRIC,
+        "value": round(main_r["fps"], 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_r["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic (seeded blob+noise smoke grid, He-normal weights)",
+        "config": {"workload": "persp128_256px", "grid": 128, "blobs": 24, "noise_amp": 0.3, "view": [H, W],
+                   "camera": "perspective 60deg at 2.5", "step_voxels": wl.step_voxels, "unet_levels": wl.levels,
+                   "unet_base": wl.base, "batch": 1, "lights": 1},
+        "roofline": main_r["roofline"],
+        "stages_us_per_frame": {k: round(v["us_per_frame"], 2) for k, v in main_r["stage"].items()},
+        "modes": {dt: {"value": round(r["fps"], 2), "ms_per_step": round(r["ms_per_step"], 5),
+                       "roofline": r["roofline"],
+                       "stages_us_per_frame": {k: round(v["us_per_frame"], 2) for k, v in r["stage"].items()}}
+                  for dt, r in res.items() if dt != args.dtype},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, params, light, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -53,7 +53,7 @@ def lib():
         L.orc_sigma_vol.argtypes = [_F, C.c_int, C.c_int, C.c_int, C.c_double, _D]
         L.orc_march.restype = C.c_int
         L.orc_march.argtypes = [_F, C.c_int, C.c_int, C.c_int, C.c_double, _D, C.c_double, C.c_double, C.c_double,
-                                C.c_int, C.c_uint64, C.c_uint32, C.c_int, _D, C.c_int, _D, _D,
+                                C.c_int, C.c_uint64, C.c_uint32, C.c_int, _D, C.c_int, C.c_int, _D, _D,
                                 C.POINTER(C.c_longlong)]
         L.orc_front_identity_gap.restype = C.c_double
         L.orc_front_identity_gap.argtypes = [_F, C.c_int, C.c_int, C.c_int, C.c_double, _D, C.c_double, C.c_int,
@@ -121,17 +121,18 @@ def sigma_at(volume, sigma_scale, p) -> float:
 
 
 def march(volume, sigma_scale, cam, step_voxels, depth_tau=0.1, ert_eps=1e-6, jitter=True, seed=0, frame=0,
-          quadrature=0, light_w=(1.0, 1.0, 1.0), unit_radiance=False):
+          quadrature=0, light_w=(1.0, 1.0, 1.0), unit_radiance=False, stride=1):
     """Guiding map [H][W][3] = (L~, T, D), the depth margin [H][W] and
-    (primary, secondary) sample counts."""
+    (primary, secondary) sample counts.  With stride > 1 only pixels on that
+    lattice are computed (others stay 0; margin +inf)."""
     v = _f32(volume)
     nz, ny, nx = v.shape
     g = np.zeros((cam.height, cam.width, 3), dtype=np.float64)
-    m = np.zeros((cam.height, cam.width), dtype=np.float64)
+    m = np.full((cam.height, cam.width), np.inf, dtype=np.float64)
     cnt = (C.c_longlong * 2)()
     st = lib().orc_march(_fp(v), nx, ny, nz, sigma_scale, _dp(camera_array(cam)), step_voxels, depth_tau, ert_eps,
-                         int(jitter), seed, frame, quadrature, _dp(_f64(light_w)), int(unit_radiance), _dp(g), _dp(m),
-                         cnt)
+                         int(jitter), seed, frame, quadrature, _dp(_f64(light_w)), int(unit_radiance), int(stride), _dp(g),
+                         _dp(m), cnt)
     if st:
         raise ValueError(f"orc_march status {st}")
     return g, m, (cnt[0], cnt[1])

@@ -203,12 +203,15 @@ static double light_transmittance(const Vol* v, const double* x, const double* l
  * counters[2] (optional): primary and secondary sample counts.
  * unit_radiance != 0 replaces L_n by 1 (diagnostic for the identity
  * sum A_n = 1 - T).
+ * stride > 1 computes only pixels whose row and column are multiples of it
+ * (the others are left untouched), for spot checks of large images.
  */
 ORC_EXPORT int orc_march(const float* rho, int nx, int ny, int nz, double sigma_scale, const double* cam,
                          double step_voxels, double depth_tau, double ert_eps, int jitter_on, uint64_t jitter_seed,
-                         uint32_t frame, int quadrature, const double* light_w, int unit_radiance, double* guide,
-                         double* d_margin, long long* counters) {
-  if (!rho || !cam || !guide || nx < 1 || ny < 1 || nz < 1 || step_voxels <= 0.0 || ert_eps < 0.0) return 1;
+                         uint32_t frame, int quadrature, const double* light_w, int unit_radiance, int stride,
+                         double* guide, double* d_margin, long long* counters) {
+  if (!rho || !cam || !guide || nx < 1 || ny < 1 || nz < 1 || step_voxels <= 0.0 || ert_eps < 0.0 || stride < 1)
+    return 1;
   Vol v = {rho, nx, ny, nz, sigma_scale};
   Cam k;
   cam_setup(cam, &k);
@@ -218,8 +221,8 @@ ORC_EXPORT int orc_march(const float* rho, int nx, int ny, int nz, double sigma_
   const double tau_max = ert_eps > 0.0 ? -log(ert_eps) : INFINITY;
   long long c_primary = 0, c_secondary = 0;
 #pragma omp parallel for schedule(dynamic, 4) reduction(+ : c_primary, c_secondary)
-  for (int j = 0; j < k.H; ++j) {
-    for (int i = 0; i < k.W; ++i) {
+  for (int j = 0; j < k.H; j += stride) {
+    for (int i = 0; i < k.W; i += stride) {
       double o[3], d[3], w[3], top[3], bot[3];
       cam_ray(&k, i, j, o, d);
       for (int a = 0; a < 3; ++a) w[a] = -d[a];

@@ -1,0 +1,709 @@
+// C ABI of liblnm: argument validation, weight packing, the layer schedule of
+// the U-Net and the entry points declared in lnm.h.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace lnm {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+lnm_status fail(lnm_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+ProfScope::ProfScope(lnm_ctx_s* ctx, int kind, hipStream_t s) : ctx_(ctx), s_(s) {
+  if (!ctx || !ctx->prof || ctx->recs.size() >= 65536) return;
+  while (ctx->pool.size() < ctx->pool_used + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    ctx->pool.push_back(e);
+  }
+  lnm_ctx_s::Rec r{kind, ctx->pool[ctx->pool_used], ctx->pool[ctx->pool_used + 1]};
+  if (hipEventRecord(r.a, s) != hipSuccess) return;
+  ctx->pool_used += 2;
+  idx_ = (int)ctx->recs.size();
+  ctx->recs.push_back(r);
+}
+
+ProfScope::~ProfScope() {
+  if (idx_ >= 0) (void)hipEventRecord(ctx_->recs[idx_].b, s_);
+}
+
+static bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+bool make_cam(const lnm_camera& c, CamDev* out, std::string* why) {
+  if (c.projection != LNM_ORTHOGRAPHIC && c.projection != LNM_PERSPECTIVE) return *why = "camera.projection", false;
+  if (c.width < 1 || c.height < 1) return *why = "camera width/height must be >= 1", false;
+  if (!finite3(c.eye) || !finite3(c.target) || !finite3(c.up)) return *why = "camera vectors must be finite", false;
+  double f[3], r[3], u[3];
+  for (int a = 0; a < 3; ++a) f[a] = (double)c.target[a] - c.eye[a];
+  double nf = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  if (!(nf > 0.0)) return *why = "camera target equals eye", false;
+  for (double& v : f) v /= nf;
+  r[0] = f[1] * c.up[2] - f[2] * c.up[1];
+  r[1] = f[2] * c.up[0] - f[0] * c.up[2];
+  r[2] = f[0] * c.up[1] - f[1] * c.up[0];
+  double nr = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (!(nr > 1e-12)) return *why = "camera up is parallel to the view direction", false;
+  for (double& v : r) v /= nr;
+  u[0] = r[1] * f[2] - r[2] * f[1];
+  u[1] = r[2] * f[0] - r[0] * f[2];
+  u[2] = r[0] * f[1] - r[1] * f[0];
+  if (c.projection == LNM_PERSPECTIVE && !(c.fov_y_deg > 0.0f && c.fov_y_deg < 180.0f))
+    return *why = "camera.fov_y_deg must be in (0, 180)", false;
+  if (c.projection == LNM_ORTHOGRAPHIC && !(c.ortho_half_extent > 0.0f && std::isfinite(c.ortho_half_extent)))
+    return *why = "camera.ortho_half_extent must be > 0", false;
+  for (int a = 0; a < 3; ++a) {
+    out->eye[a] = c.eye[a];
+    out->f[a] = (float)f[a];
+    out->r[a] = (float)r[a];
+    out->u[a] = (float)u[a];
+  }
+  out->tan_half = (float)std::tan(0.5 * (double)c.fov_y_deg * M_PI / 180.0);
+  out->half_extent = c.ortho_half_extent;
+  out->aspect = (float)((double)c.width / (double)c.height);
+  out->proj = c.projection;
+  out->W = c.width;
+  out->H = c.height;
+  return true;
+}
+
+static lnm_status check_volume(const lnm_volume* v) {
+  if (!v) return fail(LNM_ERR_ARG, "volume is NULL");
+  if (!v->density) return fail(LNM_ERR_ARG, "volume.density is NULL");
+  if (v->nx < 1 || v->ny < 1 || v->nz < 1) return fail(LNM_ERR_SHAPE, "volume dimensions must be >= 1");
+  if ((double)v->nx * v->ny * v->nz > 4.0e9) return fail(LNM_ERR_SHAPE, "volume larger than 2^32 voxels");
+  if (!(v->sigma_scale >= 0.0f) || !std::isfinite(v->sigma_scale))
+    return fail(LNM_ERR_ARG, "volume.sigma_scale must be finite and >= 0");
+  return LNM_OK;
+}
+
+static lnm_status march_setup(const lnm_volume* vol, const lnm_camera* cam, const lnm_march_params* prm,
+                              MarchDev* m, CamDev* c) {
+  lnm_status st = check_volume(vol);
+  if (st) return st;
+  if (!cam || !prm) return fail(LNM_ERR_ARG, "camera or params is NULL");
+  std::string why;
+  if (!make_cam(*cam, c, &why)) return fail(LNM_ERR_ARG, why);
+  if (!(prm->step_voxels > 0.0f) || !std::isfinite(prm->step_voxels))
+    return fail(LNM_ERR_ARG, "params.step_voxels must be > 0");
+  if (!(prm->depth_tau >= 0.0f) || !std::isfinite(prm->depth_tau)) return fail(LNM_ERR_ARG, "params.depth_tau");
+  if (!(prm->ert_eps >= 0.0f && prm->ert_eps < 1.0f)) return fail(LNM_ERR_ARG, "params.ert_eps must be in [0, 1)");
+  if (prm->quadrature != LNM_QUAD_ALPHA && prm->quadrature != LNM_QUAD_RIEMANN)
+    return fail(LNM_ERR_ARG, "params.quadrature");
+  if (!finite3(prm->light_w)) return fail(LNM_ERR_ARG, "params.light_w must be finite");
+  if (prm->reserved != 0) return fail(LNM_ERR_ARG, "params.reserved must be 0");
+  const int nmax = std::max(vol->nx, std::max(vol->ny, vol->nz));
+  m->rho = vol->density;
+  m->nx = vol->nx;
+  m->ny = vol->ny;
+  m->nz = vol->nz;
+  m->sigma_scale = vol->sigma_scale;
+  m->h = (float)((double)prm->step_voxels / nmax);
+  m->depth_tau = prm->depth_tau;
+  m->tau_max = prm->ert_eps > 0.0f ? (float)-std::log((double)prm->ert_eps) : INFINITY;
+  m->jitter_on = prm->jitter_on != 0;
+  m->seed = prm->jitter_seed;
+  m->frame = prm->frame;
+  m->quadrature = prm->quadrature;
+  m->wf = prm->light_w[0];
+  m->wt = prm->light_w[1];
+  m->wb = prm->light_w[2];
+  return LNM_OK;
+}
+
+// ---------------------------------------------------------------- network
+int elem_bytes(int precision) { return precision == LNM_FP32 ? 4 : precision == LNM_BF16 ? 2 : 1; }
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Layer table and packed-weight layout of a network at one precision.
+// fp32: chunks of 16 input channels (4 for the 3-channel input);
+// bf16: chunks of 32 (the 3-channel input packs its 27 taps x channels into
+// one 32-wide K step).
+bool net_shape(int levels, int base, int precision, std::vector<LayerDesc>* out, size_t* dev_bytes,
+                      std::string* why) {
+  if (levels < 2 || levels > 6) return *why = "levels must be in [2, 6]", false;
+  if (base < 16 || base > 256 || base % 16) return *why = "base must be a multiple of 16 in [16, 256]", false;
+  if ((base << (levels - 1)) > 4096) return *why = "deepest width exceeds 4096", false;
+  if (precision != LNM_FP32 && precision != LNM_BF16 && precision != LNM_FP8_E4M3)
+    return *why = "unknown precision", false;
+  std::vector<LayerDesc> L;
+  auto add = [&](int ci, int co, int k) {
+    LayerDesc d{};
+    d.ci = ci;
+    d.co = co;
+    d.k = k;
+    if (precision == LNM_FP32) {
+      d.ck = ci == 3 ? 4 : 16;
+      d.ci_pad = (ci + d.ck - 1) / d.ck * d.ck;
+    } else {
+      d.ck = 32;
+      d.ci_pad = ci == 3 ? 32 : (ci + 31) / 32 * 32;
+    }
+    d.co_pad = (co + kBN - 1) / kBN * kBN;
+    L.push_back(d);
+  };
+  int cin = 3;
+  for (int l = 0; l < levels - 1; ++l) {
+    add(cin, base << l, 3);
+    add(base << l, base << l, 3);
+    cin = base << l;
+  }
+  add(cin, base << (levels - 1), 3);
+  add(base << (levels - 1), base << (levels - 1), 3);
+  for (int l = levels - 2; l >= 0; --l) {
+    add((base << l) + (base << (l + 1)), base << l, 3);
+    add(base << l, base << l, 3);
+  }
+  add(base, 6, 1);
+  const size_t es = elem_bytes(precision);
+  size_t off = 0;
+  for (auto& d : L) {
+    off = align256(off);
+    d.w_off = off;
+    if (d.k == 1)
+      off += sizeof(float) * 6 * d.ci;  // the head stays fp32
+    else if (precision != LNM_FP32 && d.ci == 3)
+      off += sizeof(uint16_t) * d.co_pad * 32;  // the 3-channel input layer is bf16 in both reduced forms
+    else
+      off += es * d.co_pad * d.ci_pad * 9;
+    off = align256(off);
+    d.b_off = off;
+    off += sizeof(float) * (d.k == 3 ? d.co_pad : 6);
+    if (precision == LNM_FP8_E4M3 && d.k == 3 && d.ci != 3) {
+      off = align256(off);
+      d.s_off = off;
+      off += sizeof(float) * d.co_pad;
+    }
+  }
+  *out = std::move(L);
+  *dev_bytes = align256(off);
+  return true;
+}
+
+size_t param_count(int levels, int base) {
+  std::vector<LayerDesc> L;
+  size_t f;
+  std::string why;
+  if (!net_shape(levels, base, LNM_FP32, &L, &f, &why)) return 0;
+  size_t n = 0;
+  for (auto& d : L) n += (size_t)d.co * d.ci * d.k * d.k + d.co;
+  return n;
+}
+
+// fp32 -> bf16 bits, round to nearest even (finite inputs).
+static uint16_t host_f2bf(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// fp32 -> OCP e4m3 (bias 7, 3 mantissa bits, max 448), round to nearest
+// even, saturating; subnormals are multiples of 2^-9.
+static uint8_t host_f2e4m3(float f) {
+  const uint8_t sign = std::signbit(f) ? 0x80 : 0x00;
+  float a = std::fabs(f);
+  if (!(a == a)) return 0x7f;
+  if (a >= 448.0f) return sign | 0x7e;
+  int e;
+  std::frexp(a, &e);  // a = m 2^e, m in [0.5, 1)
+  e -= 1;             // a = (1 + f) 2^e
+  if (e < -6) {       // subnormal (or zero): q * 2^-9, q in [0, 8]
+    const float q = std::nearbyint(std::ldexp(a, 9));
+    return sign | (uint8_t)q;  // q = 8 is the smallest normal, encoded alike
+  }
+  float mq = std::nearbyint((std::ldexp(a, -e) - 1.0f) * 8.0f);
+  if (mq == 8.0f) {
+    mq = 0.0f;
+    e += 1;
+  }
+  const int ef = e + 7;
+  if (ef > 15 || (ef == 15 && mq == 7.0f)) return sign | 0x7e;
+  return sign | (uint8_t)((ef << 3) | (int)mq);
+}
+
+// Packed 3x3 layout: [n_tile][chunk][tap][n (32)][c (ck)], zero padded; the
+// bf16 3-channel input layer: [n_tile][n (32)][k = 3 tap + c (32)].
+static void pack_layer(const LayerDesc& d, int precision, const float* w, const float* b, char* dst) {
+  float* bias = reinterpret_cast<float*>(dst + d.b_off);
+  if (d.k == 1) {
+    std::memcpy(dst + d.w_off, w, sizeof(float) * 6 * d.ci);
+    std::memcpy(bias, b, sizeof(float) * 6);
+    return;
+  }
+  for (int n = 0; n < d.co_pad; ++n) bias[n] = n < d.co ? b[n] : 0.0f;
+  const int nt = d.co_pad / kBN, nch = d.ci_pad / d.ck;
+  auto W = [&](int oc, int ic, int tap) -> float {
+    return (oc < d.co && ic < d.ci) ? w[((size_t)oc * d.ci + ic) * 9 + tap] : 0.0f;
+  };
+  if (precision == LNM_FP32) {
+    float* o = reinterpret_cast<float*>(dst + d.w_off);
+    for (int t = 0; t < nt; ++t)
+      for (int ch = 0; ch < nch; ++ch)
+        for (int tap = 0; tap < 9; ++tap)
+          for (int n = 0; n < kBN; ++n)
+            for (int cc = 0; cc < d.ck; ++cc) *o++ = W(t * kBN + n, ch * d.ck + cc, tap);
+    return;
+  }
+  if (precision == LNM_FP8_E4M3 && d.ci != 3) {
+    // per-output-channel scale s = max|W[o]| / 448
+    float* sc = reinterpret_cast<float*>(dst + d.s_off);
+    for (int n = 0; n < d.co_pad; ++n) {
+      float m = 0.0f;
+      if (n < d.co)
+        for (int ic = 0; ic < d.ci; ++ic)
+          for (int tap = 0; tap < 9; ++tap) m = std::max(m, std::fabs(W(n, ic, tap)));
+      sc[n] = m > 0.0f ? m / 448.0f : 1.0f;
+    }
+    uint8_t* q = reinterpret_cast<uint8_t*>(dst + d.w_off);
+    for (int t = 0; t < nt; ++t)
+      for (int ch = 0; ch < nch; ++ch)
+        for (int tap = 0; tap < 9; ++tap)
+          for (int n = 0; n < kBN; ++n)
+            for (int cc = 0; cc < d.ck; ++cc) {
+              const int oc = t * kBN + n;
+              *q++ = host_f2e4m3(W(oc, ch * d.ck + cc, tap) / sc[oc]);
+            }
+    return;
+  }
+  uint16_t* o = reinterpret_cast<uint16_t*>(dst + d.w_off);
+  if (d.ci == 3) {
+    for (int t = 0; t < nt; ++t)
+      for (int n = 0; n < kBN; ++n)
+        for (int k = 0; k < 32; ++k) *o++ = host_f2bf(k < 27 ? W(t * kBN + n, k % 3, k / 3) : 0.0f);
+    return;
+  }
+  for (int t = 0; t < nt; ++t)
+    for (int ch = 0; ch < nch; ++ch)
+      for (int tap = 0; tap < 9; ++tap)
+        for (int n = 0; n < kBN; ++n)
+          for (int cc = 0; cc < d.ck; ++cc) *o++ = host_f2bf(W(t * kBN + n, ch * d.ck + cc, tap));
+}
+
+Plan plan_workspace(const lnm_net_s* net, int B, int H, int W) {
+  Plan p;
+  size_t off = 0;
+  const int L = net->levels;
+  int li = 0;
+  const size_t es = elem_bytes(net->precision);
+  auto add = [&](int lvl) {
+    const LayerDesc& d = net->layers[li++];
+    off = align256(off);
+    p.out_off.push_back(off);
+    off += es * (size_t)B * (H >> lvl) * (W >> lvl) * d.co;
+  };
+  for (int l = 0; l < L; ++l) {
+    add(l);
+    add(l);
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    add(l);
+    add(l);
+  }
+  p.scratch_off = align256(off);
+  p.bytes = p.scratch_off + kScratchBytes;
+  return p;
+}
+
+lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, const float* guide, float* lm,
+                           float* logits, char* ws, hipStream_t s) {
+  const Plan p = plan_workspace(net, B, H, W);
+  const int L = net->levels;
+  auto buf = [&](int i) { return static_cast<void*>(ws + p.out_off[i]); };
+  std::vector<int> skip(L);
+  int li = 0;
+  const bool fp8 = net->precision == LNM_FP8_E4M3;
+  // src: conv layer that produced the input (-1: the guide), for fp8 scales
+  auto conv = [&](int lvl, int mode, int src, const void* s0, int c0, const void* s1, int c1) -> hipError_t {
+    const LayerDesc& d = net->layers[li];
+    ConvArgs a{};
+    a.src0 = s0;
+    a.src1 = s1;
+    a.c0 = c0;
+    a.c1 = c1;
+    a.B = B;
+    a.H = H >> lvl;
+    a.W = W >> lvl;
+    a.ci_pad = d.ci_pad;
+    a.co = d.co;
+    a.w = net->dev + d.w_off;
+    a.bias = reinterpret_cast<const float*>(net->dev + d.b_off);
+    a.out = buf(li);
+    a.relu = 1;
+    if (fp8) {
+      a.in_scale = src >= 0 ? net->act_scale[src] : 1.0f;
+      a.w_scale = d.s_off ? reinterpret_cast<const float*>(net->dev + d.s_off) : nullptr;
+      a.out_inv_scale = 1.0f / net->act_scale[li];
+    }
+    ++li;
+    ProfScope ps(ctx, LNM_K_CONV, s);
+    if (fp8) return launch_conv3x3_fp8(mode, a, s);
+    if (net->precision == LNM_BF16) return launch_conv3x3_bf16(mode, a, s);
+    return launch_conv3x3_f32(mode, d.ck, a, s);
+  };
+  hipError_t e;
+  const void* x = guide;
+  int cx = 3;
+  for (int l = 0; l < L; ++l) {
+    const int mode = l == 0 ? G_GUIDE : G_POOL;
+    if ((e = conv(l, mode, l == 0 ? -1 : skip[l - 1], x, cx, nullptr, 0)) != hipSuccess)
+      return fail(LNM_ERR_DEVICE, hipGetErrorString(e));
+    x = buf(li - 1);
+    cx = net->layers[li - 1].co;
+    if ((e = conv(l, G_PLAIN, li - 1, x, cx, nullptr, 0)) != hipSuccess)
+      return fail(LNM_ERR_DEVICE, hipGetErrorString(e));
+    x = buf(li - 1);
+    cx = net->layers[li - 1].co;
+    skip[l] = li - 1;
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const int cs = net->layers[skip[l]].co;
+    if ((e = conv(l, G_CONCAT_UP, skip[l], buf(skip[l]), cs, x, cx)) != hipSuccess)
+      return fail(LNM_ERR_DEVICE, hipGetErrorString(e));
+    x = buf(li - 1);
+    cx = net->layers[li - 1].co;
+    if ((e = conv(l, G_PLAIN, li - 1, x, cx, nullptr, 0)) != hipSuccess)
+      return fail(LNM_ERR_DEVICE, hipGetErrorString(e));
+    x = buf(li - 1);
+    cx = net->layers[li - 1].co;
+  }
+  if (!lm) return LNM_OK;  // convolutions only (calibration)
+  const LayerDesc& hd = net->layers[li];
+  HeadArgs h{};
+  h.in = x;
+  h.in_type = fp8 ? 2 : net->precision == LNM_BF16 ? 1 : 0;
+  h.in_scale = fp8 ? net->act_scale[li - 1] : 1.0f;
+  h.P = B * H * W;
+  h.C = cx;
+  h.w = reinterpret_cast<const float*>(net->dev + hd.w_off);
+  h.b = reinterpret_cast<const float*>(net->dev + hd.b_off);
+  h.lm = lm;
+  h.logits = logits;
+  {
+    ProfScope ps(ctx, LNM_K_HEAD, s);
+    e = launch_head(h, s);
+  }
+  if (e != hipSuccess) return fail(LNM_ERR_DEVICE, hipGetErrorString(e));
+  return LNM_OK;
+}
+
+lnm_status check_infer(const lnm_net_s* net, int B, int H, int W, size_t ws_bytes, const void* ws) {
+  if (!net) return fail(LNM_ERR_ARG, "net is NULL");
+  if (B < 1 || H < 1 || W < 1) return fail(LNM_ERR_SHAPE, "batch, H and W must be >= 1");
+  const int div = 1 << (net->levels - 1);
+  if (H % div || W % div) return fail(LNM_ERR_SHAPE, "H and W must be divisible by 2^(levels-1)");
+  if ((double)B * H * W > 2.0e9 / 8) return fail(LNM_ERR_SHAPE, "batch x H x W too large");
+  const size_t need = plan_workspace(net, B, H, W).bytes;
+  if (ws_bytes < need || (need && !ws))
+    return fail(LNM_ERR_SHAPE, "workspace too small: need " + std::to_string(need) + " bytes");
+  return LNM_OK;
+}
+
+static lnm_status light_setup(const CamDev& c, const lnm_light* lights, int n, CompositeArgs* a) {
+  if (n < 0 || n > 16) return fail(LNM_ERR_ARG, "n_lights must be in [0, 16]");
+  if (n && !lights) return fail(LNM_ERR_ARG, "lights is NULL");
+  a->n_lights = n;
+  for (int k = 0; k < n; ++k) {
+    if (!finite3(lights[k].dir) || !finite3(lights[k].rgb)) return fail(LNM_ERR_ARG, "light values must be finite");
+    double d[3] = {lights[k].dir[0], lights[k].dir[1], lights[k].dir[2]};
+    a->l[k][0] = (float)(d[0] * c.r[0] + d[1] * c.r[1] + d[2] * c.r[2]);
+    a->l[k][1] = (float)(d[0] * c.u[0] + d[1] * c.u[1] + d[2] * c.u[2]);
+    a->l[k][2] = (float)-(d[0] * c.f[0] + d[1] * c.f[1] + d[2] * c.f[2]);
+    for (int q = 0; q < 3; ++q) a->rgb[k][q] = lights[k].rgb[q];
+  }
+  return LNM_OK;
+}
+
+}  // namespace lnm
+
+using namespace lnm;
+
+extern "C" {
+
+size_t lnm_abi_struct_size(int32_t which) {
+  switch (which) {
+    case 0: return sizeof(lnm_volume);
+    case 1: return sizeof(lnm_camera);
+    case 2: return sizeof(lnm_march_params);
+    case 3: return sizeof(lnm_light);
+    default: return 0;
+  }
+}
+
+const char* lnm_version(void) { return "liblnm 0.1 gfx950"; }
+
+const char* lnm_last_error(void) { return g_err.c_str(); }
+
+lnm_status lnm_ctx_create(int32_t hip_device, lnm_ctx* out) {
+  if (!out) return fail(LNM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  LNM_HIP_CHECK(hipGetDeviceCount(&n));
+  if (hip_device < 0 || hip_device >= n) return fail(LNM_ERR_ARG, "no such HIP device");
+  LNM_HIP_CHECK(hipSetDevice(hip_device));
+  hipDeviceProp_t prop;
+  LNM_HIP_CHECK(hipGetDeviceProperties(&prop, hip_device));
+  auto* c = new (std::nothrow) lnm_ctx_s;
+  if (!c) return fail(LNM_ERR_OOM, "host allocation failed");
+  c->device = hip_device;
+  c->cu_count = prop.multiProcessorCount;
+  c->arch = prop.gcnArchName;
+  *out = c;
+  return LNM_OK;
+}
+
+void lnm_ctx_destroy(lnm_ctx ctx) {
+  if (!ctx) return;
+  for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+lnm_status lnm_profile_enable(lnm_ctx ctx, int32_t on) {
+  if (!ctx) return fail(LNM_ERR_ARG, "ctx is NULL");
+  if (on) {
+    ctx->recs.clear();
+    ctx->pool_used = 0;
+  }
+  ctx->prof = on != 0;
+  return LNM_OK;
+}
+
+lnm_status lnm_profile_read(lnm_ctx ctx, int32_t kind, int32_t* launches, double* total_ms) {
+  if (!ctx || !launches || !total_ms) return fail(LNM_ERR_ARG, "NULL argument");
+  if (kind < 0 || kind >= LNM_K_COUNT) return fail(LNM_ERR_ARG, "unknown kernel kind");
+  int n = 0;
+  double ms = 0.0;
+  for (const auto& r : ctx->recs) {
+    if (r.kind != kind) continue;
+    LNM_HIP_CHECK(hipEventSynchronize(r.b));
+    float t = 0.0f;
+    LNM_HIP_CHECK(hipEventElapsedTime(&t, r.a, r.b));
+    ms += t;
+    ++n;
+  }
+  *launches = n;
+  *total_ms = ms;
+  return LNM_OK;
+}
+
+size_t lnm_march_workspace_bytes(const lnm_volume*) { return 0; }
+
+lnm_status lnm_march(lnm_ctx ctx, const lnm_volume* vol, const lnm_camera* cam, const lnm_march_params* prm,
+                     float* guide, void* workspace, size_t ws_bytes, void* stream) {
+  (void)workspace;
+  (void)ws_bytes;
+  if (!ctx) return fail(LNM_ERR_ARG, "ctx is NULL");
+  if (!guide) return fail(LNM_ERR_ARG, "guide is NULL");
+  MarchDev m;
+  CamDev c;
+  lnm_status st = march_setup(vol, cam, prm, &m, &c);
+  if (st) return st;
+  ProfScope ps(ctx, LNM_K_MARCH, (hipStream_t)stream);
+  LNM_HIP_CHECK(launch_march(m, c, guide, (hipStream_t)stream));
+  return LNM_OK;
+}
+
+lnm_status lnm_reference_lightmaps(lnm_ctx ctx, const lnm_volume* vol, const lnm_camera* cam, float step_voxels,
+                                   float ert_eps, int32_t srgb, float* lm, void* stream) {
+  if (!ctx) return fail(LNM_ERR_ARG, "ctx is NULL");
+  if (!lm) return fail(LNM_ERR_ARG, "lm is NULL");
+  lnm_march_params prm{};
+  prm.step_voxels = step_voxels;
+  prm.depth_tau = 0.0f;
+  prm.ert_eps = ert_eps;
+  prm.light_w[0] = prm.light_w[1] = prm.light_w[2] = 1.0f;
+  MarchDev m;
+  CamDev c;
+  lnm_status st = march_setup(vol, cam, &prm, &m, &c);
+  if (st) return st;
+  ProfScope ps(ctx, LNM_K_REFERENCE, (hipStream_t)stream);
+  LNM_HIP_CHECK(launch_reference(m, c, srgb != 0, lm, (hipStream_t)stream));
+  return LNM_OK;
+}
+
+size_t lnm_net_param_count(int32_t levels, int32_t base) { return param_count(levels, base); }
+
+size_t lnm_net_device_bytes(int32_t levels, int32_t base, int32_t precision) {
+  std::vector<LayerDesc> L;
+  size_t bytes;
+  std::string why;
+  if (!net_shape(levels, base, precision, &L, &bytes, &why)) return 0;
+  return bytes;
+}
+
+lnm_status lnm_net_create(lnm_ctx ctx, int32_t levels, int32_t base, int32_t precision, const float* host_params,
+                          size_t n_params, const float* act_scales, void* device_buf, size_t device_buf_bytes,
+                          void* stream, lnm_net* out) {
+  if (!ctx || !out || !host_params || !device_buf) return fail(LNM_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  if (precision != LNM_FP32 && precision != LNM_BF16 && precision != LNM_FP8_E4M3)
+    return fail(LNM_ERR_UNSUPPORTED, "precision " + std::to_string(precision) + " is not built");
+  const bool fp8 = precision == LNM_FP8_E4M3;
+  if (!fp8 && act_scales) return fail(LNM_ERR_ARG, "act_scales must be NULL for fp32 and bf16");
+  if (fp8 && !act_scales) return fail(LNM_ERR_ARG, "the fp8 form needs calibrated activation maxima");
+  std::vector<LayerDesc> L;
+  size_t bytes;
+  std::string why;
+  if (!net_shape(levels, base, precision, &L, &bytes, &why)) return fail(LNM_ERR_SHAPE, why);
+  // fp8: per stored activation tensor s = amax / 448, the two inputs of each
+  // decoder concatenation sharing the larger one
+  std::vector<float> scale;
+  if (fp8) {
+    const int n_conv = (int)L.size() - 1;
+    for (int i = 0; i < n_conv; ++i) {
+      const float a = act_scales[i];
+      if (!(a >= 0.0f) || !std::isfinite(a)) return fail(LNM_ERR_ARG, "activation maxima must be finite and >= 0");
+      scale.push_back(a > 0.0f ? a / 448.0f : 1.0f);
+    }
+    int li = 2 * levels;  // first decoder conv
+    for (int l = levels - 2; l >= 0; --l) {
+      const int skip = 2 * l + 1, low = li - 1;
+      const float s = std::max(scale[skip], scale[low]);
+      scale[skip] = scale[low] = s;
+      li += 2;
+    }
+  }
+  if (n_params != param_count(levels, base))
+    return fail(LNM_ERR_SHAPE, "n_params is " + std::to_string(n_params) + ", expected " +
+                                   std::to_string(param_count(levels, base)));
+  if (device_buf_bytes < bytes) return fail(LNM_ERR_SHAPE, "device_buf too small");
+  if (reinterpret_cast<uintptr_t>(device_buf) % 256) return fail(LNM_ERR_ARG, "device_buf must be 256-byte aligned");
+  for (size_t i = 0; i < n_params; ++i)
+    if (!std::isfinite(host_params[i])) return fail(LNM_ERR_ARG, "parameters must be finite");
+  std::vector<char> packed;
+  try {
+    packed.assign(bytes, 0);
+  } catch (...) {
+    return fail(LNM_ERR_OOM, "host allocation failed");
+  }
+  size_t off = 0;
+  for (auto& d : L) {
+    const size_t nw = (size_t)d.co * d.ci * d.k * d.k;
+    pack_layer(d, precision, host_params + off, host_params + off + nw, packed.data());
+    off += nw + d.co;
+  }
+  auto* net = new (std::nothrow) lnm_net_s;
+  if (!net) return fail(LNM_ERR_OOM, "host allocation failed");
+  net->levels = levels;
+  net->base = base;
+  net->precision = precision;
+  net->layers = std::move(L);
+  net->dev = static_cast<char*>(device_buf);
+  net->dev_bytes = bytes;
+  net->act_scale = std::move(scale);
+  hipError_t e = hipMemcpyAsync(device_buf, packed.data(), bytes, hipMemcpyHostToDevice, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) {
+    delete net;
+    return fail(LNM_ERR_DEVICE, std::string("weight upload: ") + hipGetErrorString(e));
+  }
+  *out = net;
+  return LNM_OK;
+}
+
+void lnm_net_destroy(lnm_net net) { delete net; }
+
+lnm_status lnm_calibrate_amax(lnm_ctx ctx, lnm_net net, int32_t batch, int32_t H, int32_t W, const float* guide,
+                              float* host_amax, int32_t n, void* workspace, size_t ws_bytes, void* stream) {
+  if (!ctx || !net || !guide || !host_amax) return fail(LNM_ERR_ARG, "NULL argument");
+  if (net->precision != LNM_FP32) return fail(LNM_ERR_ARG, "calibration runs the fp32 network");
+  const int n_conv = (int)net->layers.size() - 1;
+  if (n != n_conv) return fail(LNM_ERR_SHAPE, "n must be the number of convolution layers");
+  lnm_status st = check_infer(net, batch, H, W, ws_bytes, workspace);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = static_cast<char*>(workspace);
+  const Plan p = plan_workspace(net, batch, H, W);
+  float* amax = reinterpret_cast<float*>(ws + p.scratch_off);
+  float* part = amax + 1024;  // kAmaxBlocks floats
+  st = run_unet(ctx, net, batch, H, W, guide, nullptr, nullptr, ws, s);  // convolutions only
+  if (st) return st;
+  const int L = net->levels;
+  for (int i = 0; i < n_conv; ++i) {
+    const int lvl = i < 2 * L ? i / 2 : L - 2 - (i - 2 * L) / 2;
+    const long count = (long)batch * (H >> lvl) * (W >> lvl) * net->layers[i].co;
+    LNM_HIP_CHECK(launch_amax(reinterpret_cast<const float*>(ws + p.out_off[i]), count, part, amax + i, s));
+  }
+  LNM_HIP_CHECK(hipMemcpyAsync(host_amax, amax, sizeof(float) * n_conv, hipMemcpyDeviceToHost, s));
+  LNM_HIP_CHECK(hipStreamSynchronize(s));
+  return LNM_OK;
+}
+
+size_t lnm_workspace_bytes(lnm_net net, int32_t batch, int32_t H, int32_t W) {
+  if (!net || batch < 1 || H < 1 || W < 1) return 0;
+  return plan_workspace(net, batch, H, W).bytes;
+}
+
+lnm_status lnm_infer(lnm_ctx ctx, lnm_net net, int32_t batch, int32_t H, int32_t W, const float* guide,
+                     float* lightmaps, float* logits, void* workspace, size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(LNM_ERR_ARG, "ctx is NULL");
+  if (!guide || !lightmaps) return fail(LNM_ERR_ARG, "guide or lightmaps is NULL");
+  lnm_status st = check_infer(net, batch, H, W, ws_bytes, workspace);
+  if (st) return st;
+  return run_unet(ctx, net, batch, H, W, guide, lightmaps, logits, static_cast<char*>(workspace),
+                  (hipStream_t)stream);
+}
+
+lnm_status lnm_composite(lnm_ctx ctx, const lnm_camera* cam, const lnm_light* lights, int32_t n_lights,
+                         int32_t batch, int32_t H, int32_t W, const float* lightmaps, const float* guide, float* rgba,
+                         void* stream) {
+  if (!ctx || !cam || !lightmaps || !guide || !rgba) return fail(LNM_ERR_ARG, "NULL argument");
+  if (batch < 1 || H < 1 || W < 1) return fail(LNM_ERR_SHAPE, "batch, H and W must be >= 1");
+  CamDev c;
+  std::string why;
+  if (!make_cam(*cam, &c, &why)) return fail(LNM_ERR_ARG, why);
+  CompositeArgs a{};
+  lnm_status st = light_setup(c, lights, n_lights, &a);
+  if (st) return st;
+  a.lm = lightmaps;
+  a.guide = guide;
+  a.rgba = rgba;
+  a.P = batch * H * W;
+  ProfScope ps(ctx, LNM_K_COMPOSITE, (hipStream_t)stream);
+  LNM_HIP_CHECK(launch_composite(a, (hipStream_t)stream));
+  return LNM_OK;
+}
+
+lnm_status lnm_frame(lnm_ctx ctx, lnm_net net, const lnm_volume* vol, const lnm_camera* cam,
+                     const lnm_march_params* prm, const lnm_light* lights, int32_t n_lights, float* guide,
+                     float* lightmaps, float* rgba, void* workspace, size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(LNM_ERR_ARG, "ctx is NULL");
+  if (!guide || !lightmaps) return fail(LNM_ERR_ARG, "guide or lightmaps is NULL");
+  MarchDev m;
+  CamDev c;
+  lnm_status st = march_setup(vol, cam, prm, &m, &c);
+  if (st) return st;
+  st = check_infer(net, 1, c.H, c.W, ws_bytes, workspace);
+  if (st) return st;
+  CompositeArgs a{};
+  if (rgba) {
+    st = light_setup(c, lights, n_lights, &a);
+    if (st) return st;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  {
+    ProfScope ps(ctx, LNM_K_MARCH, s);
+    LNM_HIP_CHECK(launch_march(m, c, guide, s));
+  }
+  st = run_unet(ctx, net, 1, c.H, c.W, guide, lightmaps, nullptr, static_cast<char*>(workspace), s);
+  if (st) return st;
+  if (rgba) {
+    a.lm = lightmaps;
+    a.guide = guide;
+    a.rgba = rgba;
+    a.P = c.H * c.W;
+    ProfScope ps(ctx, LNM_K_COMPOSITE, s);
+    LNM_HIP_CHECK(launch_composite(a, s));
+  }
+  return LNM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,377 @@
+// U-Net layers (Section 4.3) for gfx950, fp32.
+//
+// 3x3 convolution as an implicit GEMM on the fp32 matrix cores
+// (v_mfma_f32_16x16x4_f32): M = output pixels, N = output channels,
+// K = 9 taps x input channels.  Activations are NHWC.
+//
+// Workgroup = 4 wavefronts computing a TH x 16 pixel tile x 32 output
+// channels.  Per 16-channel input chunk the (TH+2) x 18 input halo and the
+// 9 x 32 x 16 weight slab are staged in LDS once and every tap reads them
+// from there.  The gather that fills the halo fuses the zero padding, the
+// 2x2 max-pool of the encoder (pooled input mode) and the decoder's nearest
+// 2x upsample + skip concatenation (two-source mode), so none of those
+// tensors is materialised.  The epilogue adds the bias and applies ReLU.
+//
+// K-slot permutation: MFMA step jj pairs lane group g (= lane / 16) with input
+// channel 4g + jj for both operands, so each lane fetches its four channels of
+// A and of B with one 16-byte LDS read.
+#include "internal.h"
+
+namespace lnm {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTW = 16;        // tile width in pixels (= MFMA M)
+constexpr int kHW = kTW + 2;   // halo width
+
+template <int CK>
+struct Pad {
+  static constexpr int in = CK == 16 ? 20 : 4;  // LDS floats per halo pixel
+  static constexpr int w = CK == 16 ? 20 : 4;   // LDS floats per weight row
+};
+
+template <int MODE>
+__device__ __forceinline__ f4 gather4(const ConvArgs& a, int b, int y, int x, int c) {
+  const float* s0 = static_cast<const float*>(a.src0);
+  if constexpr (MODE == G_GUIDE) {
+    const float* g = s0 + ((size_t)(b * a.H + y) * a.W + x) * 3;
+    return f4{g[0], g[1], g[2], 0.0f};
+  } else if constexpr (MODE == G_PLAIN) {
+    return *reinterpret_cast<const f4*>(s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c);
+  } else if constexpr (MODE == G_POOL) {
+    const int W2 = 2 * a.W;
+    const float* p = s0 + ((size_t)(b * 2 * a.H + 2 * y) * W2 + 2 * x) * a.c0 + c;
+    const f4 v0 = *reinterpret_cast<const f4*>(p);
+    const f4 v1 = *reinterpret_cast<const f4*>(p + a.c0);
+    const f4 v2 = *reinterpret_cast<const f4*>(p + (size_t)W2 * a.c0);
+    const f4 v3 = *reinterpret_cast<const f4*>(p + (size_t)W2 * a.c0 + a.c0);
+    return f4{fmaxf(fmaxf(v0.x, v1.x), fmaxf(v2.x, v3.x)), fmaxf(fmaxf(v0.y, v1.y), fmaxf(v2.y, v3.y)),
+              fmaxf(fmaxf(v0.z, v1.z), fmaxf(v2.z, v3.z)), fmaxf(fmaxf(v0.w, v1.w), fmaxf(v2.w, v3.w))};
+  } else {  // G_CONCAT_UP: channels [0, c0) from the skip, then the upsampled low-res tensor
+    if (c < a.c0) return *reinterpret_cast<const f4*>(s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c);
+    const int Hl = a.H >> 1, Wl = a.W >> 1;
+    return *reinterpret_cast<const f4*>(static_cast<const float*>(a.src1) + ((size_t)(b * Hl + (y >> 1)) * Wl + (x >> 1)) * a.c1 + (c - a.c0));
+  }
+}
+
+template <int CK, int MODE, int TH>
+__global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a) {
+  constexpr int NF = kBN / 16;
+  constexpr int MF = TH / 4;
+  constexpr int PIN = Pad<CK>::in, PW = Pad<CK>::w;
+  __shared__ __attribute__((aligned(16))) float s_in[(TH + 2) * kHW * PIN];
+  __shared__ __attribute__((aligned(16))) float s_w[9 * kBN * PW];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_y = (a.H + TH - 1) / TH;
+  const int b = blockIdx.y / tiles_y;
+  const int y0 = (blockIdx.y - b * tiles_y) * TH, x0 = blockIdx.x * kTW;
+  const int nchunks = a.ci_pad / CK;
+  const float* wblk = static_cast<const float*>(a.w) + (size_t)blockIdx.z * nchunks * 9 * kBN * CK;
+  const int g = lane >> 4, li = lane & 15;
+  const int wrow = wave * MF;
+
+  f4 acc[MF][NF];
+#pragma unroll
+  for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+    for (int nf = 0; nf < NF; ++nf) acc[mf][nf] = f4{0.f, 0.f, 0.f, 0.f};
+
+  for (int ch = 0; ch < nchunks; ++ch) {
+    // stage the input halo of this channel chunk
+    constexpr int NQ = (TH + 2) * kHW * (CK / 4);
+    for (int q = tid; q < NQ; q += 256) {
+      const int c4 = q % (CK / 4), p = q / (CK / 4);
+      const int hx = p % kHW, hy = p / kHW;
+      const int y = y0 + hy - 1, x = x0 + hx - 1;
+      f4 v = f4{0.f, 0.f, 0.f, 0.f};
+      if (y >= 0 && y < a.H && x >= 0 && x < a.W) v = gather4<MODE>(a, b, y, x, ch * CK + 4 * c4);
+      *reinterpret_cast<f4*>(&s_in[p * PIN + 4 * c4]) = v;
+    }
+    // stage the weight slab [tap][n][c] of this chunk
+    const float* wsrc = wblk + (size_t)ch * 9 * kBN * CK;
+    constexpr int NW = 9 * kBN * CK / 4;
+    for (int q = tid; q < NW; q += 256) {
+      const int c4 = q % (CK / 4), row = q / (CK / 4);
+      *reinterpret_cast<f4*>(&s_w[row * PW + 4 * c4]) = *reinterpret_cast<const f4*>(wsrc + 4 * q);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap - 3 * (tap / 3);
+      if constexpr (CK == 16) {
+        f4 av[MF], bv[NF];
+#pragma unroll
+        for (int mf = 0; mf < MF; ++mf)
+          av[mf] = *reinterpret_cast<const f4*>(&s_in[((wrow + mf + dy) * kHW + li + dx) * PIN + 4 * g]);
+#pragma unroll
+        for (int nf = 0; nf < NF; ++nf)
+          bv[nf] = *reinterpret_cast<const f4*>(&s_w[(tap * kBN + nf * 16 + li) * PW + 4 * g]);
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+          for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+            for (int nf = 0; nf < NF; ++nf)
+              acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mf][jj], bv[nf][jj], acc[mf][nf], 0, 0, 0);
+      } else {
+        float av[MF], bv[NF];
+#pragma unroll
+        for (int mf = 0; mf < MF; ++mf) av[mf] = s_in[((wrow + mf + dy) * kHW + li + dx) * PIN + g];
+#pragma unroll
+        for (int nf = 0; nf < NF; ++nf) bv[nf] = s_w[(tap * kBN + nf * 16 + li) * PW + g];
+#pragma unroll
+        for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+          for (int nf = 0; nf < NF; ++nf)
+            acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mf], bv[nf], acc[mf][nf], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+  // epilogue: lane holds rows (pixels) 4g..4g+3 of each 16x16 block, column li
+#pragma unroll
+  for (int mf = 0; mf < MF; ++mf) {
+    const int y = y0 + wrow + mf;
+    if (y >= a.H) continue;
+#pragma unroll
+    for (int nf = 0; nf < NF; ++nf) {
+      const int n = blockIdx.z * kBN + nf * 16 + li;
+      if (n >= a.co) continue;
+      const float bias = a.bias[n];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x = x0 + 4 * g + r;
+        if (x >= a.W) continue;
+        float v = acc[mf][nf][r] + bias;
+        if (a.relu) v = fmaxf(v, 0.0f);
+        static_cast<float*>(a.out)[((size_t)(b * a.H + y) * a.W + x) * a.co + n] = v;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// 1x1 head C -> 6 and sigmoid, one lane per pixel; fp32 arithmetic on
+// fp32 (IN = 0) or bf16 (IN = 1) activations.
+template <int IN>
+__global__ __launch_bounds__(256) void head_kernel(HeadArgs a) {
+  __shared__ float sw[6 * 256];
+  __shared__ float sb[6];
+  for (int q = threadIdx.x; q < 6 * a.C; q += 256) sw[q] = a.w[q];
+  if (threadIdx.x < 6) sb[threadIdx.x] = a.b[threadIdx.x];
+  __syncthreads();
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= a.P) return;
+  float z[6];
+#pragma unroll
+  for (int o = 0; o < 6; ++o) z[o] = sb[o];
+  for (int c = 0; c < a.C; c += 4) {
+    f4 v;
+    if constexpr (IN == 0) {
+      v = *reinterpret_cast<const f4*>(static_cast<const float*>(a.in) + (size_t)p * a.C + c);
+    } else if constexpr (IN == 2) {
+      const int q = *reinterpret_cast<const int*>(static_cast<const uint8_t*>(a.in) + (size_t)p * a.C + c);
+      v = f4{__builtin_amdgcn_cvt_f32_fp8(q, 0), __builtin_amdgcn_cvt_f32_fp8(q, 1),
+             __builtin_amdgcn_cvt_f32_fp8(q, 2), __builtin_amdgcn_cvt_f32_fp8(q, 3)} *
+          a.in_scale;
+    } else {
+      const uint2 q = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(a.in) + (size_t)p * a.C + c);
+      v = f4{bf16_to_f32(q.x & 0xffff), bf16_to_f32(q.x >> 16), bf16_to_f32(q.y & 0xffff), bf16_to_f32(q.y >> 16)};
+    }
+#pragma unroll
+    for (int o = 0; o < 6; ++o) {
+      const float* w = sw + o * a.C + c;
+      z[o] += w[0] * v.x + w[1] * v.y + w[2] * v.z + w[3] * v.w;
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    if (a.logits) a.logits[(size_t)p * 6 + o] = z[o];
+    a.lm[(size_t)p * 6 + o] = 1.0f / (1.0f + expf(-z[o]));
+  }
+}
+
+__device__ __forceinline__ float srgb_decode(float s) {
+  return s <= 0.04045f ? s / 12.92f : powf((s + 0.055f) / 1.055f, 2.4f);
+}
+
+// Six-way shading: rgb = sum_l c_l sum_p |l_p| lin(L_p^{sign l_p}), alpha = 1 - T.
+__global__ __launch_bounds__(256) void composite_kernel(CompositeArgs a) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= a.P) return;
+  const float* L = a.lm + (size_t)p * 6;
+  float lin[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) lin[q] = srgb_decode(L[q]);
+  float r = 0.f, gg = 0.f, bb = 0.f;
+  for (int k = 0; k < a.n_lights; ++k) {
+    float s = 0.f;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const float c = a.l[k][ax];
+      s += fabsf(c) * (c >= 0.0f ? lin[2 * ax] : lin[2 * ax + 1]);
+    }
+    r += a.rgb[k][0] * s;
+    gg += a.rgb[k][1] * s;
+    bb += a.rgb[k][2] * s;
+  }
+  float* o = a.rgba + (size_t)p * 4;
+  o[0] = r;
+  o[1] = gg;
+  o[2] = bb;
+  o[3] = 1.0f - a.guide[(size_t)p * 3 + 1];
+}
+
+// Weight gradient of a 3x3 layer: dW[o][c][tap] = sum_p E[p][o] X[p + tap][c]
+// as an MFMA GEMM with M = output channels, N = input channels, K = pixels.
+// Workgroup: 32 output channels x 16 input channels x 9 taps over a group of
+// 8 x 16 pixel tiles; each wavefront takes two tile rows (32 pixels, 8 K-steps
+// of 4) and keeps its own partial sums, written to partial[group * 4 + wave]
+// and summed in a fixed order by wgrad_reduce.  X is gathered exactly as the
+// forward pass reads it (pooled / upsampled-concatenated inputs stay virtual).
+constexpr int kWTH = 8;
+
+template <int MODE>
+__global__ __launch_bounds__(256) void wgrad3x3_f32(WgradArgs a) {
+  __shared__ float s_e[kWTH * kTW][33];
+  __shared__ float s_x[(kWTH + 2) * kHW][17];
+  const ConvArgs& x = a.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, li = lane & 15;
+  const int tiles_x = (x.W + kTW - 1) / kTW, tiles_y = (x.H + kWTH - 1) / kWTH;
+  const int n_tiles = x.B * tiles_x * tiles_y;
+  const int o0 = blockIdx.y * kBN, c0 = blockIdx.z * 16;
+  const int co_pad = gridDim.y * kBN;
+  f4 acc[2][9];
+#pragma unroll
+  for (int of = 0; of < 2; ++of)
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[of][t] = f4{0.f, 0.f, 0.f, 0.f};
+
+  const int t_end = min(n_tiles, (int)(blockIdx.x + 1) * a.tiles_per_group);
+  for (int t = blockIdx.x * a.tiles_per_group; t < t_end; ++t) {
+    const int b = t / (tiles_x * tiles_y), r = t - b * tiles_x * tiles_y;
+    const int y0 = (r / tiles_x) * kWTH, x0 = (r - (r / tiles_x) * tiles_x) * kTW;
+    for (int q = tid; q < kWTH * kTW * 8; q += 256) {
+      const int p = q >> 3, o = o0 + 4 * (q & 7);
+      const int y = y0 + p / kTW, xx = x0 + p % kTW;
+      f4 v = f4{0.f, 0.f, 0.f, 0.f};
+      if (y < x.H && xx < x.W && o < a.co) v = *reinterpret_cast<const f4*>(a.e + ((size_t)(b * x.H + y) * x.W + xx) * a.co + o);
+      s_e[p][4 * (q & 7) + 0] = v.x;
+      s_e[p][4 * (q & 7) + 1] = v.y;
+      s_e[p][4 * (q & 7) + 2] = v.z;
+      s_e[p][4 * (q & 7) + 3] = v.w;
+    }
+    for (int q = tid; q < (kWTH + 2) * kHW * 4; q += 256) {
+      const int p = q >> 2, c = c0 + 4 * (q & 3);
+      const int y = y0 + p / kHW - 1, xx = x0 + p % kHW - 1;
+      f4 v = f4{0.f, 0.f, 0.f, 0.f};
+      if (y >= 0 && y < x.H && xx >= 0 && xx < x.W && c < a.ci) v = gather4<MODE>(x, b, y, xx, c);
+      s_x[p][4 * (q & 3) + 0] = v.x;
+      s_x[p][4 * (q & 3) + 1] = v.y;
+      s_x[p][4 * (q & 3) + 2] = v.z;
+      s_x[p][4 * (q & 3) + 3] = v.w;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int ks = 0; ks < 8; ++ks) {
+      const int row = 2 * wave + (ks >> 2), col = 4 * (ks & 3) + g;
+      const float a0 = s_e[row * kTW + col][li], a1 = s_e[row * kTW + col][16 + li];
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const float bv = s_x[(row + tap / 3) * kHW + col + tap % 3][li];
+        acc[0][tap] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv, acc[0][tap], 0, 0, 0);
+        acc[1][tap] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv, acc[1][tap], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  const size_t part = (size_t)blockIdx.x * 4 + wave;
+#pragma unroll
+  for (int of = 0; of < 2; ++of)
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int o = o0 + of * 16 + 4 * g + rr, c = c0 + li;
+        a.partial[((part * co_pad + o) * a.ci_pad16 + c) * 9 + tap] = acc[of][tap][rr];
+      }
+}
+
+__global__ __launch_bounds__(256) void wgrad_reduce(const float* __restrict__ partial, int n_partials, int co, int ci,
+                                                     int co_pad, int ci_pad16, float* __restrict__ grad_w) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (long)co * ci * 9) return;
+  const int tap = i % 9, c = (i / 9) % ci, o = i / (9 * ci);
+  const size_t stride = (size_t)co_pad * ci_pad16 * 9, base = ((size_t)o * ci_pad16 + c) * 9 + tap;
+  float s = 0.0f;
+  for (int p = 0; p < n_partials; ++p) s += partial[p * stride + base];
+  grad_w[i] = s;
+}
+
+template <int CK, int MODE>
+hipError_t launch_tile(const ConvArgs& a, hipStream_t s) {
+  constexpr int TH = 8;
+  dim3 grid((a.W + kTW - 1) / kTW, ((a.H + TH - 1) / TH) * a.B, (a.co + kBN - 1) / kBN);
+  hipLaunchKernelGGL((conv3x3_f32<CK, MODE, TH>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_conv3x3_f32(int mode, int ck, const ConvArgs& a, hipStream_t s) {
+  if (mode == G_GUIDE && ck == 4) return launch_tile<4, G_GUIDE>(a, s);
+  if (ck != 16) return hipErrorInvalidValue;
+  switch (mode) {
+    case G_PLAIN: return launch_tile<16, G_PLAIN>(a, s);
+    case G_POOL: return launch_tile<16, G_POOL>(a, s);
+    case G_CONCAT_UP: return launch_tile<16, G_CONCAT_UP>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_wgrad3x3(int mode, const WgradArgs& a, int* n_partials, hipStream_t s) {
+  const int tiles = a.x.B * ((a.x.W + kTW - 1) / kTW) * ((a.x.H + kWTH - 1) / kWTH);
+  const int groups = (tiles + a.tiles_per_group - 1) / a.tiles_per_group;
+  dim3 grid(groups, (a.co + kBN - 1) / kBN, a.ci_pad16 / 16);
+  *n_partials = groups * 4;
+  switch (mode) {
+    case G_GUIDE: hipLaunchKernelGGL(wgrad3x3_f32<G_GUIDE>, grid, dim3(256), 0, s, a); break;
+    case G_PLAIN: hipLaunchKernelGGL(wgrad3x3_f32<G_PLAIN>, grid, dim3(256), 0, s, a); break;
+    case G_POOL: hipLaunchKernelGGL(wgrad3x3_f32<G_POOL>, grid, dim3(256), 0, s, a); break;
+    case G_CONCAT_UP: hipLaunchKernelGGL(wgrad3x3_f32<G_CONCAT_UP>, grid, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad_reduce(const float* partial, int n_partials, int co, int ci, int co_pad, int ci_pad16,
+                               float* grad_w, hipStream_t s) {
+  const long n = (long)co * ci * 9;
+  hipLaunchKernelGGL(wgrad_reduce, dim3((n + 255) / 256), dim3(256), 0, s, partial, n_partials, co, ci, co_pad,
+                     ci_pad16, grad_w);
+  return hipGetLastError();
+}
+
+hipError_t launch_head(const HeadArgs& a, hipStream_t s) {
+  if (a.C > 256 || (a.C & 3)) return hipErrorInvalidValue;
+  if (a.in_type == 0)
+    hipLaunchKernelGGL(head_kernel<0>, dim3((a.P + 255) / 256), dim3(256), 0, s, a);
+  else if (a.in_type == 1)
+    hipLaunchKernelGGL(head_kernel<1>, dim3((a.P + 255) / 256), dim3(256), 0, s, a);
+  else if (a.in_type == 2)
+    hipLaunchKernelGGL(head_kernel<2>, dim3((a.P + 255) / 256), dim3(256), 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_composite(const CompositeArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(composite_kernel, dim3((a.P + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace lnm

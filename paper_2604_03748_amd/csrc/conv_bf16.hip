@@ -1,0 +1,229 @@
+// U-Net 3x3 convolutions (Section 4.3) in bf16 on the gfx950 matrix cores
+// (v_mfma_f32_16x16x32_bf16, fp32 accumulation).  Activations and weights
+// are bf16 (round to nearest even), bias and ReLU are applied to the fp32
+// accumulator, and the result is rounded to bf16 once.
+//
+// Same tiling as the fp32 kernel: a workgroup of 4 wavefronts computes a
+// TH x 16 pixel tile x 32 output channels; per 32-channel input chunk the
+// (TH+2) x 18 halo and the 9 x 32 x 32 weight slab are staged in LDS and read
+// by all nine taps; the halo gather fuses zero padding, 2x2 max-pooling and the
+// decoder's upsample + skip concatenation.
+//
+// K-slot permutation: lane group g (= lane / 16) supplies input channels
+// 8g .. 8g+7 of the chunk to both MFMA operands, one 16-byte LDS read each.
+// The 3-channel input layer packs all 27 (tap, channel) pairs of its 3x3
+// window into one 32-wide K step instead of padding each tap to 32 channels.
+#include "internal.h"
+
+namespace lnm {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTW = 16;
+constexpr int kHW = kTW + 2;
+constexpr int kCK = 32;   // input channels per chunk
+constexpr int kPad = 40;  // bf16 per LDS row (32 + 8 to spread banks)
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// fp32 -> bf16, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ uint32_t max_bf16x2(uint32_t a, uint32_t b) {
+  const float lo = fmaxf(bf2f(a & 0xffff), bf2f(b & 0xffff));
+  const float hi = fmaxf(bf2f(a >> 16), bf2f(b >> 16));
+  // the maximum is one of the inputs, so the bf16 conversion is exact
+  return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+}
+
+// Eight consecutive channels [c, c+8) of the (virtual) input at pixel (y, x).
+template <int MODE>
+__device__ __forceinline__ uint4 gather8(const ConvArgs& a, int b, int y, int x, int c) {
+  const uint16_t* s0 = static_cast<const uint16_t*>(a.src0);
+  if constexpr (MODE == G_PLAIN) {
+    return *reinterpret_cast<const uint4*>(s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c);
+  } else if constexpr (MODE == G_POOL) {
+    const int W2 = 2 * a.W;
+    const uint16_t* p = s0 + ((size_t)(b * 2 * a.H + 2 * y) * W2 + 2 * x) * a.c0 + c;
+    const uint4 v0 = *reinterpret_cast<const uint4*>(p);
+    const uint4 v1 = *reinterpret_cast<const uint4*>(p + a.c0);
+    const uint4 v2 = *reinterpret_cast<const uint4*>(p + (size_t)W2 * a.c0);
+    const uint4 v3 = *reinterpret_cast<const uint4*>(p + (size_t)W2 * a.c0 + a.c0);
+    uint4 r;
+    r.x = max_bf16x2(max_bf16x2(v0.x, v1.x), max_bf16x2(v2.x, v3.x));
+    r.y = max_bf16x2(max_bf16x2(v0.y, v1.y), max_bf16x2(v2.y, v3.y));
+    r.z = max_bf16x2(max_bf16x2(v0.z, v1.z), max_bf16x2(v2.z, v3.z));
+    r.w = max_bf16x2(max_bf16x2(v0.w, v1.w), max_bf16x2(v2.w, v3.w));
+    return r;
+  } else {  // G_CONCAT_UP
+    if (c < a.c0) return *reinterpret_cast<const uint4*>(s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c);
+    const int Hl = a.H >> 1, Wl = a.W >> 1;
+    return *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(a.src1) +
+                                           ((size_t)(b * Hl + (y >> 1)) * Wl + (x >> 1)) * a.c1 + (c - a.c0));
+  }
+}
+
+template <int TH>
+__device__ __forceinline__ void store_tile(const ConvArgs& a, const f4 (&acc)[TH / 4][2], int b, int y0, int x0,
+                                           int wrow, int g, int li) {
+  uint16_t* out = static_cast<uint16_t*>(a.out);
+#pragma unroll
+  for (int mf = 0; mf < TH / 4; ++mf) {
+    const int y = y0 + wrow + mf;
+    if (y >= a.H) continue;
+#pragma unroll
+    for (int nf = 0; nf < 2; ++nf) {
+      const int n = blockIdx.z * kBN + nf * 16 + li;
+      if (n >= a.co) continue;
+      const float bias = a.bias[n];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x = x0 + 4 * g + r;
+        if (x >= a.W) continue;
+        float v = acc[mf][nf][r] + bias;
+        if (a.relu) v = fmaxf(v, 0.0f);
+        out[((size_t)(b * a.H + y) * a.W + x) * a.co + n] = f2bf(v);
+      }
+    }
+  }
+}
+
+template <int MODE, int TH>
+__global__ __launch_bounds__(256) void conv3x3_bf16(ConvArgs a) {
+  constexpr int MF = TH / 4;
+  __shared__ __attribute__((aligned(16))) uint16_t s_in[(TH + 2) * kHW * kPad];
+  __shared__ __attribute__((aligned(16))) uint16_t s_w[9 * kBN * kPad];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_y = (a.H + TH - 1) / TH;
+  const int b = blockIdx.y / tiles_y;
+  const int y0 = (blockIdx.y - b * tiles_y) * TH, x0 = blockIdx.x * kTW;
+  const int g = lane >> 4, li = lane & 15, wrow = wave * MF;
+  const int nchunks = a.ci_pad / kCK;
+  const int ci = a.c0 + a.c1;  // real input channels (the rest of ci_pad is zero padding)
+  const uint16_t* wblk = static_cast<const uint16_t*>(a.w) + (size_t)blockIdx.z * nchunks * 9 * kBN * kCK;
+
+  f4 acc[MF][2];
+#pragma unroll
+  for (int mf = 0; mf < MF; ++mf) acc[mf][0] = acc[mf][1] = f4{0.f, 0.f, 0.f, 0.f};
+
+  for (int ch = 0; ch < nchunks; ++ch) {
+    constexpr int NQ = (TH + 2) * kHW * (kCK / 8);
+    for (int q = tid; q < NQ; q += 256) {
+      const int c8 = q & 3, p = q >> 2;
+      const int hx = p % kHW, hy = p / kHW;
+      const int y = y0 + hy - 1, x = x0 + hx - 1, c = ch * kCK + 8 * c8;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (y >= 0 && y < a.H && x >= 0 && x < a.W && c < ci) v = gather8<MODE>(a, b, y, x, c);
+      *reinterpret_cast<uint4*>(&s_in[p * kPad + 8 * c8]) = v;
+    }
+    const uint16_t* wsrc = wblk + (size_t)ch * 9 * kBN * kCK;
+    constexpr int NW = 9 * kBN * kCK / 8;
+    for (int q = tid; q < NW; q += 256) {
+      const int c8 = q & 3, row = q >> 2;
+      *reinterpret_cast<uint4*>(&s_w[row * kPad + 8 * c8]) = *reinterpret_cast<const uint4*>(wsrc + 8 * q);
+    }
+    __syncthreads();
+#pragma unroll 3
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap - 3 * (tap / 3);
+      bf16x8 av[MF], bv[2];
+#pragma unroll
+      for (int mf = 0; mf < MF; ++mf)
+        av[mf] = *reinterpret_cast<const bf16x8*>(&s_in[((wrow + mf + dy) * kHW + li + dx) * kPad + 8 * g]);
+#pragma unroll
+      for (int nf = 0; nf < 2; ++nf)
+        bv[nf] = *reinterpret_cast<const bf16x8*>(&s_w[(tap * kBN + nf * 16 + li) * kPad + 8 * g]);
+#pragma unroll
+      for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+        for (int nf = 0; nf < 2; ++nf)
+          acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mf], bv[nf], acc[mf][nf], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  store_tile<TH>(a, acc, b, y0, x0, wrow, g, li);
+}
+
+// First layer: 3 fp32 input channels; K slot k = 3 tap + c for k < 27.
+// Packed weights per n-tile: [n (32)][k (32)] bf16.
+template <int TH>
+__global__ __launch_bounds__(256) void conv3x3_bf16_guide(ConvArgs a) {
+  constexpr int MF = TH / 4;
+  __shared__ __attribute__((aligned(16))) float s_in[(TH + 2) * kHW * 4];
+  __shared__ __attribute__((aligned(16))) uint16_t s_w[kBN * kPad];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_y = (a.H + TH - 1) / TH;
+  const int b = blockIdx.y / tiles_y;
+  const int y0 = (blockIdx.y - b * tiles_y) * TH, x0 = blockIdx.x * kTW;
+  const int g = lane >> 4, li = lane & 15, wrow = wave * MF;
+  const float* gsrc = static_cast<const float*>(a.src0);
+  for (int p = tid; p < (TH + 2) * kHW; p += 256) {
+    const int hx = p % kHW, hy = p / kHW, y = y0 + hy - 1, x = x0 + hx - 1;
+    f4 v = f4{0.f, 0.f, 0.f, 0.f};
+    if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
+      const float* q = gsrc + ((size_t)(b * a.H + y) * a.W + x) * 3;
+      v = f4{q[0], q[1], q[2], 0.0f};
+    }
+    *reinterpret_cast<f4*>(&s_in[4 * p]) = v;
+  }
+  const uint16_t* wsrc = static_cast<const uint16_t*>(a.w) + (size_t)blockIdx.z * kBN * kCK;
+  for (int q = tid; q < kBN * kCK / 8; q += 256) {
+    const int c8 = q & 3, row = q >> 2;
+    *reinterpret_cast<uint4*>(&s_w[row * kPad + 8 * c8]) = *reinterpret_cast<const uint4*>(wsrc + 8 * q);
+  }
+  __syncthreads();
+  f4 acc[MF][2];
+  bf16x8 bv[2];
+#pragma unroll
+  for (int nf = 0; nf < 2; ++nf) bv[nf] = *reinterpret_cast<const bf16x8*>(&s_w[(nf * 16 + li) * kPad + 8 * g]);
+#pragma unroll
+  for (int mf = 0; mf < MF; ++mf) {
+    bf16x8 av;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = 8 * g + s;
+      float v = 0.0f;
+      if (k < 27) {
+        const int tap = k / 3, c = k - 3 * tap;
+        v = s_in[((wrow + mf + tap / 3) * kHW + li + (tap - 3 * (tap / 3))) * 4 + c];
+      }
+      av[s] = __builtin_bit_cast(__bf16, f2bf(v));
+    }
+#pragma unroll
+    for (int nf = 0; nf < 2; ++nf)
+      acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nf], f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+  }
+  store_tile<TH>(a, acc, b, y0, x0, wrow, g, li);
+}
+
+template <int MODE>
+hipError_t launch_tile(const ConvArgs& a, hipStream_t s) {
+  constexpr int TH = 8;
+  dim3 grid((a.W + kTW - 1) / kTW, ((a.H + TH - 1) / TH) * a.B, (a.co + kBN - 1) / kBN);
+  if constexpr (MODE == G_GUIDE)
+    hipLaunchKernelGGL((conv3x3_bf16_guide<TH>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((conv3x3_bf16<MODE, TH>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_conv3x3_bf16(int mode, const ConvArgs& a, hipStream_t s) {
+  switch (mode) {
+    case G_GUIDE: return launch_tile<G_GUIDE>(a, s);
+    case G_PLAIN: return launch_tile<G_PLAIN>(a, s);
+    case G_POOL: return launch_tile<G_POOL>(a, s);
+    case G_CONCAT_UP: return launch_tile<G_CONCAT_UP>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace lnm

@@ -1,0 +1,271 @@
+// U-Net 3x3 convolutions (Section 4.3) in FP8 e4m3 (OCP) on the gfx950
+// matrix cores (v_mfma_f32_16x16x32_fp8_fp8, fp32 accumulation).
+//
+// Quantisation: weights per output channel, q_w = rne(W / s_w[o]) with
+// s_w[o] = max|W[o]| / 448; activations per stored tensor, q = rne(y / s_t)
+// saturated to 448.  A layer computes y = s_in s_w[o] sum q_in q_w + b,
+// applies ReLU and stores rne(y / s_out) for its consumers.  The two inputs
+// of a decoder concatenation share one scale, so the K-sum factors.
+//
+// Tiling as in the bf16 kernel (TH x 16 pixels x 32 output channels per
+// workgroup, 32-channel input chunks staged in LDS, lane group g supplying
+// channels 8g..8g+7 of a chunk to both operands with one 8-byte read).  The
+// 3-channel input layer runs in bf16 (27 taps x channels in one K step) and
+// writes fp8.
+#include "internal.h"
+
+namespace lnm {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTW = 16;
+constexpr int kHW = kTW + 2;
+constexpr int kCK = 32;      // input channels per chunk (bytes per pixel row)
+constexpr int kRow = 40;     // LDS bytes per halo pixel / weight row (32 + 8)
+constexpr int kRowBf = 40;   // bf16 elements per weight row of the guide layer
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// fp32 -> e4m3 byte, round to nearest even, saturating at +-448.
+__device__ __forceinline__ uint32_t f2fp8(float v) {
+  v = fminf(fmaxf(v, -448.0f), 448.0f);
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xffu;
+}
+
+__device__ __forceinline__ uint32_t max_u8x4(uint32_t a, uint32_t b) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t x = (a >> (8 * k)) & 0xffu, y = (b >> (8 * k)) & 0xffu;
+    r |= (x > y ? x : y) << (8 * k);
+  }
+  return r;
+}
+
+// Eight channels [c, c+8) of the virtual input at (y, x) as 8 e4m3 bytes.
+// Stored activations are ReLU outputs (non-negative, +0 encoded as 0), whose
+// e4m3 encodings order like unsigned bytes, so max-pooling compares bytes.
+template <int MODE>
+__device__ __forceinline__ uint2 gather8(const ConvArgs& a, int b, int y, int x, int c) {
+  const uint8_t* s0 = static_cast<const uint8_t*>(a.src0);
+  if constexpr (MODE == G_PLAIN) {
+    return *reinterpret_cast<const uint2*>(s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c);
+  } else if constexpr (MODE == G_POOL) {
+    const int W2 = 2 * a.W;
+    const uint8_t* p = s0 + ((size_t)(b * 2 * a.H + 2 * y) * W2 + 2 * x) * a.c0 + c;
+    const uint2 v0 = *reinterpret_cast<const uint2*>(p);
+    const uint2 v1 = *reinterpret_cast<const uint2*>(p + a.c0);
+    const uint2 v2 = *reinterpret_cast<const uint2*>(p + (size_t)W2 * a.c0);
+    const uint2 v3 = *reinterpret_cast<const uint2*>(p + (size_t)W2 * a.c0 + a.c0);
+    return make_uint2(max_u8x4(max_u8x4(v0.x, v1.x), max_u8x4(v2.x, v3.x)),
+                      max_u8x4(max_u8x4(v0.y, v1.y), max_u8x4(v2.y, v3.y)));
+  } else {  // G_CONCAT_UP
+    if (c < a.c0) return *reinterpret_cast<const uint2*>(s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c);
+    const int Hl = a.H >> 1, Wl = a.W >> 1;
+    return *reinterpret_cast<const uint2*>(static_cast<const uint8_t*>(a.src1) +
+                                           ((size_t)(b * Hl + (y >> 1)) * Wl + (x >> 1)) * a.c1 + (c - a.c0));
+  }
+}
+
+// y = scale[o] * acc + bias (scale = s_in s_w[o], or 1 for the bf16 layer),
+// ReLU, stored as e4m3 of y * out_inv_scale.
+template <int TH>
+__device__ __forceinline__ void store_fp8(const ConvArgs& a, const f4 (&acc)[TH / 4][2], int b, int y0, int x0,
+                                          int wrow, int g, int li, bool scaled) {
+  uint8_t* out = static_cast<uint8_t*>(a.out);
+#pragma unroll
+  for (int nf = 0; nf < 2; ++nf) {
+    const int n = blockIdx.z * kBN + nf * 16 + li;
+    if (n >= a.co) continue;
+    const float bias = a.bias[n];
+    const float sc = scaled ? a.in_scale * a.w_scale[n] : 1.0f;
+#pragma unroll
+    for (int mf = 0; mf < TH / 4; ++mf) {
+      const int y = y0 + wrow + mf;
+      if (y >= a.H) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int x = x0 + 4 * g + r;
+        if (x >= a.W) continue;
+        float v = sc * acc[mf][nf][r] + bias;
+        v = v > 0.0f ? v * a.out_inv_scale : 0.0f;
+        out[((size_t)(b * a.H + y) * a.W + x) * a.co + n] = (uint8_t)f2fp8(v);
+      }
+    }
+  }
+}
+
+template <int MODE, int TH>
+__global__ __launch_bounds__(256) void conv3x3_fp8(ConvArgs a) {
+  constexpr int MF = TH / 4;
+  __shared__ __attribute__((aligned(16))) uint8_t s_in[(TH + 2) * kHW * kRow];
+  __shared__ __attribute__((aligned(16))) uint8_t s_w[9 * kBN * kRow];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_y = (a.H + TH - 1) / TH;
+  const int b = blockIdx.y / tiles_y;
+  const int y0 = (blockIdx.y - b * tiles_y) * TH, x0 = blockIdx.x * kTW;
+  const int g = lane >> 4, li = lane & 15, wrow = wave * MF;
+  const int nchunks = a.ci_pad / kCK;
+  const int ci = a.c0 + a.c1;
+  const uint8_t* wblk = static_cast<const uint8_t*>(a.w) + (size_t)blockIdx.z * nchunks * 9 * kBN * kCK;
+
+  f4 acc[MF][2];
+#pragma unroll
+  for (int mf = 0; mf < MF; ++mf) acc[mf][0] = acc[mf][1] = f4{0.f, 0.f, 0.f, 0.f};
+
+  for (int ch = 0; ch < nchunks; ++ch) {
+    constexpr int NQ = (TH + 2) * kHW * (kCK / 8);
+    for (int q = tid; q < NQ; q += 256) {
+      const int c8 = q & 3, p = q >> 2;
+      const int hx = p % kHW, hy = p / kHW;
+      const int y = y0 + hy - 1, x = x0 + hx - 1, c = ch * kCK + 8 * c8;
+      uint2 v = make_uint2(0, 0);
+      if (y >= 0 && y < a.H && x >= 0 && x < a.W && c < ci) v = gather8<MODE>(a, b, y, x, c);
+      *reinterpret_cast<uint2*>(&s_in[p * kRow + 8 * c8]) = v;
+    }
+    const uint8_t* wsrc = wblk + (size_t)ch * 9 * kBN * kCK;
+    constexpr int NW = 9 * kBN * kCK / 16;
+    for (int q = tid; q < NW; q += 256) {
+      const int c16 = q & 1, row = q >> 1;
+      const uint4 w = *reinterpret_cast<const uint4*>(wsrc + 16 * q);
+      *reinterpret_cast<uint2*>(&s_w[row * kRow + 16 * c16]) = make_uint2(w.x, w.y);
+      *reinterpret_cast<uint2*>(&s_w[row * kRow + 16 * c16 + 8]) = make_uint2(w.z, w.w);
+    }
+    __syncthreads();
+#pragma unroll 3
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap - 3 * (tap / 3);
+      long av[MF], bv[2];
+#pragma unroll
+      for (int mf = 0; mf < MF; ++mf)
+        av[mf] = *reinterpret_cast<const long*>(&s_in[((wrow + mf + dy) * kHW + li + dx) * kRow + 8 * g]);
+#pragma unroll
+      for (int nf = 0; nf < 2; ++nf)
+        bv[nf] = *reinterpret_cast<const long*>(&s_w[(tap * kBN + nf * 16 + li) * kRow + 8 * g]);
+#pragma unroll
+      for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+        for (int nf = 0; nf < 2; ++nf)
+          acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av[mf], bv[nf], acc[mf][nf], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  store_fp8<TH>(a, acc, b, y0, x0, wrow, g, li, true);
+}
+
+// The 3-channel input layer in bf16 (as in the bf16 network), fp8 output.
+template <int TH>
+__global__ __launch_bounds__(256) void conv3x3_guide_to_fp8(ConvArgs a) {
+  constexpr int MF = TH / 4;
+  __shared__ __attribute__((aligned(16))) float s_in[(TH + 2) * kHW * 4];
+  __shared__ __attribute__((aligned(16))) uint16_t s_w[kBN * kRowBf];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_y = (a.H + TH - 1) / TH;
+  const int b = blockIdx.y / tiles_y;
+  const int y0 = (blockIdx.y - b * tiles_y) * TH, x0 = blockIdx.x * kTW;
+  const int g = lane >> 4, li = lane & 15, wrow = wave * MF;
+  const float* gsrc = static_cast<const float*>(a.src0);
+  for (int p = tid; p < (TH + 2) * kHW; p += 256) {
+    const int hx = p % kHW, hy = p / kHW, y = y0 + hy - 1, x = x0 + hx - 1;
+    f4 v = f4{0.f, 0.f, 0.f, 0.f};
+    if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
+      const float* q = gsrc + ((size_t)(b * a.H + y) * a.W + x) * 3;
+      v = f4{q[0], q[1], q[2], 0.0f};
+    }
+    *reinterpret_cast<f4*>(&s_in[4 * p]) = v;
+  }
+  const uint16_t* wsrc = static_cast<const uint16_t*>(a.w) + (size_t)blockIdx.z * kBN * 32;
+  for (int q = tid; q < kBN * 32 / 8; q += 256) {
+    const int c8 = q & 3, row = q >> 2;
+    *reinterpret_cast<uint4*>(&s_w[row * kRowBf + 8 * c8]) = *reinterpret_cast<const uint4*>(wsrc + 8 * q);
+  }
+  __syncthreads();
+  f4 acc[MF][2];
+  bf16x8 bv[2];
+#pragma unroll
+  for (int nf = 0; nf < 2; ++nf) bv[nf] = *reinterpret_cast<const bf16x8*>(&s_w[(nf * 16 + li) * kRowBf + 8 * g]);
+#pragma unroll
+  for (int mf = 0; mf < MF; ++mf) {
+    bf16x8 av;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = 8 * g + s;
+      float v = 0.0f;
+      if (k < 27) {
+        const int tap = k / 3, c = k - 3 * tap;
+        v = s_in[((wrow + mf + tap / 3) * kHW + li + (tap - 3 * (tap / 3))) * 4 + c];
+      }
+      av[s] = __builtin_bit_cast(__bf16, f2bf(v));
+    }
+#pragma unroll
+    for (int nf = 0; nf < 2; ++nf)
+      acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nf], f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+  }
+  store_fp8<TH>(a, acc, b, y0, x0, wrow, g, li, false);
+}
+
+// Per-block maximum of |x| over a fixed range, then the maximum of those.
+__global__ __launch_bounds__(256) void amax_partial(const float* __restrict__ x, long n, float* __restrict__ part) {
+  __shared__ float sh[256];
+  const long per = (n + gridDim.x - 1) / gridDim.x;
+  const long lo = (long)blockIdx.x * per, hi = min(n, lo + per);
+  float m = 0.0f;
+  for (long i = lo + threadIdx.x; i < hi; i += 256) m = fmaxf(m, fabsf(x[i]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void amax_finish(const float* __restrict__ part, int n, float* __restrict__ out) {
+  __shared__ float sh[256];
+  float m = 0.0f;
+  for (int i = threadIdx.x; i < n; i += 256) m = fmaxf(m, part[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+template <int MODE>
+hipError_t launch_tile(const ConvArgs& a, hipStream_t s) {
+  constexpr int TH = 8;
+  dim3 grid((a.W + kTW - 1) / kTW, ((a.H + TH - 1) / TH) * a.B, (a.co + kBN - 1) / kBN);
+  if constexpr (MODE == G_GUIDE)
+    hipLaunchKernelGGL((conv3x3_guide_to_fp8<TH>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((conv3x3_fp8<MODE, TH>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_conv3x3_fp8(int mode, const ConvArgs& a, hipStream_t s) {
+  switch (mode) {
+    case G_GUIDE: return launch_tile<G_GUIDE>(a, s);
+    case G_PLAIN: return launch_tile<G_PLAIN>(a, s);
+    case G_POOL: return launch_tile<G_POOL>(a, s);
+    case G_CONCAT_UP: return launch_tile<G_CONCAT_UP>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_amax(const float* x, long n, float* partial, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(amax_partial, dim3(kAmaxBlocks), dim3(256), 0, s, x, n, partial);
+  hipLaunchKernelGGL(amax_finish, dim3(1), dim3(256), 0, s, partial, kAmaxBlocks, out);
+  return hipGetLastError();
+}
+
+}  // namespace lnm

@@ -1,0 +1,210 @@
+// Internal declarations shared by the liblnm translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lnm.h"
+
+namespace lnm {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+lnm_status fail(lnm_status st, const std::string& msg);
+#define LNM_HIP_CHECK(expr)                                                              \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess)                                                                \
+      return ::lnm::fail(LNM_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+// ---------------------------------------------------------------- camera
+// Camera basis prepared on the host in fp64 and rounded once to fp32.
+struct CamDev {
+  float eye[3], f[3], r[3], u[3];
+  float tan_half, half_extent, aspect;
+  int proj, W, H;
+};
+bool make_cam(const lnm_camera& c, CamDev* out, std::string* why);
+
+// ---------------------------------------------------------------- march
+struct MarchDev {
+  const float* rho;
+  int nx, ny, nz;
+  float sigma_scale;
+  float h;        // world step
+  float depth_tau;
+  float tau_max;  // -ln(eps), +inf when disabled
+  int jitter_on;
+  uint64_t seed;
+  uint32_t frame;
+  int quadrature;
+  float wf, wt, wb;
+};
+hipError_t launch_march(const MarchDev& m, const CamDev& cam, float* guide, hipStream_t s);
+hipError_t launch_reference(const MarchDev& m, const CamDev& cam, int srgb, float* lm, hipStream_t s);
+
+// ---------------------------------------------------------------- network
+constexpr int kBN = 32;  // output-channel tile of the conv kernels
+
+enum Gather : int { G_GUIDE = 0, G_PLAIN = 1, G_POOL = 2, G_CONCAT_UP = 3 };
+
+struct LayerDesc {
+  int ci, co, k;
+  int ck;        // input-channel chunk of the packed layout
+  int ci_pad;    // ci rounded up to ck
+  int co_pad;    // co rounded up to kBN
+  size_t w_off;  // byte offset of the packed weights in the device buffer
+  size_t b_off;  // byte offset of the fp32 biases (co_pad of them)
+  size_t s_off;  // byte offset of fp32 per-output-channel weight scales (fp8)
+};
+
+// Activation element types: fp32 (4 bytes), bf16 (2), fp8 e4m3 (1).
+struct ConvArgs {
+  const void* src0;   // input (guide / plain / pooled source / skip)
+  const void* src1;   // low-resolution tensor for concat-upsample
+  int c0, c1;         // channels of src0 and src1
+  int B, H, W;        // output spatial size
+  int ci_pad, co;     // padded input channels, real output channels
+  const void* w;      // packed weights
+  const float* bias;  // [co_pad]
+  void* out;          // [B][H][W][co]
+  int relu;
+  // fp8 form: y = in_scale * w_scale[o] * acc + bias; stored as y * out_inv_scale
+  const float* w_scale;
+  float in_scale, out_inv_scale;
+};
+hipError_t launch_conv3x3_f32(int mode, int ck, const ConvArgs& a, hipStream_t s);
+hipError_t launch_conv3x3_bf16(int mode, const ConvArgs& a, hipStream_t s);
+hipError_t launch_conv3x3_fp8(int mode, const ConvArgs& a, hipStream_t s);
+constexpr int kAmaxBlocks = 256;
+// max |x| over n floats into *out (partial: kAmaxBlocks floats of scratch)
+hipError_t launch_amax(const float* x, long n, float* partial, float* out, hipStream_t s);
+
+struct HeadArgs {
+  const void* in;   // [P][C] activations of the last decoder layer
+  int in_type;      // 0 fp32, 1 bf16, 2 fp8
+  float in_scale;   // fp8 dequantisation scale
+  int P, C;
+  const float* w;   // [6][C]
+  const float* b;   // [6]
+  float* lm;        // [P][6] sigmoid output
+  float* logits;    // optional [P][6]
+};
+hipError_t launch_head(const HeadArgs& a, hipStream_t s);
+
+struct CompositeArgs {
+  const float* lm;     // [P][6]
+  const float* guide;  // [P][3]
+  float* rgba;         // [P][4]
+  int P;
+  int n_lights;
+  float l[16][3];      // light direction in the camera frame
+  float rgb[16][3];
+};
+hipError_t launch_composite(const CompositeArgs& a, hipStream_t s);
+
+}  // namespace lnm
+
+struct lnm_ctx_s {
+  int device;
+  int cu_count;
+  std::string arch;
+  // per-launch timing (lnm_profile_enable)
+  bool prof = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+};
+
+namespace lnm {
+// Brackets one kernel launch with events when the context is profiling.
+class ProfScope {
+ public:
+  ProfScope(lnm_ctx_s* ctx, int kind, hipStream_t s);
+  ~ProfScope();
+
+ private:
+  lnm_ctx_s* ctx_;
+  hipStream_t s_;
+  int idx_ = -1;
+};
+}  // namespace lnm
+
+struct lnm_net_s {
+  int levels, base, precision;
+  std::vector<lnm::LayerDesc> layers;
+  char* dev;  // caller-owned buffer
+  size_t dev_bytes;
+  std::vector<float> act_scale;  // fp8: per stored activation tensor (one per conv layer + the guide)
+};
+
+namespace lnm {
+// ---------------------------------------------------------------- network helpers (api.hip)
+int elem_bytes(int precision);
+size_t align256(size_t x);
+bool net_shape(int levels, int base, int precision, std::vector<LayerDesc>* out, size_t* dev_bytes, std::string* why);
+size_t param_count(int levels, int base);
+constexpr size_t kScratchBytes = 64 * 1024;  // small reductions (calibration)
+struct Plan {
+  std::vector<size_t> out_off;  // byte offset of each conv layer's output
+  size_t scratch_off;           // kScratchBytes of scratch after the activations
+  size_t bytes;
+};
+Plan plan_workspace(const lnm_net_s* net, int B, int H, int W);
+lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, const float* guide, float* lm,
+                    float* logits, char* ws, hipStream_t s);
+lnm_status check_infer(const lnm_net_s* net, int B, int H, int W, size_t ws_bytes, const void* ws);
+
+// ---------------------------------------------------------------- training kernels (train.hip)
+// Layer geometry shared by the backward kernels.
+struct WgradArgs {
+  ConvArgs x;       // the layer's (virtual) input, as the forward gather sees it
+  const float* e;   // [B][H][W][co] gradient at the pre-activation
+  int co, ci;       // real channels
+  int ci_pad16;     // ci rounded up to 16
+  int tiles_per_group;
+  float* partial;   // [groups * 4][co_pad][ci_pad16][9]
+};
+hipError_t launch_wgrad3x3(int mode, const WgradArgs& a, int* n_partials, hipStream_t s);
+hipError_t launch_wgrad_reduce(const float* partial, int n_partials, int co, int ci, int co_pad, int ci_pad16,
+                               float* grad_w, hipStream_t s);
+hipError_t launch_loss(const float* y, const float* t, float* dz, float* partial, long n, float* loss,
+                       hipStream_t s);
+hipError_t launch_colsum(const float* e, long P, int C, float* partial, float* out, hipStream_t s);
+hipError_t launch_relu_mask(float* g, const float* y, long n, hipStream_t s);
+hipError_t launch_head_bwd(const float* dz, const float* w, const float* x, long P, int C, float* e_out,
+                           float* grad_w, float* grad_b, float* partial, hipStream_t s);
+hipError_t launch_route_concat(const float* dx, int B, int H, int W, int c0, int c1, float* g_skip, float* g_low,
+                               hipStream_t s);
+hipError_t launch_route_pool(const float* dx, const float* y, int B, int h, int w, int c, float* g, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, long n, float lr, float b1, float b2, float eps,
+                       int t, hipStream_t s);
+// Repack flat parameters into the fp32 forward layout (dgrad = 0) or the
+// transposed, tap-flipped layout used to propagate gradients (dgrad = 1).
+hipError_t launch_pack_f32(const float* flat_w, const float* flat_b, const LayerDesc& d, int dgrad, char* dst,
+                           size_t w_off, size_t b_off, hipStream_t s);
+constexpr int kLossBlocks = 256;
+constexpr int kColsumBlocks = 128;
+}  // namespace lnm
+
+struct lnm_trainer_s {
+  lnm_ctx_s* ctx;
+  lnm_net_s net;         // fp32 forward weights inside the state buffer
+  char* state;
+  size_t n_params;
+  float *p, *g, *m, *v;  // flat, parameter-file order
+  std::vector<size_t> flat_w, flat_b;  // per layer offsets (floats) in the flat vector
+  std::vector<lnm::LayerDesc> dgrad;   // transposed layout per layer (layer 0 unused)
+  std::vector<size_t> dgrad_off;       // byte offset of each transposed weight block in the state
+  float* zeros;          // zero bias for the data-gradient convolutions
+  int step;
+};

@@ -1,0 +1,464 @@
+"""ctypes binding of liblnm (include/lnm.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current stream.  If the
+library is missing this module raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblnm.so")
+
+LNM_OK, LNM_ERR_ARG, LNM_ERR_SHAPE, LNM_ERR_OOM, LNM_ERR_DEVICE, LNM_ERR_UNSUPPORTED = range(6)
+FP32, BF16, FP8_E4M3 = 0, 1, 2
+ORTHOGRAPHIC, PERSPECTIVE = 0, 1
+QUAD_ALPHA, QUAD_RIEMANN = 0, 1
+
+EXPORTS = [
+    "lnm_abi_struct_size", "lnm_version", "lnm_ctx_create", "lnm_ctx_destroy", "lnm_last_error",
+    "lnm_march_workspace_bytes", "lnm_march", "lnm_reference_lightmaps", "lnm_net_param_count",
+    "lnm_net_device_bytes", "lnm_net_create", "lnm_net_destroy", "lnm_workspace_bytes", "lnm_infer", "lnm_frame",
+    "lnm_composite", "lnm_profile_enable", "lnm_profile_read", "lnm_trainer_state_bytes",
+    "lnm_train_workspace_bytes", "lnm_trainer_create", "lnm_trainer_destroy", "lnm_train_grad", "lnm_train_step",
+    "lnm_trainer_read_params", "lnm_trainer_save", "lnm_trainer_load", "lnm_trainer_infer", "lnm_calibrate_amax",
+]
+K_MARCH, K_CONV, K_HEAD, K_COMPOSITE, K_REFERENCE = range(5)
+
+
+class LnmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"liblnm status {status}: {msg}")
+        self.status = status
+
+
+class Volume(C.Structure):
+    _fields_ = [("density", C.c_void_p), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("sigma_scale", C.c_float)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("projection", C.c_int32), ("eye", C.c_float * 3), ("target", C.c_float * 3), ("up", C.c_float * 3),
+                ("fov_y_deg", C.c_float), ("ortho_half_extent", C.c_float), ("width", C.c_int32),
+                ("height", C.c_int32)]
+
+
+class MarchParams(C.Structure):
+    _fields_ = [("step_voxels", C.c_float), ("depth_tau", C.c_float), ("ert_eps", C.c_float),
+                ("jitter_on", C.c_int32), ("jitter_seed", C.c_uint64), ("frame", C.c_uint32),
+                ("quadrature", C.c_int32), ("light_w", C.c_float * 3), ("reserved", C.c_int32)]
+
+
+class Light(C.Structure):
+    _fields_ = [("dir", C.c_float * 3), ("rgb", C.c_float * 3)]
+
+
+_lib = None
+
+
+def lib():
+    """Load liblnm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, sz = C.c_void_p, C.c_int32, C.c_size_t
+        L.lnm_abi_struct_size.restype = sz
+        L.lnm_abi_struct_size.argtypes = [i32]
+        L.lnm_version.restype = C.c_char_p
+        L.lnm_last_error.restype = C.c_char_p
+        L.lnm_ctx_create.restype = i32
+        L.lnm_ctx_create.argtypes = [i32, C.POINTER(vp)]
+        L.lnm_ctx_destroy.argtypes = [vp]
+        L.lnm_march_workspace_bytes.restype = sz
+        L.lnm_march_workspace_bytes.argtypes = [C.POINTER(Volume)]
+        L.lnm_march.restype = i32
+        L.lnm_march.argtypes = [vp, C.POINTER(Volume), C.POINTER(Camera), C.POINTER(MarchParams), vp, vp, sz, vp]
+        L.lnm_reference_lightmaps.restype = i32
+        L.lnm_reference_lightmaps.argtypes = [vp, C.POINTER(Volume), C.POINTER(Camera), C.c_float, C.c_float, i32,
+                                              vp, vp]
+        L.lnm_net_param_count.restype = sz
+        L.lnm_net_param_count.argtypes = [i32, i32]
+        L.lnm_net_device_bytes.restype = sz
+        L.lnm_net_device_bytes.argtypes = [i32, i32, i32]
+        L.lnm_net_create.restype = i32
+        L.lnm_net_create.argtypes = [vp, i32, i32, i32, vp, sz, vp, vp, sz, vp, C.POINTER(vp)]
+        L.lnm_net_destroy.argtypes = [vp]
+        L.lnm_workspace_bytes.restype = sz
+        L.lnm_workspace_bytes.argtypes = [vp, i32, i32, i32]
+        L.lnm_infer.restype = i32
+        L.lnm_infer.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, sz, vp]
+        L.lnm_frame.restype = i32
+        L.lnm_frame.argtypes = [vp, vp, C.POINTER(Volume), C.POINTER(Camera), C.POINTER(MarchParams),
+                                C.POINTER(Light), i32, vp, vp, vp, vp, sz, vp]
+        L.lnm_composite.restype = i32
+        L.lnm_composite.argtypes = [vp, C.POINTER(Camera), C.POINTER(Light), i32, i32, i32, i32, vp, vp, vp, vp]
+        L.lnm_calibrate_amax.restype = i32
+        L.lnm_calibrate_amax.argtypes = [vp, vp, i32, i32, i32, vp, vp, i32, vp, sz, vp]
+        L.lnm_profile_enable.restype = i32
+        L.lnm_profile_enable.argtypes = [vp, i32]
+        L.lnm_profile_read.restype = i32
+        L.lnm_profile_read.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(C.c_double)]
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != LNM_OK:
+        raise LnmError(status, lib().lnm_last_error().decode())
+
+
+# ------------------------------------------------------------------ marshalling
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _need(t, shape, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def make_camera(cam) -> Camera:
+    """From any object with the fields of lnm_camera (e.g. synth.scene.Camera)."""
+    c = Camera()
+    c.projection = int(cam.projection)
+    c.eye[:] = [float(v) for v in cam.eye]
+    c.target[:] = [float(v) for v in cam.target]
+    c.up[:] = [float(v) for v in cam.up]
+    c.fov_y_deg = float(cam.fov_y_deg)
+    c.ortho_half_extent = float(cam.ortho_half_extent)
+    c.width = int(cam.width)
+    c.height = int(cam.height)
+    return c
+
+
+def make_params(step_voxels, depth_tau=0.1, ert_eps=1e-6, jitter=True, seed=0, frame=0, quadrature=QUAD_ALPHA,
+                light_w=(1.0, 1.0, 1.0)) -> MarchParams:
+    p = MarchParams()
+    p.step_voxels = step_voxels
+    p.depth_tau = depth_tau
+    p.ert_eps = ert_eps
+    p.jitter_on = int(bool(jitter))
+    p.jitter_seed = int(seed) & (2**64 - 1)
+    p.frame = int(frame)
+    p.quadrature = int(quadrature)
+    p.light_w[:] = [float(v) for v in light_w]
+    p.reserved = 0
+    return p
+
+
+def make_volume(density, sigma_scale) -> Volume:
+    import torch
+
+    if not isinstance(density, torch.Tensor) or density.dtype != torch.float32 or not density.is_cuda \
+            or density.dim() != 3 or not density.is_contiguous():
+        raise TypeError("density must be a contiguous 3-D float32 CUDA tensor [nz][ny][nx]")
+    v = Volume()
+    v.density = density.data_ptr()
+    v.nz, v.ny, v.nx = (int(s) for s in density.shape)
+    v.sigma_scale = float(sigma_scale)
+    return v
+
+
+def make_lights(lights):
+    lights = list(lights or [])
+    arr = (Light * max(1, len(lights)))()
+    for k, (d, rgb) in enumerate(lights):
+        arr[k].dir[:] = [float(v) for v in d]
+        arr[k].rgb[:] = [float(v) for v in rgb]
+    return arr, len(lights)
+
+
+# ------------------------------------------------------------------ objects
+class Context:
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        check(lib().lnm_ctx_create(device, C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.lnm_ctx_destroy(self.handle)
+            self.handle = None
+
+    # -- per-launch timing
+    def profile(self, on: bool):
+        check(lib().lnm_profile_enable(self.handle, int(bool(on))))
+
+    def profile_read(self, kind: int):
+        """(launches, total milliseconds) recorded for one kernel kind."""
+        n, ms = C.c_int32(), C.c_double()
+        check(lib().lnm_profile_read(self.handle, kind, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+    # -- march
+    def march(self, density, sigma_scale, cam, params: MarchParams, out=None, stream=None):
+        import torch
+
+        vol = make_volume(density, sigma_scale)
+        c = make_camera(cam)
+        if out is None:
+            out = torch.empty((c.height, c.width, 3), dtype=torch.float32, device=density.device)
+        _need(out, (c.height, c.width, 3), "guide")
+        check(lib().lnm_march(self.handle, C.byref(vol), C.byref(c), C.byref(params), _ptr(out), None, 0,
+                              _stream(stream)))
+        return out
+
+    def reference_lightmaps(self, density, sigma_scale, cam, step_voxels=0.25, ert_eps=1e-6, srgb=False, out=None,
+                            stream=None):
+        import torch
+
+        vol = make_volume(density, sigma_scale)
+        c = make_camera(cam)
+        if out is None:
+            out = torch.empty((c.height, c.width, 6), dtype=torch.float32, device=density.device)
+        _need(out, (c.height, c.width, 6), "lightmaps")
+        check(lib().lnm_reference_lightmaps(self.handle, C.byref(vol), C.byref(c), step_voxels, ert_eps, int(srgb),
+                                            _ptr(out), _stream(stream)))
+        return out
+
+    def composite(self, cam, lights, lightmaps, guide, out=None, stream=None):
+        import torch
+
+        c = make_camera(cam)
+        B = lightmaps.shape[0] if lightmaps.dim() == 4 else 1
+        H, W = c.height, c.width
+        if out is None:
+            out = torch.empty(tuple(lightmaps.shape[:-1]) + (4,), dtype=torch.float32, device=lightmaps.device)
+        arr, n = make_lights(lights)
+        check(lib().lnm_composite(self.handle, C.byref(c), arr, n, B, H, W, _ptr(lightmaps), _ptr(guide), _ptr(out),
+                                  _stream(stream)))
+        return out
+
+
+def param_count(levels: int, base: int) -> int:
+    return int(lib().lnm_net_param_count(levels, base))
+
+
+class Net:
+    """Packed U-Net weights in a torch-owned device buffer."""
+
+    def __init__(self, ctx: Context, levels: int, base: int, params, precision: int = FP32, act_scales=None,
+                 device=None, stream=None):
+        import torch
+
+        self.ctx, self.levels, self.base, self.precision = ctx, levels, base, precision
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        nbytes = int(lib().lnm_net_device_bytes(levels, base, precision))
+        if nbytes == 0:
+            raise LnmError(LNM_ERR_UNSUPPORTED, f"no packed layout for levels={levels} base={base} "
+                                                f"precision={precision}")
+        dev = device if device is not None else torch.device("cuda", ctx.device)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        sc = None if act_scales is None else np.ascontiguousarray(act_scales, dtype=np.float32)
+        h = C.c_void_p()
+        check(lib().lnm_net_create(ctx.handle, levels, base, precision, p.ctypes.data_as(C.c_void_p), p.size,
+                                   None if sc is None else sc.ctypes.data_as(C.c_void_p), _ptr(self.buf), nbytes,
+                                   _stream(stream), C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.lnm_net_destroy(self.handle)
+            self.handle = None
+
+    def workspace_bytes(self, batch, H, W) -> int:
+        return int(lib().lnm_workspace_bytes(self.handle, batch, H, W))
+
+    def calibrate_amax(self, guide, stream=None) -> np.ndarray:
+        """Per-convolution maximum |output| of this (fp32) net on guide [B][H][W][3]."""
+        g = guide if guide.dim() == 4 else guide.unsqueeze(0)
+        B, H, W, _ = g.shape
+        _need(g, (B, H, W, 3), "guide")
+        n = 4 * self.levels - 2
+        out = np.zeros(n, dtype=np.float32)
+        ws = self.workspace(B, H, W)
+        check(lib().lnm_calibrate_amax(self.ctx.handle, self.handle, B, H, W, _ptr(g), out.ctypes.data_as(C.c_void_p),
+                                       n, _ptr(ws), ws.numel(), _stream(stream)))
+        return out
+
+    def workspace(self, batch, H, W):
+        import torch
+
+        return torch.empty(max(1, self.workspace_bytes(batch, H, W)), dtype=torch.uint8, device=self.buf.device)
+
+    def infer(self, guide, out=None, logits=None, workspace=None, stream=None):
+        import torch
+
+        g = guide if guide.dim() == 4 else guide.unsqueeze(0)
+        B, H, W, _ = g.shape
+        _need(g, (B, H, W, 3), "guide")
+        if out is None:
+            out = torch.empty((B, H, W, 6), dtype=torch.float32, device=g.device)
+        if workspace is None:
+            workspace = self.workspace(B, H, W)
+        check(lib().lnm_infer(self.ctx.handle, self.handle, B, H, W, _ptr(g), _ptr(out), _ptr(logits),
+                              _ptr(workspace), workspace.numel(), _stream(stream)))
+        return out if guide.dim() == 4 else out[0]
+
+    def frame(self, density, sigma_scale, cam, params: MarchParams, lights=(), guide=None, lightmaps=None, rgba=None,
+              workspace=None, stream=None, shade=True):
+        import torch
+
+        vol = make_volume(density, sigma_scale)
+        c = make_camera(cam)
+        H, W = c.height, c.width
+        dev = density.device
+        guide = guide if guide is not None else torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+        lightmaps = lightmaps if lightmaps is not None else torch.empty((H, W, 6), dtype=torch.float32, device=dev)
+        if shade and rgba is None:
+            rgba = torch.empty((H, W, 4), dtype=torch.float32, device=dev)
+        if workspace is None:
+            workspace = self.workspace(1, H, W)
+        arr, n = make_lights(lights)
+        check(lib().lnm_frame(self.ctx.handle, self.handle, C.byref(vol), C.byref(c), C.byref(params), arr, n,
+                              _ptr(guide), _ptr(lightmaps), _ptr(rgba) if shade else None, _ptr(workspace),
+                              workspace.numel(), _stream(stream)))
+        return guide, lightmaps, rgba
+
+
+# ------------------------------------------------------------------ training
+def _train_sigs(L):
+    vp, i32, sz, f = C.c_void_p, C.c_int32, C.c_size_t, C.c_float
+    L.lnm_trainer_state_bytes.restype = sz
+    L.lnm_trainer_state_bytes.argtypes = [i32, i32]
+    L.lnm_train_workspace_bytes.restype = sz
+    L.lnm_train_workspace_bytes.argtypes = [i32, i32, i32, i32, i32]
+    L.lnm_trainer_create.restype = i32
+    L.lnm_trainer_create.argtypes = [vp, i32, i32, vp, sz, vp, sz, vp, C.POINTER(vp)]
+    L.lnm_trainer_destroy.argtypes = [vp]
+    L.lnm_train_grad.restype = i32
+    L.lnm_train_grad.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, sz, vp]
+    L.lnm_train_step.restype = i32
+    L.lnm_train_step.argtypes = [vp, vp, i32, i32, i32, vp, vp, f, f, f, f, vp, vp, sz, vp]
+    L.lnm_trainer_read_params.restype = i32
+    L.lnm_trainer_read_params.argtypes = [vp, vp, sz, vp]
+    L.lnm_trainer_save.restype = i32
+    L.lnm_trainer_save.argtypes = [vp, vp, vp, C.POINTER(i32), sz, vp]
+    L.lnm_trainer_load.restype = i32
+    L.lnm_trainer_load.argtypes = [vp, vp, vp, vp, i32, sz, vp]
+    L.lnm_trainer_infer.restype = i32
+    L.lnm_trainer_infer.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, sz, vp]
+
+
+class Trainer:
+    """fp32 U-Net trained on the GPU by the library's forward/backward kernels."""
+
+    def __init__(self, ctx: Context, levels: int, base: int, params, stream=None):
+        import torch
+
+        L = lib()
+        if not hasattr(L, "_train_sigs_done"):
+            _train_sigs(L)
+            L._train_sigs_done = True
+        self.ctx, self.levels, self.base = ctx, levels, base
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self.n_params = p.size
+        nbytes = int(L.lnm_trainer_state_bytes(levels, base))
+        if nbytes == 0:
+            raise LnmError(LNM_ERR_SHAPE, f"no trainer for levels={levels} base={base}")
+        self.state = torch.empty(nbytes, dtype=torch.uint8, device=torch.device("cuda", ctx.device))
+        h = C.c_void_p()
+        check(L.lnm_trainer_create(ctx.handle, levels, base, p.ctypes.data_as(C.c_void_p), p.size, _ptr(self.state),
+                                   nbytes, _stream(stream), C.byref(h)))
+        self.handle = h
+        self._ws = {}
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.lnm_trainer_destroy(self.handle)
+            self.handle = None
+
+    def workspace(self, B, H, W):
+        import torch
+
+        key = (B, H, W)
+        if key not in self._ws:
+            n = int(lib().lnm_train_workspace_bytes(self.levels, self.base, B, H, W))
+            self._ws[key] = torch.empty(max(n, 1), dtype=torch.uint8, device=self.state.device)
+        return self._ws[key]
+
+    def grad(self, guide, target, stream=None):
+        """(loss tensor [1], gradient tensor [n_params]) for one batch."""
+        import torch
+
+        B, H, W, _ = guide.shape
+        _need(guide, (B, H, W, 3), "guide")
+        _need(target, (B, H, W, 6), "target")
+        loss = torch.empty(1, dtype=torch.float32, device=guide.device)
+        g = torch.empty(self.n_params, dtype=torch.float32, device=guide.device)
+        ws = self.workspace(B, H, W)
+        check(lib().lnm_train_grad(self.ctx.handle, self.handle, B, H, W, _ptr(guide), _ptr(target), _ptr(loss),
+                                   _ptr(g), _ptr(ws), ws.numel(), _stream(stream)))
+        return loss, g
+
+    def step(self, guide, target, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, loss=None, stream=None):
+        import torch
+
+        B, H, W, _ = guide.shape
+        _need(guide, (B, H, W, 3), "guide")
+        _need(target, (B, H, W, 6), "target")
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=guide.device)
+        ws = self.workspace(B, H, W)
+        check(lib().lnm_train_step(self.ctx.handle, self.handle, B, H, W, _ptr(guide), _ptr(target), lr, beta1,
+                                   beta2, eps, _ptr(loss), _ptr(ws), ws.numel(), _stream(stream)))
+        return loss
+
+    def params(self, stream=None) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        check(lib().lnm_trainer_read_params(self.handle, out.ctypes.data_as(C.c_void_p), out.size, _stream(stream)))
+        return out
+
+    def save(self, stream=None) -> dict:
+        m = np.empty(self.n_params, dtype=np.float32)
+        v = np.empty(self.n_params, dtype=np.float32)
+        st = C.c_int32()
+        check(lib().lnm_trainer_save(self.handle, m.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p),
+                                     C.byref(st), self.n_params, _stream(stream)))
+        return {"params": self.params(stream), "m": m, "v": v, "step": st.value, "levels": self.levels,
+                "base": self.base}
+
+    def load(self, ck: dict, stream=None):
+        p = np.ascontiguousarray(ck["params"], dtype=np.float32)
+        m = np.ascontiguousarray(ck["m"], dtype=np.float32)
+        v = np.ascontiguousarray(ck["v"], dtype=np.float32)
+        check(lib().lnm_trainer_load(self.handle, p.ctypes.data_as(C.c_void_p), m.ctypes.data_as(C.c_void_p),
+                                     v.ctypes.data_as(C.c_void_p), int(ck["step"]), self.n_params, _stream(stream)))
+
+    def infer(self, guide, out=None, stream=None):
+        import torch
+
+        B, H, W, _ = guide.shape
+        if out is None:
+            out = torch.empty((B, H, W, 6), dtype=torch.float32, device=guide.device)
+        ws = self.workspace(B, H, W)
+        check(lib().lnm_trainer_infer(self.ctx.handle, self.handle, B, H, W, _ptr(guide), _ptr(out), _ptr(ws),
+                                      ws.numel(), _stream(stream)))
+        return out
+
+
+def save_checkpoint(path, ck: dict):
+    np.savez(path, **{k: np.asarray(v) for k, v in ck.items()})
+
+
+def load_checkpoint(path) -> dict:
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] if z[k].ndim else z[k].item() for k in z.files}

@@ -1,0 +1,245 @@
+"""Continuous-batching frame server for many smoke instances.
+
+Each request asks for the next frame of one smoke instance (its density grid
+stays resident on the device).  The scheduler admits pending requests in
+arrival order as stream slots and HBM budget free up: requests of the same
+view resolution are grouped into a batch, each is marched from its own grid
+and camera, the batch goes through one U-Net call, and each result is shaded
+for its own lights.  Batches are issued on several HIP streams, so work of
+requests that arrive while others run overlaps on the device.  Every kernel
+computes an image from that image's inputs only, in the same order
+regardless of batch composition, so a frame is bit-identical alone and in a
+mix.
+
+The device work is the library's (march, U-Net, shading); this module is
+host-side scheduling, memory accounting and timing.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import time
+
+import numpy as np
+
+from . import lnm
+
+
+@dataclasses.dataclass
+class Instance:
+    """One smoke instance: a resident density grid, its orbit camera and light."""
+    key: int
+    density: object  # torch float32 [n][n][n] on the device
+    res: int
+    sigma_scale: float = 8.0
+    step_voxels: float = 4.0
+    distance: float = 2.5
+    fov_y_deg: float = 60.0
+    deg_per_frame: float = 1.5
+    start_deg: float = 0.0
+    light: tuple = ((0.0, 1.0, 0.0), (1.0, 1.0, 1.0))
+    seed: int = 0
+
+    def camera(self, frame: int):
+        a = math.radians(self.start_deg + self.deg_per_frame * frame)
+        eye = (0.5 + self.distance * math.cos(a), 0.5, 0.5 + self.distance * math.sin(a))
+        return _Cam(lnm.PERSPECTIVE, eye, (0.5, 0.5, 0.5), (0.0, 1.0, 0.0), self.fov_y_deg, 0.8, self.res, self.res)
+
+
+@dataclasses.dataclass
+class _Cam:
+    projection: int
+    eye: tuple
+    target: tuple
+    up: tuple
+    fov_y_deg: float
+    ortho_half_extent: float
+    width: int
+    height: int
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    instance: int
+    frame: int
+    t_arrival: float  # seconds from the start of the run
+    t_admit: float = -1.0
+    t_done: float = -1.0
+    batch: int = -1
+
+
+class Backend:
+    """Issues one batch of requests on one stream; returns a completion handle."""
+
+    def __init__(self, ctx, net, n_streams: int = 4):
+        import torch
+
+        self.ctx, self.net = ctx, net
+        # all streams at the default priority
+        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.keep = {}
+
+    def request_bytes(self, res: int) -> int:
+        """Device bytes one request of this view size occupies while in flight."""
+        return 4 * res * res * (3 + 6 + 4) + self.net.workspace_bytes(1, res, res)
+
+    def launch(self, slot: int, reqs, instances, keep_ids=()):
+        import torch
+
+        st = self.streams[slot]
+        res = instances[reqs[0].instance].res
+        B = len(reqs)
+        with torch.cuda.stream(st):
+            guide = torch.empty((B, res, res, 3), dtype=torch.float32, device="cuda")
+            lm = torch.empty((B, res, res, 6), dtype=torch.float32, device="cuda")
+            rgba = torch.empty((B, res, res, 4), dtype=torch.float32, device="cuda")
+            ws = self.net.workspace(B, res, res)
+            for b, r in enumerate(reqs):
+                inst = instances[r.instance]
+                prm = lnm.make_params(inst.step_voxels, seed=inst.seed, frame=r.frame)
+                self.ctx.march(inst.density, inst.sigma_scale, inst.camera(r.frame), prm, out=guide[b], stream=st)
+            self.net.infer(guide, out=lm, workspace=ws, stream=st)
+            for b, r in enumerate(reqs):
+                inst = instances[r.instance]
+                self.ctx.composite(inst.camera(r.frame), [inst.light], lm[b], guide[b], out=rgba[b], stream=st)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        for b, r in enumerate(reqs):
+            if r.rid in keep_ids:
+                self.keep[r.rid] = (guide[b], lm[b], rgba[b])
+        return ev, (guide, lm, rgba, ws)
+
+    @staticmethod
+    def done(handle) -> bool:
+        return handle[0].query()
+
+
+class Scheduler:
+    """Admission by HBM budget and stream slots, batching by view size."""
+
+    def __init__(self, backend, instances, budget_bytes: int, max_batch: int = 16, clock=time.perf_counter,
+                 keep_ids=()):
+        self.be, self.inst = backend, instances
+        self.budget = int(budget_bytes)
+        self.max_batch = max_batch
+        self.clock = clock
+        self.keep_ids = set(keep_ids)
+        self.in_use = 0
+        self.peak_in_use = 0
+        self.free_slots = list(range(len(getattr(backend, "streams", [0]))))
+        self.inflight = []  # (slot, handle, reqs, bytes)
+        self.done = []
+        self.n_batches = 0
+        self.rejected = []  # requests larger than the whole budget
+        self.failed = []  # (request, error) of batches whose launch failed
+
+    def _admit(self, pending, now):
+        while self.free_slots and pending:
+            res = self.inst[pending[0].instance].res
+            need1 = self.be.request_bytes(res)
+            if need1 > self.budget:  # can never fit
+                self.rejected.append(pending.popleft())
+                continue
+            batch, used = [], 0
+            keep = collections.deque()
+            while pending and len(batch) < self.max_batch:
+                r = pending.popleft()
+                if self.inst[r.instance].res != res:
+                    keep.append(r)
+                    continue
+                nb = self.be.request_bytes(res)
+                if self.in_use + used + nb > self.budget:
+                    keep.append(r)
+                    break
+                batch.append(r)
+                used += nb
+            while keep:
+                pending.appendleft(keep.pop())
+            if not batch:
+                return
+            slot = self.free_slots.pop()
+            for r in batch:
+                r.t_admit = now
+                r.batch = self.n_batches
+            try:
+                handle = self.be.launch(slot, batch, self.inst, self.keep_ids)
+            except (lnm.LnmError, MemoryError, RuntimeError) as e:
+                # the batch never reached the device: release its slot and budget
+                self.free_slots.append(slot)
+                for r in batch:
+                    self.failed.append((r, str(e)))
+                self.n_batches += 1
+                continue
+            self.inflight.append((slot, handle, batch, used))
+            self.in_use += used
+            self.peak_in_use = max(self.peak_in_use, self.in_use)
+            self.n_batches += 1
+
+    def _reap(self, now):
+        still = []
+        for slot, handle, batch, used in self.inflight:
+            if self.be.done(handle):
+                for r in batch:
+                    r.t_done = now
+                self.done.extend(batch)
+                self.in_use -= used
+                self.free_slots.append(slot)
+            else:
+                still.append((slot, handle, batch, used))
+        self.inflight = still
+
+    def run(self, requests, poll_sleep: float = 0.0):
+        """Serve requests (sorted by t_arrival, seconds from start) in real time."""
+        reqs = sorted(requests, key=lambda r: r.t_arrival)
+        pending = collections.deque()
+        t0 = self.clock()
+        i = 0
+        while i < len(reqs) or pending or self.inflight:
+            now = self.clock() - t0
+            while i < len(reqs) and reqs[i].t_arrival <= now:
+                pending.append(reqs[i])
+                i += 1
+            self._reap(now)
+            self._admit(pending, now)
+            if poll_sleep:
+                time.sleep(poll_sleep)
+        return self.stats(self.clock() - t0)
+
+    def stats(self, wall):
+        lat = np.array([r.t_done - r.t_arrival for r in self.done]) * 1e3
+        return {
+            "requests": len(self.done),
+            "rejected": len(self.rejected),
+            "failed": len(self.failed),
+            "batches": self.n_batches,
+            "wall_s": wall,
+            "throughput_fps": len(self.done) / wall if wall > 0 else 0.0,
+            "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
+            "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
+            "mean_batch": len(self.done) / max(self.n_batches, 1),
+            "peak_bytes_in_flight": self.peak_in_use,
+            "budget_bytes": self.budget,
+        }
+
+
+def poisson_requests(n_instances: int, rate_hz: float, duration_s: float, seed: int = 7):
+    """Aggregate Poisson arrivals; each request is the next frame of a
+    uniformly chosen instance."""
+    from synth.rng import substream
+
+    s = substream(seed, "arrivals")
+    n_est = int(rate_hz * duration_s * 1.5) + 16
+    u = s.uniform(2 * n_est).reshape(n_est, 2)
+    gaps = -np.log(1.0 - u[:, 0]) / rate_hz
+    times = np.cumsum(gaps)
+    frames = collections.Counter()
+    out = []
+    for k, (t, v) in enumerate(zip(times, u[:, 1])):
+        if t > duration_s:
+            break
+        inst = int(v * n_instances)
+        out.append(Request(k, inst, frames[inst], float(t)))
+        frames[inst] += 1
+    return out

@@ -214,3 +214,33 @@ def headline(seed: int = 0, res: int = 256) -> Workload:
 def dynamic(seed: int = 0) -> Workload:
     """256^3, 32 moving blobs + noise, sphere obstacle, orbit camera 1024^2, base-48."""
     return Workload("dynamic256_1024px", 256, 32, 0.3, orbit_camera(0), 4.0, 4, 48, seed)
+
+
+def make_volume_torch(n: int, n_blobs: int, seed: int, noise_amp: float = 0.0, frame: int = 0,
+                      obstacle_radius: float | None = None, device="cuda"):
+    """The recipe of make_volume evaluated with torch in fp64 on `device`
+    (same seeded draws; values agree with make_volume to fp64 rounding before
+    the final fp32 cast).  For large serving-scale grids."""
+    import torch
+
+    blobs = draw_blobs(n_blobs, seed)
+    c = torch.as_tensor(_centres(n), device=device)
+    cen = blob_centres_at(blobs, frame)
+    rho = torch.zeros((n, n, n), dtype=torch.float64, device=device)
+    for b in range(len(blobs.radii)):
+        inv = 1.0 / (2.0 * blobs.radii[b] ** 2)
+        gx = torch.exp(-((c - cen[b, 0]) ** 2) * inv)
+        gy = torch.exp(-((c - cen[b, 1]) ** 2) * inv)
+        gz = torch.exp(-((c - cen[b, 2]) ** 2) * inv)
+        rho += blobs.peaks[b] * (gz[:, None, None] * gy[None, :, None] * gx[None, None, :])
+    if noise_amp:
+        s = substream(seed, "noise")
+        noise = torch.zeros_like(rho)
+        for f, a in zip((4, 8, 16), (1.0, 0.5, 0.25)):
+            lat = torch.as_tensor(2.0 * s.uniform((f + 1) ** 3).reshape(f + 1, f + 1, f + 1) - 1.0, device=device)
+            w = torch.as_tensor(_lattice_weights(n, f), device=device)
+            noise += a * torch.einsum("zi,yj,xk,ijk->zyx", w, w, w, lat)
+        rho = torch.clamp(rho * (1.0 + noise_amp * noise / 1.75), min=0.0)
+    if obstacle_radius is not None:
+        rho[torch.as_tensor(sphere_mask((n, n, n), radius=obstacle_radius), device=device)] = 0.0
+    return rho.to(torch.float32).contiguous()

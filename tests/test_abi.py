@@ -1,0 +1,57 @@
+"""The C-ABI library loads and exports what include/lnm.h declares (CPU only;
+no compute calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from synth.weights import n_params
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^LNM_API\s+[^(]*?\b(lnm_\w+)\s*\(", text, flags=re.M))
+    return names
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2604_03748_amd import lnm
+
+    return lnm
+
+
+def test_header_declares_entry_points():
+    d = _declared()
+    for name in ("lnm_march", "lnm_infer", "lnm_frame", "lnm_ctx_create", "lnm_net_create"):
+        assert name in d
+
+
+def test_library_exports_every_declared_symbol(L):
+    lib = L.lib()
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(L.EXPORTS) == _declared()
+
+
+def test_struct_sizes_match_binding(L):
+    lib = L.lib()
+    for i, s in enumerate([L.Volume, L.Camera, L.MarchParams, L.Light]):
+        assert lib.lnm_abi_struct_size(i) == C.sizeof(s)
+    assert lib.lnm_abi_struct_size(99) == 0
+
+
+def test_param_count_and_device_bytes(L):
+    lib = L.lib()
+    for lv, b in ((2, 16), (3, 16), (4, 32), (4, 48)):
+        assert L.param_count(lv, b) == n_params(lv, b)
+        assert lib.lnm_net_device_bytes(lv, b, L.FP32) >= 4 * n_params(lv, b)
+    assert L.param_count(1, 16) == 0  # unsupported depth
+    assert L.param_count(3, 8) == 0  # width not a multiple of 16
+    assert lib.lnm_version().startswith(b"liblnm")

@@ -1,0 +1,88 @@
+"""FP8 (OCP e4m3) form of the U-Net: per-output-channel weight scales,
+per-tensor activation scales calibrated on the fp32 network, fp32
+accumulation on MFMA; error against the fp64 oracle per lightmap channel."""
+import os
+
+import numpy as np
+import pytest
+
+from synth.scene import Camera, PERSPECTIVE, make_volume
+from synth.weights import he_normal_params
+from tests.helpers import log, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+# e4m3 keeps 3 mantissa bits (relative rounding up to 2^-4); the bound on a
+# trained network is three times the bf16 one for the max, 1e-2 for the mean.
+FP8_MAX_ABS = 6e-2
+FP8_MEAN_ABS = 1e-2
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2604_03748_amd import lnm
+
+    return lnm.Context(0)
+
+
+def guides(orc, seeds, res=64):
+    out = []
+    for s in seeds:
+        vol = make_volume(32, 6, s)
+        cam = Camera(PERSPECTIVE, (2.6, 0.4 + 0.05 * (s % 9), 0.3 + 0.1 * (s % 7)), fov_y_deg=40.0, width=res,
+                     height=res)
+        g, _, _ = orc.march(vol, 8.0, cam, 2.0, seed=s)
+        out.append(g)
+    return np.stack(out).astype(np.float32)
+
+
+def calibrated_fp8(ctx, levels, base, params, calib):
+    from paper_2604_03748_amd import lnm
+
+    n32 = lnm.Net(ctx, levels, base, params)
+    amax = np.max([n32.calibrate_amax(to_dev(calib[i: i + 1])) for i in range(len(calib))], axis=0)
+    assert np.all(amax > 0)
+    return lnm.Net(ctx, levels, base, params, precision=lnm.FP8_E4M3, act_scales=amax), amax
+
+
+def per_channel(lm, ref):
+    d = np.abs(lm - ref).reshape(-1, 6)
+    return d.max(axis=0), d.mean(axis=0)
+
+
+def test_fp8_trained_network_on_guiding_maps(ctx, orc):
+    params = np.load(os.path.join(os.path.dirname(__file__), "golden", "trained_L3b16.npy"))
+    calib = guides(orc, range(700, 716))
+    net8, amax = calibrated_fp8(ctx, 3, 16, params, calib)
+    g = guides(orc, range(900, 904))
+    ref, _ = orc.unet_forward(params, 3, 16, g.astype(np.float64))
+    lm = to_host(net8.infer(to_dev(g)))
+    mx, mean = per_channel(lm, ref)
+    log(f"fp8 trained L3b16: activation maxima {np.round(amax, 3).tolist()}")
+    log(f"fp8 trained L3b16: max abs per channel {np.round(mx, 5).tolist()}, mean {np.round(mean, 5).tolist()}")
+    assert np.all(mx <= FP8_MAX_ABS), mx
+    assert np.all(mean <= FP8_MEAN_ABS), mean
+    assert mx.max() > 1e-4  # the fp8 path is really reduced precision
+
+
+def test_fp8_headline_net_reports_error(ctx, orc):
+    """He-normal 4-level base-32 network on guiding-map-like inputs: the error
+    is reported; only gross failures (wrong format or scale) are rejected."""
+    params = he_normal_params(4, 32, seed=7, bias="uniform")
+    calib = guides(orc, range(720, 728), res=64)
+    net8, _ = calibrated_fp8(ctx, 4, 32, params, calib)
+    g = guides(orc, range(910, 912), res=64)
+    ref, _ = orc.unet_forward(params, 4, 32, g.astype(np.float64))
+    lm = to_host(net8.infer(to_dev(g)))
+    mx, mean = per_channel(lm, ref)
+    log(f"fp8 He-init L4b32: max abs per channel {np.round(mx, 4).tolist()}, mean {np.round(mean, 5).tolist()}")
+    assert np.all(mean <= 0.05), mean
+
+
+def test_fp8_requires_scales(ctx):
+    from paper_2604_03748_amd import lnm
+
+    params = he_normal_params(3, 16, seed=0)
+    with pytest.raises(lnm.LnmError) as e:
+        lnm.Net(ctx, 3, 16, params, precision=lnm.FP8_E4M3)
+    assert e.value.status == lnm.LNM_ERR_ARG

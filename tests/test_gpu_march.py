@@ -1,0 +1,110 @@
+"""Parity of the HIP guiding-map march (lnm_march) with the fp64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from synth.scene import Camera, ORTHOGRAPHIC, PERSPECTIVE, dynamic, headline, make_volume, small_ortho
+from tests.helpers import check_march, fp32_ray_allowance, log, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2604_03748_amd import lnm
+
+    return lnm.Context(0)
+
+
+def _run(ctx, vol, ss, cam, step, **kw):
+    from paper_2604_03748_amd import lnm
+
+    p = lnm.make_params(step, depth_tau=kw.get("depth_tau", 0.1), ert_eps=kw.get("ert_eps", 1e-6),
+                        jitter=kw.get("jitter", True), seed=kw.get("seed", 0), frame=kw.get("frame", 0),
+                        quadrature=kw.get("quadrature", 0), light_w=kw.get("light_w", (1.0, 1.0, 1.0)))
+    g = ctx.march(to_dev(vol), ss, cam, p)
+    return to_host(g)
+
+
+def _both(ctx, orc, vol, ss, cam, step, what, stride=1, **kw):
+    log(f"case {what}: grid {vol.shape} image {cam.width}x{cam.height} step {step} {kw}")
+    gg = _run(ctx, vol, ss, cam, step, **kw)
+    gr, m, cnt = orc.march(vol, ss, cam, step, stride=stride, **kw)
+    allow = fp32_ray_allowance(orc, vol, ss, cam, step, stride=stride, **kw)
+    if stride > 1:
+        gg, gr, m, allow = (a[::stride, ::stride] for a in (gg, gr, m, allow))
+    check_march(gg, gr, m, kw.get("depth_tau", 0.1), step / max(vol.shape), what, allow=allow)
+    return gg, gr, cnt
+
+
+def test_small_ortho(ctx, orc):
+    wl = small_ortho()
+    _, gr, cnt = _both(ctx, orc, wl.volume(), 8.0, wl.camera, wl.step_voxels, "ortho32_64px")
+    assert cnt[1] > cnt[0] > 0
+    assert (gr[..., 1] < 0.5).sum() > 100  # the scene is not trivial
+
+
+def test_headline_full_image(ctx, orc):
+    wl = headline()
+    _both(ctx, orc, wl.volume(), 8.0, wl.camera, wl.step_voxels, "persp128_256px")
+
+
+def test_ragged_sizes_oblique_camera(ctx, orc):
+    vol = make_volume((20, 28, 36), 5, 17, noise_amp=0.3)
+    cam = Camera(PERSPECTIVE, (-1.3, 2.1, 1.7), target=(0.55, 0.45, 0.5), up=(0.2, 0.1, 1.0), fov_y_deg=48.0,
+                 width=45, height=37)
+    _both(ctx, orc, vol, 6.0, cam, 1.5, "ragged", seed=5, frame=3)
+    cam_o = Camera(ORTHOGRAPHIC, (0.4, -2.0, 0.7), target=(0.5, 0.5, 0.5), up=(0.0, 0.0, 1.0),
+                   ortho_half_extent=0.8, width=33, height=50)
+    _both(ctx, orc, vol, 6.0, cam_o, 0.75, "ragged_ortho", seed=9)
+
+
+def test_riemann_weights_and_light_mix(ctx, orc):
+    wl = small_ortho()
+    _both(ctx, orc, wl.volume(), 8.0, wl.camera, 2.0, "riemann", quadrature=1, light_w=(0.5, 2.0, 0.0))
+    _both(ctx, orc, wl.volume(), 8.0, wl.camera, 2.0, "top_only", light_w=(0.0, 1.0, 0.0), jitter=False)
+
+
+def test_ert_off_and_dense(ctx, orc):
+    wl = small_ortho()
+    _both(ctx, orc, wl.volume(), 8.0, wl.camera, 2.0, "ert_off", ert_eps=0.0)
+    _, gr, _ = _both(ctx, orc, wl.volume() * 6.0, 8.0, wl.camera, 1.0, "dense")
+    assert (gr[..., 1] == 0.0).sum() > 100  # many rays terminated early
+
+
+def test_empty_volume_and_miss(ctx, orc):
+    wl = small_ortho()
+    g = _run(ctx, np.zeros((32, 32, 32), np.float32), 8.0, wl.camera, 2.0)
+    assert np.all(g[..., 0] == 0) and np.all(g[..., 1] == 1) and np.all(g[..., 2] == 0)
+    away = Camera(PERSPECTIVE, (3.0, 0.5, 0.5), target=(4.0, 0.5, 0.5), width=24, height=24)
+    g = _run(ctx, wl.volume(), 8.0, away, 2.0)
+    assert np.all(g[..., 0] == 0) and np.all(g[..., 1] == 1) and np.all(g[..., 2] == 0)
+
+
+def test_degenerate_view_along_z(ctx, orc):
+    """w parallel to the world z axis: the side lights fall back to w x x."""
+    vol = make_volume(24, 5, 2)
+    cam = Camera(ORTHOGRAPHIC, (0.5, 0.5, 3.0), target=(0.5, 0.5, 0.5), up=(0.0, 1.0, 0.0), width=24, height=24)
+    _both(ctx, orc, vol, 8.0, cam, 1.0, "view_along_z", light_w=(0.0, 1.0, 0.5))
+
+
+def test_tiny_grid_and_image(ctx, orc):
+    vol = np.full((1, 1, 1), 0.7, np.float32)
+    cam = Camera(PERSPECTIVE, (2.0, 0.6, 0.4), width=1, height=1)
+    _both(ctx, orc, vol, 3.0, cam, 0.1, "1voxel_1px")
+    vol2 = make_volume((2, 3, 2), 2, 1)
+    cam2 = Camera(ORTHOGRAPHIC, (0.5, 0.5, 2.5), target=(0.5, 0.5, 0.5), up=(0.0, 1.0, 0.0),
+                  ortho_half_extent=0.6, width=3, height=2)
+    _both(ctx, orc, vol2, 5.0, cam2, 0.5, "2x3x2_3x2px")
+
+
+def test_dynamic_scene_full_size_sampled(ctx, orc):
+    """256^3 grid with the sphere obstacle, 1024^2 orbit view: a 1-in-16
+    pixel lattice is checked against the oracle."""
+    wl = dynamic()
+    vol = wl.volume(frame=37, obstacle_radius=0.15)
+    from synth.scene import orbit_camera
+
+    cam = orbit_camera(37)
+    _both(ctx, orc, vol, 8.0, cam, wl.step_voxels, "dynamic256_1024px_stride16", stride=16, frame=37)
