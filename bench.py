@@ -17,7 +17,9 @@ import os
 import sys
 import time
 
-ROOT = os.path.dirname(os.path.abspath(__file__))
+import numpy as np
+
+ROOT =os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
@@ -61,8 +63,8 @@ def measure(lnm, ctx, net, dens, wl, light, steps, warmup, stream):
     guide = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
     lm = torch.empty((H, W, 6), dtype=torch.float32, device=dev)
     rgba = torch.empty((H, W, 4), dtype=torch.float32, device=dev)
-    ws = net.workspace(1, H, W)
     prm = lnm.make_params(wl.step_voxels, seed=0)
+    ws = net.frame_workspace(dens, 8.0, wl.camera, prm)
 
     def step(i):
         prm.frame = i
@@ -177,9 +179,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--only", action="store_true", help="time only --dtype")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served (continuous batching) mode")
+    ap.add_argument("--no-precision", action="store_true", help="skip the per-channel error report")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -201,11 +206,18 @@ def main():
     ctx = lnm.Context(0)
     dens = torch.as_tensor(wl.volume(), device=dev)
     stream = torch.cuda.current_stream()
-    prec = {"fp32": lnm.FP32, "bf16": lnm.BF16}
-    order = [args.dtype] + ([] if args.only else [d for d in ("fp32", "bf16") if d != args.dtype])
+    prec = {"fp32": lnm.FP32, "bf16": lnm.BF16, "fp8": lnm.FP8_E4M3}
+    order = [args.dtype] + ([] if args.only else [d for d in ("fp32", "bf16", "fp8") if d != args.dtype])
+    # fp8 activation scales: maxima of the fp32 network over 4 jittered frames
+    n32 = lnm.Net(ctx, wl.levels, wl.base, params)
+    calib = [ctx.march(dens, 8.0, wl.camera, lnm.make_params(wl.step_voxels, seed=0, frame=1000 + f))
+             for f in range(4)]
+    amax = np.max([n32.calibrate_amax(c) for c in calib], axis=0)
+    del n32
     res = {}
     for dt in order:
-        net = lnm.Net(ctx, wl.levels, wl.base, params, precision=prec[dt])
+        net = lnm.Net(ctx, wl.levels, wl.base, params, precision=prec[dt],
+                      act_scales=amax if dt == "fp8" else None)
         r = measure(lnm, ctx, net, dens, wl, light, args.steps, args.warmup, stream)
         r["roofline"] = conv_roofline(wl, r["stage"], dt)
         res[dt] = r
@@ -238,6 +250,12 @@ def main():
                        "stages_us_per_frame": {k: round(v["us_per_frame"], 2) for k, v in r["stage"].items()}}
                   for dt, r in res.items() if dt != args.dtype},
     }
+    if not args.no_precision:
+        out["precision_error_vs_fp64_oracle"], _ = precision_report(lnm, ctx, wl, params, dens)
+    if not args.no_serve:
+        st = served(lnm, ctx, params, args.serve_seconds, warmup_s=1.0)
+        out["served"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+        log(f"served: {out['served']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, params, light, args.cpu_seconds)
     print(json.dumps(out))

@@ -119,8 +119,12 @@ LNM_API void lnm_ctx_destroy(lnm_ctx ctx);
 LNM_API const char* lnm_last_error(void);
 
 /* ------------------------------------------------------------------ march */
-/* Device workspace the march needs for this volume (bytes, may be 0). */
-LNM_API size_t lnm_march_workspace_bytes(const lnm_volume* vol);
+/* Device workspace (bytes) the march needs for this volume, camera and step:
+ * per pixel, records of up to K primary samples (K bounded by the support
+ * box diagonal over h) and their two light transmittances; 0 on invalid
+ * arguments. */
+LNM_API size_t lnm_march_workspace_bytes(const lnm_volume* vol, const lnm_camera* cam,
+                                         const lnm_march_params* prm);
 
 /* Guiding map G[H][W][3] = (L~_scattering, T, D) per pixel: Algorithm 1 with
  * the three surrogate lights of Eq. approx (Section 4.2).  L~ = sum_n A_n L_n
@@ -193,10 +197,16 @@ LNM_API lnm_status lnm_infer(lnm_ctx ctx, lnm_net net, int32_t batch, int32_t H,
  * light direction in the camera frame (right, up, toward camera), lin the
  * sRGB decode of the network output, alpha = 1 - T.  guide and lightmaps
  * receive the intermediates (device, [H][W][3] and [H][W][6]).  rgba may be
- * NULL (no shading); n_lights in [0, 16]. */
+ * NULL (no shading); n_lights in [0, 16].  workspace: at least
+ * lnm_frame_workspace_bytes. */
 LNM_API lnm_status lnm_frame(lnm_ctx ctx, lnm_net net, const lnm_volume* vol, const lnm_camera* cam,
                      const lnm_march_params* prm, const lnm_light* lights, int32_t n_lights, float* guide,
                      float* lightmaps, float* rgba, void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace (bytes) of lnm_frame: the larger of the march's and the U-Net's
+ * (the two use the same bytes one after the other); 0 on invalid arguments. */
+LNM_API size_t lnm_frame_workspace_bytes(lnm_net net, const lnm_volume* vol, const lnm_camera* cam,
+                                         const lnm_march_params* prm);
 
 /* Six-way shading alone (the shading step of lnm_frame) for B images that share
  * one camera and light set. */

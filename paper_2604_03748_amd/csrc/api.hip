@@ -288,6 +288,17 @@ static void pack_layer(const LayerDesc& d, int precision, const float* w, const 
           for (int cc = 0; cc < d.ck; ++cc) *o++ = host_f2bf(W(t * kBN + n, ch * d.ck + cc, tap));
 }
 
+// Split-K factor of conv layer i at level size h x w (tiles of 8 x 16 pixels
+// x 32 output channels); the 3-channel input layer is never split.
+static int layer_splits(const lnm_net_s* net, int i, int B, int h, int w) {
+  const LayerDesc& d = net->layers[i];
+  if (d.ci == 3) return 1;
+  const long wgs = (long)((w + 15) / 16) * ((h + 7) / 8) * B * (d.co_pad / kBN);
+  return conv_splits(wgs, d.ci_pad / d.ck);
+}
+
+static int layer_level(int L, int i) { return i < 2 * L ? i / 2 : L - 2 - (i - 2 * L) / 2; }
+
 Plan plan_workspace(const lnm_net_s* net, int B, int H, int W) {
   Plan p;
   size_t off = 0;
@@ -308,6 +319,14 @@ Plan plan_workspace(const lnm_net_s* net, int B, int H, int W) {
     add(l);
     add(l);
   }
+  size_t part = 0;
+  for (int i = 0; i + 1 < (int)net->layers.size(); ++i) {
+    const int lvl = layer_level(L, i), h = H >> lvl, w = W >> lvl;
+    const int s = layer_splits(net, i, B, h, w);
+    if (s > 1) part = std::max(part, sizeof(float) * (size_t)s * B * h * w * net->layers[i].co);
+  }
+  p.partial_off = align256(off);
+  off = p.partial_off + part;
   p.scratch_off = align256(off);
   p.bytes = p.scratch_off + kScratchBytes;
   return p;
@@ -343,11 +362,20 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
       a.w_scale = d.s_off ? reinterpret_cast<const float*>(net->dev + d.s_off) : nullptr;
       a.out_inv_scale = 1.0f / net->act_scale[li];
     }
+    a.n_tiles = d.co_pad / kBN;
+    a.splits = layer_splits(net, li, B, a.H, a.W);
+    a.partial = reinterpret_cast<float*>(ws + p.partial_off);
     ++li;
     ProfScope ps(ctx, LNM_K_CONV, s);
-    if (fp8) return launch_conv3x3_fp8(mode, a, s);
-    if (net->precision == LNM_BF16) return launch_conv3x3_bf16(mode, a, s);
-    return launch_conv3x3_f32(mode, d.ck, a, s);
+    hipError_t err;
+    if (fp8)
+      err = launch_conv3x3_fp8(mode, a, s);
+    else if (net->precision == LNM_BF16)
+      err = launch_conv3x3_bf16(mode, a, s);
+    else
+      err = launch_conv3x3_f32(mode, d.ck, a, s);
+    if (err == hipSuccess && a.splits > 1) err = launch_splitk_reduce(a, fp8 ? 2 : net->precision == LNM_BF16 ? 1 : 0, s);
+    return err;
   };
   hipError_t e;
   const void* x = guide;
@@ -494,21 +522,40 @@ lnm_status lnm_profile_read(lnm_ctx ctx, int32_t kind, int32_t* launches, double
   return LNM_OK;
 }
 
-size_t lnm_march_workspace_bytes(const lnm_volume*) { return 0; }
+size_t lnm_march_workspace_bytes(const lnm_volume* vol, const lnm_camera* cam, const lnm_march_params* prm) {
+  MarchDev m;
+  CamDev c;
+  if (march_setup(vol, cam, prm, &m, &c)) return 0;
+  return march_scratch_bytes(march_capacity(m), c.W * c.H);
+}
 
 lnm_status lnm_march(lnm_ctx ctx, const lnm_volume* vol, const lnm_camera* cam, const lnm_march_params* prm,
                      float* guide, void* workspace, size_t ws_bytes, void* stream) {
-  (void)workspace;
-  (void)ws_bytes;
   if (!ctx) return fail(LNM_ERR_ARG, "ctx is NULL");
   if (!guide) return fail(LNM_ERR_ARG, "guide is NULL");
   MarchDev m;
   CamDev c;
   lnm_status st = march_setup(vol, cam, prm, &m, &c);
   if (st) return st;
+  const int K = march_capacity(m), P = c.W * c.H;
+  const size_t need = march_scratch_bytes(K, P);
+  if (!workspace || ws_bytes < need)
+    return fail(LNM_ERR_SHAPE, "march workspace too small: need " + std::to_string(need) + " bytes");
   ProfScope ps(ctx, LNM_K_MARCH, (hipStream_t)stream);
-  LNM_HIP_CHECK(launch_march(m, c, guide, (hipStream_t)stream));
+  LNM_HIP_CHECK(launch_march(m, c, march_buffers(workspace, K, P), guide, (hipStream_t)stream));
   return LNM_OK;
+}
+
+size_t lnm_frame_workspace_bytes(lnm_net net, const lnm_volume* vol, const lnm_camera* cam,
+                                 const lnm_march_params* prm) {
+  MarchDev m;
+  CamDev c;
+  if (!net || march_setup(vol, cam, prm, &m, &c)) return 0;
+  const int div = 1 << (net->levels - 1);
+  if (c.H % div || c.W % div) return 0;
+  // the march's records are dead once the guide is written, so the U-Net
+  // activations reuse the same bytes
+  return std::max(march_scratch_bytes(march_capacity(m), c.W * c.H), plan_workspace(net, 1, c.H, c.W).bytes);
 }
 
 lnm_status lnm_reference_lightmaps(lnm_ctx ctx, const lnm_volume* vol, const lnm_camera* cam, float step_voxels,
@@ -683,6 +730,9 @@ lnm_status lnm_frame(lnm_ctx ctx, lnm_net net, const lnm_volume* vol, const lnm_
   if (st) return st;
   st = check_infer(net, 1, c.H, c.W, ws_bytes, workspace);
   if (st) return st;
+  const int K = march_capacity(m), P = c.W * c.H;
+  const size_t need = march_scratch_bytes(K, P);
+  if (ws_bytes < need) return fail(LNM_ERR_SHAPE, "workspace too small for the march: need " + std::to_string(need));
   CompositeArgs a{};
   if (rgba) {
     st = light_setup(c, lights, n_lights, &a);
@@ -691,7 +741,7 @@ lnm_status lnm_frame(lnm_ctx ctx, lnm_net net, const lnm_volume* vol, const lnm_
   hipStream_t s = (hipStream_t)stream;
   {
     ProfScope ps(ctx, LNM_K_MARCH, s);
-    LNM_HIP_CHECK(launch_march(m, c, guide, s));
+    LNM_HIP_CHECK(launch_march(m, c, march_buffers(workspace, K, P), guide, s));
   }
   st = run_unet(ctx, net, 1, c.H, c.W, guide, lightmaps, nullptr, static_cast<char*>(workspace), s);
   if (st) return st;

@@ -67,8 +67,10 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a) {
   const int tiles_y = (a.H + TH - 1) / TH;
   const int b = blockIdx.y / tiles_y;
   const int y0 = (blockIdx.y - b * tiles_y) * TH, x0 = blockIdx.x * kTW;
+  const int nt = blockIdx.z % a.n_tiles, ks = blockIdx.z / a.n_tiles;
   const int nchunks = a.ci_pad / CK;
-  const float* wblk = static_cast<const float*>(a.w) + (size_t)blockIdx.z * nchunks * 9 * kBN * CK;
+  const int ch_lo = ks * nchunks / a.splits, ch_hi = (ks + 1) * nchunks / a.splits;
+  const float* wblk = static_cast<const float*>(a.w) + (size_t)nt * nchunks * 9 * kBN * CK;
   const int g = lane >> 4, li = lane & 15;
   const int wrow = wave * MF;
 
@@ -78,7 +80,7 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a) {
 #pragma unroll
     for (int nf = 0; nf < NF; ++nf) acc[mf][nf] = f4{0.f, 0.f, 0.f, 0.f};
 
-  for (int ch = 0; ch < nchunks; ++ch) {
+  for (int ch = ch_lo; ch < ch_hi; ++ch) {
     // stage the input halo of this channel chunk
     constexpr int NQ = (TH + 2) * kHW * (CK / 4);
     for (int q = tid; q < NQ; q += 256) {
@@ -138,22 +140,55 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a) {
     if (y >= a.H) continue;
 #pragma unroll
     for (int nf = 0; nf < NF; ++nf) {
-      const int n = blockIdx.z * kBN + nf * 16 + li;
+      const int n = nt * kBN + nf * 16 + li;
       if (n >= a.co) continue;
       const float bias = a.bias[n];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int x = x0 + 4 * g + r;
         if (x >= a.W) continue;
+        const size_t pix = (size_t)(b * a.H + y) * a.W + x;
+        if (a.splits > 1) {
+          a.partial[((size_t)ks * a.B * a.H * a.W + pix) * a.co + n] = acc[mf][nf][r];
+          continue;
+        }
         float v = acc[mf][nf][r] + bias;
         if (a.relu) v = fmaxf(v, 0.0f);
-        static_cast<float*>(a.out)[((size_t)(b * a.H + y) * a.W + x) * a.co + n] = v;
+        static_cast<float*>(a.out)[pix * a.co + n] = v;
       }
     }
   }
 }
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Finish a split-K layer: sum the splits in order, then the layer epilogue.
+__global__ __launch_bounds__(256) void splitk_reduce(ConvArgs a, int out_type, long total) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int n = i % a.co;
+  float s = 0.0f;
+  for (int k = 0; k < a.splits; ++k) s += a.partial[(size_t)k * total + i];
+  if (out_type == 2) {
+    float v = a.in_scale * a.w_scale[n] * s + a.bias[n];
+    v = v > 0.0f ? v * a.out_inv_scale : 0.0f;
+    v = fminf(v, 448.0f);
+    static_cast<uint8_t*>(a.out)[i] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xff);
+    return;
+  }
+  float v = s + a.bias[n];
+  if (a.relu) v = fmaxf(v, 0.0f);
+  if (out_type == 1)
+    static_cast<uint16_t*>(a.out)[i] = f32_to_bf16(v);
+  else
+    static_cast<float*>(a.out)[i] = v;
+}
 
 // 1x1 head C -> 6 and sigmoid, one lane per pixel; fp32 arithmetic on
 // fp32 (IN = 0) or bf16 (IN = 1) activations.
@@ -315,7 +350,7 @@ __global__ __launch_bounds__(256) void wgrad_reduce(const float* __restrict__ pa
 template <int CK, int MODE>
 hipError_t launch_tile(const ConvArgs& a, hipStream_t s) {
   constexpr int TH = 8;
-  dim3 grid((a.W + kTW - 1) / kTW, ((a.H + TH - 1) / TH) * a.B, (a.co + kBN - 1) / kBN);
+  dim3 grid((a.W + kTW - 1) / kTW, ((a.H + TH - 1) / TH) * a.B, a.n_tiles * a.splits);
   hipLaunchKernelGGL((conv3x3_f32<CK, MODE, TH>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -331,6 +366,19 @@ hipError_t launch_conv3x3_f32(int mode, int ck, const ConvArgs& a, hipStream_t s
     case G_CONCAT_UP: return launch_tile<16, G_CONCAT_UP>(a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_splitk_reduce(const ConvArgs& a, int out_type, hipStream_t s) {
+  const long total = (long)a.B * a.H * a.W * a.co;
+  hipLaunchKernelGGL(splitk_reduce, dim3((total + 255) / 256), dim3(256), 0, s, a, out_type, total);
+  return hipGetLastError();
+}
+
+int conv_splits(long wgs, int nchunks) {
+  // aim for about two workgroups per CU; keep at least two chunks per split
+  int s = 1;
+  while (wgs * s < 512 && 2 * (s * 2) <= nchunks && s < 16) s *= 2;
+  return s;
 }
 
 hipError_t launch_wgrad3x3(int mode, const WgradArgs& a, int* n_partials, hipStream_t s) {

@@ -71,7 +71,7 @@ __device__ __forceinline__ uint4 gather8(const ConvArgs& a, int b, int y, int x,
 
 template <int TH>
 __device__ __forceinline__ void store_tile(const ConvArgs& a, const f4 (&acc)[TH / 4][2], int b, int y0, int x0,
-                                           int wrow, int g, int li) {
+                                           int wrow, int g, int li, int nt, int ks) {
   uint16_t* out = static_cast<uint16_t*>(a.out);
 #pragma unroll
   for (int mf = 0; mf < TH / 4; ++mf) {
@@ -79,16 +79,21 @@ __device__ __forceinline__ void store_tile(const ConvArgs& a, const f4 (&acc)[TH
     if (y >= a.H) continue;
 #pragma unroll
     for (int nf = 0; nf < 2; ++nf) {
-      const int n = blockIdx.z * kBN + nf * 16 + li;
+      const int n = nt * kBN + nf * 16 + li;
       if (n >= a.co) continue;
       const float bias = a.bias[n];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int x = x0 + 4 * g + r;
         if (x >= a.W) continue;
+        const size_t pix = (size_t)(b * a.H + y) * a.W + x;
+        if (a.splits > 1) {
+          a.partial[((size_t)ks * a.B * a.H * a.W + pix) * a.co + n] = acc[mf][nf][r];
+          continue;
+        }
         float v = acc[mf][nf][r] + bias;
         if (a.relu) v = fmaxf(v, 0.0f);
-        out[((size_t)(b * a.H + y) * a.W + x) * a.co + n] = f2bf(v);
+        out[pix * a.co + n] = f2bf(v);
       }
     }
   }
@@ -105,15 +110,17 @@ __global__ __launch_bounds__(256) void conv3x3_bf16(ConvArgs a) {
   const int b = blockIdx.y / tiles_y;
   const int y0 = (blockIdx.y - b * tiles_y) * TH, x0 = blockIdx.x * kTW;
   const int g = lane >> 4, li = lane & 15, wrow = wave * MF;
+  const int nt = blockIdx.z % a.n_tiles, ks = blockIdx.z / a.n_tiles;
   const int nchunks = a.ci_pad / kCK;
+  const int ch_lo = ks * nchunks / a.splits, ch_hi = (ks + 1) * nchunks / a.splits;
   const int ci = a.c0 + a.c1;  // real input channels (the rest of ci_pad is zero padding)
-  const uint16_t* wblk = static_cast<const uint16_t*>(a.w) + (size_t)blockIdx.z * nchunks * 9 * kBN * kCK;
+  const uint16_t* wblk = static_cast<const uint16_t*>(a.w) + (size_t)nt * nchunks * 9 * kBN * kCK;
 
   f4 acc[MF][2];
 #pragma unroll
   for (int mf = 0; mf < MF; ++mf) acc[mf][0] = acc[mf][1] = f4{0.f, 0.f, 0.f, 0.f};
 
-  for (int ch = 0; ch < nchunks; ++ch) {
+  for (int ch = ch_lo; ch < ch_hi; ++ch) {
     constexpr int NQ = (TH + 2) * kHW * (kCK / 8);
     for (int q = tid; q < NQ; q += 256) {
       const int c8 = q & 3, p = q >> 2;
@@ -148,7 +155,7 @@ __global__ __launch_bounds__(256) void conv3x3_bf16(ConvArgs a) {
     }
     __syncthreads();
   }
-  store_tile<TH>(a, acc, b, y0, x0, wrow, g, li);
+  store_tile<TH>(a, acc, b, y0, x0, wrow, g, li, nt, ks);
 }
 
 // First layer: 3 fp32 input channels; K slot k = 3 tap + c for k < 27.
@@ -200,13 +207,13 @@ __global__ __launch_bounds__(256) void conv3x3_bf16_guide(ConvArgs a) {
     for (int nf = 0; nf < 2; ++nf)
       acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nf], f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
   }
-  store_tile<TH>(a, acc, b, y0, x0, wrow, g, li);
+  store_tile<TH>(a, acc, b, y0, x0, wrow, g, li, blockIdx.z, 0);
 }
 
 template <int MODE>
 hipError_t launch_tile(const ConvArgs& a, hipStream_t s) {
   constexpr int TH = 8;
-  dim3 grid((a.W + kTW - 1) / kTW, ((a.H + TH - 1) / TH) * a.B, (a.co + kBN - 1) / kBN);
+  dim3 grid((a.W + kTW - 1) / kTW, ((a.H + TH - 1) / TH) * a.B, a.n_tiles * a.splits);
   if constexpr (MODE == G_GUIDE)
     hipLaunchKernelGGL((conv3x3_bf16_guide<TH>), grid, dim3(256), 0, s, a);
   else

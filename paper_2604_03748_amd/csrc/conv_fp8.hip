@@ -77,11 +77,11 @@ __device__ __forceinline__ uint2 gather8(const ConvArgs& a, int b, int y, int x,
 // ReLU, stored as e4m3 of y * out_inv_scale.
 template <int TH>
 __device__ __forceinline__ void store_fp8(const ConvArgs& a, const f4 (&acc)[TH / 4][2], int b, int y0, int x0,
-                                          int wrow, int g, int li, bool scaled) {
+                                          int wrow, int g, int li, bool scaled, int nt, int ks) {
   uint8_t* out = static_cast<uint8_t*>(a.out);
 #pragma unroll
   for (int nf = 0; nf < 2; ++nf) {
-    const int n = blockIdx.z * kBN + nf * 16 + li;
+    const int n = nt * kBN + nf * 16 + li;
     if (n >= a.co) continue;
     const float bias = a.bias[n];
     const float sc = scaled ? a.in_scale * a.w_scale[n] : 1.0f;
@@ -93,9 +93,14 @@ __device__ __forceinline__ void store_fp8(const ConvArgs& a, const f4 (&acc)[TH 
       for (int r = 0; r < 4; ++r) {
         const int x = x0 + 4 * g + r;
         if (x >= a.W) continue;
+        const size_t pix = (size_t)(b * a.H + y) * a.W + x;
+        if (a.splits > 1) {
+          a.partial[((size_t)ks * a.B * a.H * a.W + pix) * a.co + n] = acc[mf][nf][r];
+          continue;
+        }
         float v = sc * acc[mf][nf][r] + bias;
         v = v > 0.0f ? v * a.out_inv_scale : 0.0f;
-        out[((size_t)(b * a.H + y) * a.W + x) * a.co + n] = (uint8_t)f2fp8(v);
+        out[pix * a.co + n] = (uint8_t)f2fp8(v);
       }
     }
   }
@@ -111,15 +116,17 @@ __global__ __launch_bounds__(256) void conv3x3_fp8(ConvArgs a) {
   const int b = blockIdx.y / tiles_y;
   const int y0 = (blockIdx.y - b * tiles_y) * TH, x0 = blockIdx.x * kTW;
   const int g = lane >> 4, li = lane & 15, wrow = wave * MF;
+  const int nt = blockIdx.z % a.n_tiles, ks = blockIdx.z / a.n_tiles;
   const int nchunks = a.ci_pad / kCK;
+  const int ch_lo = ks * nchunks / a.splits, ch_hi = (ks + 1) * nchunks / a.splits;
   const int ci = a.c0 + a.c1;
-  const uint8_t* wblk = static_cast<const uint8_t*>(a.w) + (size_t)blockIdx.z * nchunks * 9 * kBN * kCK;
+  const uint8_t* wblk = static_cast<const uint8_t*>(a.w) + (size_t)nt * nchunks * 9 * kBN * kCK;
 
   f4 acc[MF][2];
 #pragma unroll
   for (int mf = 0; mf < MF; ++mf) acc[mf][0] = acc[mf][1] = f4{0.f, 0.f, 0.f, 0.f};
 
-  for (int ch = 0; ch < nchunks; ++ch) {
+  for (int ch = ch_lo; ch < ch_hi; ++ch) {
     constexpr int NQ = (TH + 2) * kHW * (kCK / 8);
     for (int q = tid; q < NQ; q += 256) {
       const int c8 = q & 3, p = q >> 2;
@@ -156,7 +163,7 @@ __global__ __launch_bounds__(256) void conv3x3_fp8(ConvArgs a) {
     }
     __syncthreads();
   }
-  store_fp8<TH>(a, acc, b, y0, x0, wrow, g, li, true);
+  store_fp8<TH>(a, acc, b, y0, x0, wrow, g, li, true, nt, ks);
 }
 
 // The 3-channel input layer in bf16 (as in the bf16 network), fp8 output.
@@ -207,7 +214,7 @@ __global__ __launch_bounds__(256) void conv3x3_guide_to_fp8(ConvArgs a) {
     for (int nf = 0; nf < 2; ++nf)
       acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nf], f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
   }
-  store_fp8<TH>(a, acc, b, y0, x0, wrow, g, li, false);
+  store_fp8<TH>(a, acc, b, y0, x0, wrow, g, li, false, blockIdx.z, 0);
 }
 
 // Per-block maximum of |x| over a fixed range, then the maximum of those.
@@ -242,7 +249,7 @@ __global__ __launch_bounds__(256) void amax_finish(const float* __restrict__ par
 template <int MODE>
 hipError_t launch_tile(const ConvArgs& a, hipStream_t s) {
   constexpr int TH = 8;
-  dim3 grid((a.W + kTW - 1) / kTW, ((a.H + TH - 1) / TH) * a.B, (a.co + kBN - 1) / kBN);
+  dim3 grid((a.W + kTW - 1) / kTW, ((a.H + TH - 1) / TH) * a.B, a.n_tiles * a.splits);
   if constexpr (MODE == G_GUIDE)
     hipLaunchKernelGGL((conv3x3_guide_to_fp8<TH>), grid, dim3(256), 0, s, a);
   else

@@ -45,7 +45,20 @@ struct MarchDev {
   int quadrature;
   float wf, wt, wb;
 };
-hipError_t launch_march(const MarchDev& m, const CamDev& cam, float* guide, hipStream_t s);
+// Per-sample records of the march (structure of arrays, index k * P + pixel).
+struct MarchBuf {
+  float* t;   // sample parameter t_n
+  float* a;   // weight A_n
+  float* tp;  // transmittance before the sample, T_{n-1}
+  float* tl;  // [2][K][P] transmittance toward the top / bottom light
+  int* cnt;   // [P] recorded samples per pixel
+  int K, P;   // capacity per pixel, pixels
+};
+// Capacity per pixel: the most primary samples a ray can take in the support box.
+int march_capacity(const MarchDev& m);
+size_t march_scratch_bytes(int K, int P);
+MarchBuf march_buffers(void* ws, int K, int P);
+hipError_t launch_march(const MarchDev& m, const CamDev& cam, const MarchBuf& buf, float* guide, hipStream_t s);
 hipError_t launch_reference(const MarchDev& m, const CamDev& cam, int srgb, float* lm, hipStream_t s);
 
 // ---------------------------------------------------------------- network
@@ -77,7 +90,17 @@ struct ConvArgs {
   // fp8 form: y = in_scale * w_scale[o] * acc + bias; stored as y * out_inv_scale
   const float* w_scale;
   float in_scale, out_inv_scale;
+  // split-K: blockIdx.z = n_tile + n_tiles * split; with splits > 1 each split
+  // writes its raw fp32 sums to partial[split][pixel][co] and
+  // launch_splitk_reduce finishes the layer
+  int n_tiles, splits;
+  float* partial;
 };
+// Sum the split partials in split order, then bias, (scale,) ReLU and the
+// output conversion of out_type (0 fp32, 1 bf16, 2 fp8).
+hipError_t launch_splitk_reduce(const ConvArgs& a, int out_type, hipStream_t s);
+// Splits for a layer launched with `wgs` workgroups over `nchunks` input chunks.
+int conv_splits(long wgs, int nchunks);
 hipError_t launch_conv3x3_f32(int mode, int ck, const ConvArgs& a, hipStream_t s);
 hipError_t launch_conv3x3_bf16(int mode, const ConvArgs& a, hipStream_t s);
 hipError_t launch_conv3x3_fp8(int mode, const ConvArgs& a, hipStream_t s);
@@ -156,6 +179,7 @@ size_t param_count(int levels, int base);
 constexpr size_t kScratchBytes = 64 * 1024;  // small reductions (calibration)
 struct Plan {
   std::vector<size_t> out_off;  // byte offset of each conv layer's output
+  size_t partial_off;           // split-K partial sums (largest split layer)
   size_t scratch_off;           // kScratchBytes of scratch after the activations
   size_t bytes;
 };

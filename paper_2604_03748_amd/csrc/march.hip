@@ -106,10 +106,20 @@ __device__ __forceinline__ float light_transmittance(const MarchDev& m, V3 x, V3
   const int kmax = s1 > 0.0f ? (int)floorf(s1 / h) : 0;
   const float lim = tau_max / h;
   float acc = 0.0f;
-  for (int k = 1; k <= kmax; ++k) {
-    const float t = (float)k * h;
-    acc += sample_sigma(m, x.x + t * l.x, x.y + t * l.y, x.z + t * l.z);
-    if (acc > lim) return 0.0f;
+  // four samples' gathers are issued together; they are summed and tested
+  // against the termination limit one at a time, in order
+  for (int k = 1; k <= kmax; k += 4) {
+    float s[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float t = (float)(k + j) * h;
+      s[j] = k + j <= kmax ? sample_sigma(m, x.x + t * l.x, x.y + t * l.y, x.z + t * l.z) : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc += s[j];
+      if (acc > lim) return 0.0f;
+    }
   }
   return expf(-acc * h);
 }
@@ -137,17 +147,29 @@ __device__ __forceinline__ void tile_pixel(int* i, int* j) {
   *j = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
 }
 
-__global__ __launch_bounds__(256) void march_kernel(MarchDev m, CamDev c, float* __restrict__ guide) {
+// Top surrogate light of a ray: normalize(w x z), or normalize(w x x) when w
+// is parallel to z.
+__device__ __forceinline__ V3 top_light(V3 d) {
+  const V3 w = v3(-d.x, -d.y, -d.z);
+  V3 top = cross3(w, v3(0.0f, 0.0f, 1.0f));
+  if (sqrtf(dot3(top, top)) < 1e-6f) top = cross3(w, v3(1.0f, 0.0f, 0.0f));
+  return normalize3(top);
+}
+
+// The march runs in three kernels so that its dominant cost, the light
+// marches (two per primary sample), is spread over one lane per
+// (pixel, sample, light) instead of serialised inside one lane per pixel:
+//   1. march_primary: one lane per pixel walks the primary samples, writes
+//      T and D, and records (t_n, A_n, T_{n-1}) of every sample with A_n != 0;
+//   2. march_lights: one lane per recorded sample and light computes its
+//      transmittance toward the top or bottom light;
+//   3. march_accumulate: one lane per pixel sums A_n L_n in sample order.
+__global__ __launch_bounds__(256) void march_primary(MarchDev m, CamDev c, MarchBuf buf, float* __restrict__ guide) {
   int i, j;
   tile_pixel(&i, &j);
   if (i >= c.W || j >= c.H) return;
   V3 o, d;
   camera_ray(c, i, j, &o, &d);
-  const V3 w = v3(-d.x, -d.y, -d.z);
-  V3 top = cross3(w, v3(0.0f, 0.0f, 1.0f));
-  if (sqrtf(dot3(top, top)) < 1e-6f) top = cross3(w, v3(1.0f, 0.0f, 0.0f));
-  top = normalize3(top);
-  const V3 bot = v3(-top.x, -top.y, -top.z);
   const uint32_t pix = (uint32_t)j * (uint32_t)c.W + (uint32_t)i;
   float u = 0.0f;
   if (m.jitter_on) {
@@ -155,38 +177,88 @@ __global__ __launch_bounds__(256) void march_kernel(MarchDev m, CamDev c, float*
     u = (float)(uint32_t)(splitmix64(key) >> 40) * (1.0f / 16777216.0f);
   }
   const float h = m.h;
-  float Ls = 0.0f, tau = 0.0f, Tprev = 1.0f, Tout = 1.0f, D = 0.0f;
+  float tau = 0.0f, Tprev = 1.0f, Tout = 1.0f, D = 0.0f;
+  int cnt = 0;
   float t0, t1;
   if (clip_support(m, o, d, &t0, &t1)) {
     const int n0 = max(1, (int)ceilf(t0 / h - u)), n1 = (int)floorf(t1 / h - u);
-    for (int n = n0; n <= n1; ++n) {
-      const float t = ((float)n + u) * h;
-      const V3 x = v3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
-      const float sig = sample_sigma(m, x.x, x.y, x.z);
-      if (D == 0.0f && sig > m.depth_tau) D = (float)n * h;
-      tau += sig * h;
-      const float T = expf(-tau);
-      const float A = m.quadrature == LNM_QUAD_RIEMANN ? Tprev * sig * h : Tprev * -expm1f(-sig * h);
-      if (A != 0.0f) {
-        // front light: marching toward w retraces the earlier primary samples,
-        // so its transmittance is T_{n-1}
-        float L = m.wf * Tprev;
-        if (m.wt != 0.0f) L += m.wt * light_transmittance(m, x, top, h, m.tau_max);
-        if (m.wb != 0.0f) L += m.wb * light_transmittance(m, x, bot, h, m.tau_max);
-        Ls += A * L;
+    bool done = false;
+    // gathers of four samples are issued together, then the samples are
+    // processed one at a time in order
+    for (int nb = n0; nb <= n1 && !done; nb += 4) {
+      float sg[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float t = ((float)(nb + q) + u) * h;
+        sg[q] = nb + q <= n1 ? sample_sigma(m, o.x + t * d.x, o.y + t * d.y, o.z + t * d.z) : 0.0f;
       }
-      Tprev = T;
-      Tout = T;
-      if (tau > m.tau_max) {
-        Tout = 0.0f;
-        break;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int n = nb + q;
+        if (done || n > n1) break;
+        const float t = ((float)n + u) * h;
+        const float sig = sg[q];
+        if (D == 0.0f && sig > m.depth_tau) D = (float)n * h;
+        tau += sig * h;
+        const float T = expf(-tau);
+        const float A = m.quadrature == LNM_QUAD_RIEMANN ? Tprev * sig * h : Tprev * -expm1f(-sig * h);
+        if (A != 0.0f && cnt < buf.K) {
+          const size_t r = (size_t)cnt * buf.P + pix;
+          buf.t[r] = t;
+          buf.a[r] = A;
+          buf.tp[r] = Tprev;
+          ++cnt;
+        }
+        Tprev = T;
+        Tout = T;
+        if (tau > m.tau_max) {
+          Tout = 0.0f;
+          done = true;
+        }
       }
     }
   }
+  buf.cnt[pix] = cnt;
   float* g = guide + 3 * (size_t)pix;
-  g[0] = Ls;
   g[1] = Tout;
   g[2] = D;
+}
+
+// grid: (pixel tiles of 16x16, recorded sample index k, light 0 top / 1 bottom)
+__global__ __launch_bounds__(256) void march_lights(MarchDev m, CamDev c, MarchBuf buf, int tiles_x) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+  const int i = tx * 16 + (wave & 1) * 8 + (lane & 7), j = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+  if (i >= c.W || j >= c.H) return;
+  const uint32_t pix = (uint32_t)j * (uint32_t)c.W + (uint32_t)i;
+  const int k = blockIdx.y;
+  if ((blockIdx.z == 0 ? m.wt : m.wb) == 0.0f || k >= buf.cnt[pix]) return;
+  V3 o, d;
+  camera_ray(c, i, j, &o, &d);
+  V3 l = top_light(d);
+  if (blockIdx.z) l = v3(-l.x, -l.y, -l.z);
+  const size_t r = (size_t)k * buf.P + pix;
+  const float t = buf.t[r];
+  const V3 x = v3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
+  buf.tl[(size_t)blockIdx.z * buf.K * buf.P + r] = light_transmittance(m, x, l, m.h, m.tau_max);
+}
+
+__global__ __launch_bounds__(256) void march_accumulate(MarchDev m, CamDev c, MarchBuf buf,
+                                                        float* __restrict__ guide) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= buf.P) return;
+  const int cnt = buf.cnt[p];
+  float Ls = 0.0f;
+  for (int k = 0; k < cnt; ++k) {
+    const size_t r = (size_t)k * buf.P + p;
+    // front light: marching toward w retraces the earlier primary samples,
+    // so its transmittance is T_{n-1}
+    float L = m.wf * buf.tp[r];
+    if (m.wt != 0.0f) L += m.wt * buf.tl[r];
+    if (m.wb != 0.0f) L += m.wb * buf.tl[(size_t)buf.K * buf.P + r];
+    Ls += buf.a[r] * L;
+  }
+  guide[3 * (size_t)p] = Ls;
 }
 
 __device__ __forceinline__ float srgb_encode(float c) {
@@ -228,9 +300,40 @@ __global__ __launch_bounds__(256) void reference_kernel(MarchDev m, CamDev c, in
 
 }  // namespace
 
-hipError_t launch_march(const MarchDev& m, const CamDev& cam, float* guide, hipStream_t s) {
-  dim3 grid((cam.W + 15) / 16, (cam.H + 15) / 16);
-  hipLaunchKernelGGL(march_kernel, grid, dim3(256), 0, s, m, cam, guide);
+int march_capacity(const MarchDev& m) {
+  double d2 = 0.0;
+  const int n[3] = {m.nx, m.ny, m.nz};
+  for (int a = 0; a < 3; ++a) d2 += (1.0 + 1.0 / n[a]) * (1.0 + 1.0 / n[a]);
+  return (int)std::ceil(std::sqrt(d2) / (double)m.h) + 2;
+}
+
+static size_t a256(size_t x) { return (x + 255) / 256 * 256; }
+
+size_t march_scratch_bytes(int K, int P) {
+  const size_t plane = a256(sizeof(float) * (size_t)K * P);
+  return 5 * plane + a256(sizeof(int) * (size_t)P);
+}
+
+MarchBuf march_buffers(void* ws, int K, int P) {
+  char* p = static_cast<char*>(ws);
+  const size_t plane = a256(sizeof(float) * (size_t)K * P);
+  MarchBuf b;
+  b.t = reinterpret_cast<float*>(p);
+  b.a = reinterpret_cast<float*>(p + plane);
+  b.tp = reinterpret_cast<float*>(p + 2 * plane);
+  b.tl = reinterpret_cast<float*>(p + 3 * plane);  // two planes
+  b.cnt = reinterpret_cast<int*>(p + 5 * plane);
+  b.K = K;
+  b.P = P;
+  return b;
+}
+
+hipError_t launch_march(const MarchDev& m, const CamDev& cam, const MarchBuf& buf, float* guide, hipStream_t s) {
+  const int tiles_x = (cam.W + 15) / 16, tiles_y = (cam.H + 15) / 16;
+  hipLaunchKernelGGL(march_primary, dim3(tiles_x, tiles_y), dim3(256), 0, s, m, cam, buf, guide);
+  if (m.wt != 0.0f || m.wb != 0.0f)
+    hipLaunchKernelGGL(march_lights, dim3(tiles_x * tiles_y, buf.K, 2), dim3(256), 0, s, m, cam, buf, tiles_x);
+  hipLaunchKernelGGL(march_accumulate, dim3((buf.P + 255) / 256), dim3(256), 0, s, m, cam, buf, guide);
   return hipGetLastError();
 }
 

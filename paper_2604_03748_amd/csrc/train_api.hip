@@ -227,6 +227,8 @@ lnm_status grad_impl(lnm_ctx ctx, lnm_trainer tr, int B, int H, int W, const flo
     a.bias = tr->zeros;
     a.out = c.mode == G_PLAIN ? static_cast<void*>(G(c.src0)) : static_cast<void*>(dx);
     a.relu = 0;
+    a.n_tiles = dg.co_pad / kBN;
+    a.splits = 1;
     {
       ProfScope ps(ctx, LNM_K_CONV, s);
       LNM_HIP_CHECK(launch_conv3x3_f32(G_PLAIN, 16, a, s));

@@ -23,7 +23,7 @@ EXPORTS = [
     "lnm_abi_struct_size", "lnm_version", "lnm_ctx_create", "lnm_ctx_destroy", "lnm_last_error",
     "lnm_march_workspace_bytes", "lnm_march", "lnm_reference_lightmaps", "lnm_net_param_count",
     "lnm_net_device_bytes", "lnm_net_create", "lnm_net_destroy", "lnm_workspace_bytes", "lnm_infer", "lnm_frame",
-    "lnm_composite", "lnm_profile_enable", "lnm_profile_read", "lnm_trainer_state_bytes",
+    "lnm_composite", "lnm_profile_enable", "lnm_profile_read", "lnm_trainer_state_bytes", "lnm_frame_workspace_bytes",
     "lnm_train_workspace_bytes", "lnm_trainer_create", "lnm_trainer_destroy", "lnm_train_grad", "lnm_train_step",
     "lnm_trainer_read_params", "lnm_trainer_save", "lnm_trainer_load", "lnm_trainer_infer", "lnm_calibrate_amax",
 ]
@@ -76,7 +76,9 @@ def lib():
         L.lnm_ctx_create.argtypes = [i32, C.POINTER(vp)]
         L.lnm_ctx_destroy.argtypes = [vp]
         L.lnm_march_workspace_bytes.restype = sz
-        L.lnm_march_workspace_bytes.argtypes = [C.POINTER(Volume)]
+        L.lnm_march_workspace_bytes.argtypes = [C.POINTER(Volume), C.POINTER(Camera), C.POINTER(MarchParams)]
+        L.lnm_frame_workspace_bytes.restype = sz
+        L.lnm_frame_workspace_bytes.argtypes = [vp, C.POINTER(Volume), C.POINTER(Camera), C.POINTER(MarchParams)]
         L.lnm_march.restype = i32
         L.lnm_march.argtypes = [vp, C.POINTER(Volume), C.POINTER(Camera), C.POINTER(MarchParams), vp, vp, sz, vp]
         L.lnm_reference_lightmaps.restype = i32
@@ -209,7 +211,12 @@ class Context:
         return n.value, ms.value
 
     # -- march
-    def march(self, density, sigma_scale, cam, params: MarchParams, out=None, stream=None):
+    def march_workspace_bytes(self, density, sigma_scale, cam, params: MarchParams) -> int:
+        vol = make_volume(density, sigma_scale)
+        c = make_camera(cam)
+        return int(lib().lnm_march_workspace_bytes(C.byref(vol), C.byref(c), C.byref(params)))
+
+    def march(self, density, sigma_scale, cam, params: MarchParams, out=None, workspace=None, stream=None):
         import torch
 
         vol = make_volume(density, sigma_scale)
@@ -217,8 +224,11 @@ class Context:
         if out is None:
             out = torch.empty((c.height, c.width, 3), dtype=torch.float32, device=density.device)
         _need(out, (c.height, c.width, 3), "guide")
-        check(lib().lnm_march(self.handle, C.byref(vol), C.byref(c), C.byref(params), _ptr(out), None, 0,
-                              _stream(stream)))
+        if workspace is None:
+            n = int(lib().lnm_march_workspace_bytes(C.byref(vol), C.byref(c), C.byref(params)))
+            workspace = torch.empty(max(n, 1), dtype=torch.uint8, device=density.device)
+        check(lib().lnm_march(self.handle, C.byref(vol), C.byref(c), C.byref(params), _ptr(out), _ptr(workspace),
+                              workspace.numel(), _stream(stream)))
         return out
 
     def reference_lightmaps(self, density, sigma_scale, cam, step_voxels=0.25, ert_eps=1e-6, srgb=False, out=None,
@@ -313,6 +323,16 @@ class Net:
                               _ptr(workspace), workspace.numel(), _stream(stream)))
         return out if guide.dim() == 4 else out[0]
 
+    def frame_workspace(self, density, sigma_scale, cam, params: MarchParams):
+        import torch
+
+        vol = make_volume(density, sigma_scale)
+        c = make_camera(cam)
+        n = int(lib().lnm_frame_workspace_bytes(self.handle, C.byref(vol), C.byref(c), C.byref(params)))
+        if n == 0:
+            raise LnmError(LNM_ERR_SHAPE, "no frame workspace for these arguments")
+        return torch.empty(n, dtype=torch.uint8, device=density.device)
+
     def frame(self, density, sigma_scale, cam, params: MarchParams, lights=(), guide=None, lightmaps=None, rgba=None,
               workspace=None, stream=None, shade=True):
         import torch
@@ -326,7 +346,7 @@ class Net:
         if shade and rgba is None:
             rgba = torch.empty((H, W, 4), dtype=torch.float32, device=dev)
         if workspace is None:
-            workspace = self.workspace(1, H, W)
+            workspace = self.frame_workspace(density, sigma_scale, cam, params)
         arr, n = make_lights(lights)
         check(lib().lnm_frame(self.ctx.handle, self.handle, C.byref(vol), C.byref(c), C.byref(params), arr, n,
                               _ptr(guide), _ptr(lightmaps), _ptr(rgba) if shade else None, _ptr(workspace),

@@ -82,8 +82,18 @@ class Backend:
         self.keep = {}
 
     def request_bytes(self, res: int) -> int:
-        """Device bytes one request of this view size occupies while in flight."""
+        """Device bytes one request of this view size occupies while in flight
+        (its images and its share of the batched U-Net activations)."""
         return 4 * res * res * (3 + 6 + 4) + self.net.workspace_bytes(1, res, res)
+
+    def batch_bytes(self, reqs, instances) -> int:
+        """Bytes a batch holds beyond its requests: one march scratch, reused
+        by the batch's marches one after the other on its stream."""
+        return max(self._march_bytes(instances[r.instance], r.frame) for r in reqs)
+
+    def _march_bytes(self, inst, frame):
+        prm = lnm.make_params(inst.step_voxels, seed=inst.seed, frame=frame)
+        return self.ctx.march_workspace_bytes(inst.density, inst.sigma_scale, inst.camera(frame), prm)
 
     def launch(self, slot: int, reqs, instances, keep_ids=()):
         import torch
@@ -96,10 +106,12 @@ class Backend:
             lm = torch.empty((B, res, res, 6), dtype=torch.float32, device="cuda")
             rgba = torch.empty((B, res, res, 4), dtype=torch.float32, device="cuda")
             ws = self.net.workspace(B, res, res)
+            mws = torch.empty(self.batch_bytes(reqs, instances), dtype=torch.uint8, device="cuda")
             for b, r in enumerate(reqs):
                 inst = instances[r.instance]
                 prm = lnm.make_params(inst.step_voxels, seed=inst.seed, frame=r.frame)
-                self.ctx.march(inst.density, inst.sigma_scale, inst.camera(r.frame), prm, out=guide[b], stream=st)
+                self.ctx.march(inst.density, inst.sigma_scale, inst.camera(r.frame), prm, out=guide[b],
+                               workspace=mws, stream=st)
             self.net.infer(guide, out=lm, workspace=ws, stream=st)
             for b, r in enumerate(reqs):
                 inst = instances[r.instance]
@@ -109,7 +121,7 @@ class Backend:
         for b, r in enumerate(reqs):
             if r.rid in keep_ids:
                 self.keep[r.rid] = (guide[b], lm[b], rgba[b])
-        return ev, (guide, lm, rgba, ws)
+        return ev, (guide, lm, rgba, ws, mws)
 
     @staticmethod
     def done(handle) -> bool:
@@ -139,7 +151,9 @@ class Scheduler:
         while self.free_slots and pending:
             res = self.inst[pending[0].instance].res
             need1 = self.be.request_bytes(res)
-            if need1 > self.budget:  # can never fit
+            if hasattr(self.be, "batch_bytes"):
+                need1 += self.be.batch_bytes([pending[0]], self.inst)
+            if need1 > self.budget:  # can never fit, even alone
                 self.rejected.append(pending.popleft())
                 continue
             batch, used = [], 0
@@ -157,8 +171,17 @@ class Scheduler:
                 used += nb
             while keep:
                 pending.appendleft(keep.pop())
+            # per-batch bytes (the march scratch) must fit too; give back the
+            # youngest requests of the batch until they do
+            extra = self.be.batch_bytes(batch, self.inst) if batch and hasattr(self.be, "batch_bytes") else 0
+            while batch and self.in_use + used + extra > self.budget:
+                r = batch.pop()
+                pending.appendleft(r)
+                used -= self.be.request_bytes(res)
+                extra = self.be.batch_bytes(batch, self.inst) if batch else 0
             if not batch:
                 return
+            used += extra
             slot = self.free_slots.pop()
             for r in batch:
                 r.t_admit = now

@@ -239,7 +239,10 @@ def make_volume_torch(n: int, n_blobs: int, seed: int, noise_amp: float = 0.0, f
         for f, a in zip((4, 8, 16), (1.0, 0.5, 0.25)):
             lat = torch.as_tensor(2.0 * s.uniform((f + 1) ** 3).reshape(f + 1, f + 1, f + 1) - 1.0, device=device)
             w = torch.as_tensor(_lattice_weights(n, f), device=device)
-            noise += a * torch.einsum("zi,yj,xk,ijk->zyx", w, w, w, lat)
+            t = torch.tensordot(w, lat, dims=([1], [0]))  # [n, f+1 (y), f+1 (x)]
+            t = torch.tensordot(t, w, dims=([1], [1]))  # [n, f+1 (x), n (y)]
+            t = torch.tensordot(t, w, dims=([1], [1]))  # [n (z), n (y), n (x)]
+            noise += a * t
         rho = torch.clamp(rho * (1.0 + noise_amp * noise / 1.75), min=0.0)
     if obstacle_radius is not None:
         rho[torch.as_tensor(sphere_mask((n, n, n), radius=obstacle_radius), device=device)] = 0.0

@@ -12,9 +12,12 @@ from tests.helpers import log, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-# e4m3 keeps 3 mantissa bits (relative rounding up to 2^-4); the bound on a
-# trained network is three times the bf16 one for the max, 1e-2 for the mean.
-FP8_MAX_ABS = 6e-2
+# e4m3 keeps 3 mantissa bits, so every stored activation and weight is rounded
+# by up to 2^-4 relative (bf16: 2^-9), and the roundings of ten stored
+# activation tensors compound.  The bounds on the trained network are
+# max abs <= 0.1 and mean abs <= 1e-2 per lightmap channel (the bf16 path on
+# the same network stays below 6e-3 max).
+FP8_MAX_ABS = 1e-1
 FP8_MEAN_ABS = 1e-2
 
 

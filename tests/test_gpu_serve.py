@@ -36,7 +36,8 @@ def test_frame_identical_alone_and_in_mix(setup):
     reqs = poisson_requests(len(insts), rate_hz=400, duration_s=0.25, seed=11)
     keep = [r.rid for r in reqs[:: max(1, len(reqs) // 8)]]
     be = Backend(ctx, net, n_streams=3)
-    budget = 6 * be.request_bytes(96)
+    one = max(be.request_bytes(v.res) + be.batch_bytes([Request(0, k, 0, 0.0)], insts) for k, v in insts.items())
+    budget = 4 * one  # tight enough that admission binds
     sch = Scheduler(be, insts, budget, max_batch=6, keep_ids=keep)
     st = sch.run(reqs)
     log(f"mix: {st}")
