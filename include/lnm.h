@@ -46,6 +46,8 @@ typedef enum { LNM_ORTHOGRAPHIC = 0, LNM_PERSPECTIVE = 1 } lnm_projection;
 /* Weight of sample n in Algorithm 1: ALPHA = T_{n-1} (1 - exp(-sigma_n h)),
  * RIEMANN = T_{n-1} sigma_n h (the algorithm's term with the step length). */
 typedef enum { LNM_QUAD_ALPHA = 0, LNM_QUAD_RIEMANN = 1 } lnm_quadrature;
+/* Side lights of the guiding map (see lnm_march_params). */
+typedef enum { LNM_LIGHTS_TOP_BOTTOM = 0, LNM_LIGHTS_LEFT_RIGHT = 1 } lnm_light_set;
 
 typedef struct lnm_ctx_s* lnm_ctx; /* per-device state: properties, error text */
 typedef struct lnm_net_s* lnm_net; /* host descriptor of a packed network */
@@ -82,9 +84,13 @@ typedef struct {
  * Jitter u = (SplitMix64(jitter_seed ^ (frame << 32) ^ pixel) >> 40) / 2^24,
  * pixel = row * W + column, where SplitMix64(s) is the generator's output for
  * state s (finaliser of s + 0x9E3779B97F4A7C15); u = 0 when jitter_on = 0.
- * light_w = intensities of the front, top and bottom surrogate lights
- * (front = w = -d, top = normalize(w x z), bottom = -top; if w is parallel to
- * z the limit normalize(w x x) is used).  The phase function is isotropic. */
+ * light_w = intensities of the front light and the two side lights
+ * (front = w = -d).  light_set picks the side lights: LNM_LIGHTS_TOP_BOTTOM
+ * (the method's set, Section 4.2) top = normalize(w x z), bottom = -top, with
+ * the limit normalize(w x x) when w is parallel to z; LNM_LIGHTS_LEFT_RIGHT
+ * (the alternative of the guiding-light ablation, Section 5) left =
+ * normalize(w x top), right = -left.  The front-only configuration is
+ * light_w = (1, 0, 0).  The phase function is isotropic. */
 typedef struct {
   float step_voxels;  /* > 0 */
   float depth_tau;    /* >= 0 */
@@ -93,8 +99,8 @@ typedef struct {
   uint64_t jitter_seed;
   uint32_t frame;
   int32_t quadrature; /* lnm_quadrature */
-  float light_w[3];
-  int32_t reserved;   /* must be 0 */
+  float light_w[3];   /* front, first side, second side */
+  int32_t light_set;  /* lnm_light_set */
 } lnm_march_params;   /* 48 bytes */
 
 /* A directional light for six-way shading: dir points toward the light (need
@@ -104,8 +110,26 @@ typedef struct {
   float rgb[3];
 } lnm_light; /* 24 bytes */
 
+/* Light space shared by the obstacle shadow maps (Section 4.5).  A light
+ * with unit direction l (toward the light) gets the orthographic frame
+ * e1 = normalize(a x l), a = +y (+x when |l_y| > 0.99), e2 = l x e1, and
+ * coordinates (u, v, z) = ((p - origin).e1, (p - origin).e2, (p - origin).l).
+ * Its shadow map is size x size texels over u, v in [-half_extent,
+ * half_extent] (texel (i, j) covers u in [-E + 2E i/S, -E + 2E (i+1)/S),
+ * row j likewise in v), each holding the largest z of the obstacle along the
+ * texel centre's light ray (the occluder surface nearest the light), -inf
+ * where there is none.  A smoke point at z is shadowed when its texel holds
+ * a depth greater than z + bias. */
+typedef struct {
+  float origin[3];
+  float half_extent;
+  int32_t size;
+  float bias;
+} lnm_shadow_frame; /* 24 bytes */
+
 /* sizeof of the structs above as compiled into the library, for bindings:
- * which = 0 volume, 1 camera, 2 march params, 3 light; 0 for other values. */
+ * which = 0 volume, 1 camera, 2 march params, 3 light, 4 shadow frame; 0 for
+ * other values. */
 LNM_API size_t lnm_abi_struct_size(int32_t which);
 /* Library version string (static storage). */
 LNM_API const char* lnm_version(void);
@@ -213,6 +237,27 @@ LNM_API size_t lnm_frame_workspace_bytes(lnm_net net, const lnm_volume* vol, con
 LNM_API lnm_status lnm_composite(lnm_ctx ctx, const lnm_camera* cam, const lnm_light* lights, int32_t n_lights,
                          int32_t batch, int32_t H, int32_t W, const float* lightmaps, const float* guide, float* rgba,
                          void* stream);
+
+/* ------------------------------------------------------------ obstacle shadows */
+/* Shadow map (see lnm_shadow_frame) of a sphere obstacle (centre, radius in
+ * world units) for the light direction light_dir[3] (host, need not be unit):
+ * depth[size][size] (device, row v, column u) = c_z + sqrt(r^2 - (u - c_u)^2
+ * - (v - c_v)^2) at texel centres inside the sphere's disc, -inf outside. */
+LNM_API lnm_status lnm_shadow_map_sphere(lnm_ctx ctx, const lnm_shadow_frame* sf, const float* light_dir,
+                                         const float* centre, float radius, float* depth, void* stream);
+
+/* Six-way shading with obstacle shadows (Section 4.5): lnm_composite with
+ * light k's term multiplied by the visibility of each pixel's smoke surface
+ * P = o + D d (the guide's depth channel, ray of the pixel centre) in the
+ * shadow map depth_maps[k] (device [size][size] in the frame sf).
+ * depth_maps is a host array of n_lights device pointers; a NULL array or
+ * entry leaves that light unshadowed, and pixels with D = 0 (no smoke
+ * surface) or outside the map are lit.  vis (device [n_lights][batch][H][W],
+ * optional) receives the visibilities (0 or 1). */
+LNM_API lnm_status lnm_composite_shadowed(lnm_ctx ctx, const lnm_camera* cam, const lnm_light* lights,
+                                          int32_t n_lights, const lnm_shadow_frame* sf, const float* const* depth_maps,
+                                          int32_t batch, int32_t H, int32_t W, const float* lightmaps,
+                                          const float* guide, float* rgba, float* vis, void* stream);
 
 /* ------------------------------------------------------------------ training */
 /* Training of the fp32 network on the GPU (Section 4.4 pixel loss, Section 5

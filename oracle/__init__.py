@@ -53,7 +53,7 @@ def lib():
         L.orc_sigma_vol.argtypes = [_F, C.c_int, C.c_int, C.c_int, C.c_double, _D]
         L.orc_march.restype = C.c_int
         L.orc_march.argtypes = [_F, C.c_int, C.c_int, C.c_int, C.c_double, _D, C.c_double, C.c_double, C.c_double,
-                                C.c_int, C.c_uint64, C.c_uint32, C.c_int, _D, C.c_int, C.c_int, _D, _D,
+                                C.c_int, C.c_uint64, C.c_uint32, C.c_int, _D, C.c_int, C.c_int, C.c_int, _D, _D,
                                 C.POINTER(C.c_longlong)]
         L.orc_front_identity_gap.restype = C.c_double
         L.orc_front_identity_gap.argtypes = [_F, C.c_int, C.c_int, C.c_int, C.c_double, _D, C.c_double, C.c_int,
@@ -76,6 +76,13 @@ def lib():
         L.orc_adam.restype = None
         L.orc_adam.argtypes = [C.c_long, _D, _D, _D, _D, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
         L.orc_num_threads.restype = C.c_int
+        L.orc_shadow_map_sphere.restype = None
+        L.orc_shadow_map_sphere.argtypes = [C.c_int, C.c_double, _D, _D, _D, C.c_double, _D]
+        L.orc_shadow_visibility.restype = None
+        L.orc_shadow_visibility.argtypes = [C.c_int, C.c_int, _D, _D, _D, C.c_int, C.c_double, _D, _D, C.c_double,
+                                            _D, _D]
+        L.orc_composite_shadowed.restype = C.c_int
+        L.orc_composite_shadowed.argtypes = [C.c_int, C.c_int, _D, _D, _D, _D, C.c_int, _D, _D]
         _lib = L
     return _lib
 
@@ -121,7 +128,7 @@ def sigma_at(volume, sigma_scale, p) -> float:
 
 
 def march(volume, sigma_scale, cam, step_voxels, depth_tau=0.1, ert_eps=1e-6, jitter=True, seed=0, frame=0,
-          quadrature=0, light_w=(1.0, 1.0, 1.0), unit_radiance=False, stride=1):
+          quadrature=0, light_w=(1.0, 1.0, 1.0), unit_radiance=False, stride=1, light_set=0):
     """Guiding map [H][W][3] = (L~, T, D), the depth margin [H][W] and
     (primary, secondary) sample counts.  With stride > 1 only pixels on that
     lattice are computed (others stay 0; margin +inf)."""
@@ -131,7 +138,8 @@ def march(volume, sigma_scale, cam, step_voxels, depth_tau=0.1, ert_eps=1e-6, ji
     m = np.full((cam.height, cam.width), np.inf, dtype=np.float64)
     cnt = (C.c_longlong * 2)()
     st = lib().orc_march(_fp(v), nx, ny, nz, sigma_scale, _dp(camera_array(cam)), step_voxels, depth_tau, ert_eps,
-                         int(jitter), seed, frame, quadrature, _dp(_f64(light_w)), int(unit_radiance), int(stride), _dp(g),
+                         int(jitter), seed, frame, quadrature, _dp(_f64(light_w)), int(light_set), int(unit_radiance),
+                         int(stride), _dp(g),
                          _dp(m), cnt)
     if st:
         raise ValueError(f"orc_march status {st}")
@@ -177,6 +185,39 @@ def composite(lightmaps, guide, cam, lights):
                              _dp(out))
     if st:
         raise ValueError(f"orc_composite status {st}")
+    return out
+
+
+def shadow_map_sphere(size, half_extent, origin, light, centre, radius):
+    """[S][S] occluder depths of a sphere seen from a directional light."""
+    out = np.zeros((size, size), dtype=np.float64)
+    lib().orc_shadow_map_sphere(size, half_extent, _dp(_f64(origin)), _dp(_f64(light)), _dp(_f64(centre)), radius,
+                                _dp(out))
+    return out
+
+
+def shadow_visibility(guide, cam, light, depth, half_extent, origin, bias, with_margin=False):
+    """[H][W] visibility in {0, 1} (and, with_margin, the decision margin)."""
+    g = _f64(guide)
+    H, W = g.shape[:2]
+    d = _f64(depth)
+    out = np.zeros((H, W), dtype=np.float64)
+    mg = np.zeros((H, W), dtype=np.float64)
+    lib().orc_shadow_visibility(H, W, _dp(g), _dp(camera_array(cam)), _dp(_f64(light)), d.shape[0], half_extent,
+                                _dp(_f64(origin)), _dp(d), bias, _dp(out), _dp(mg))
+    return (out, mg) if with_margin else out
+
+
+def composite_shadowed(lightmaps, guide, cam, lights, vis):
+    """orc_composite with light k's term multiplied by vis[k] ([n][H][W])."""
+    lm = _f64(lightmaps)
+    H, W = lm.shape[:2]
+    la = _f64(np.array([[*d, *c] for d, c in lights]).reshape(-1, 6))
+    out = np.zeros((H, W, 4), dtype=np.float64)
+    st = lib().orc_composite_shadowed(H, W, _dp(lm), _dp(_f64(guide)), _dp(camera_array(cam)), _dp(la), la.shape[0],
+                                      _dp(_f64(vis)), _dp(out))
+    if st:
+        raise ValueError(f"orc_composite_shadowed status {st}")
     return out
 
 

@@ -10,7 +10,8 @@
  *   - zero-border, cell-centred trilinear sampling of the density grid
  *     (the paper's "3D texture", Section 4.2);
  *   - camera rays, the three surrogate guiding lights front = w,
- *     top = w x z, bottom = -w x z (Section 4.2, Eq. approx);
+ *     top = w x z, bottom = -w x z (Section 4.2, Eq. approx), or the
+ *     left/right pair of the guiding-light ablation (Section 5);
  *   - the coarse-step guiding-map march of Algorithm 1 producing
  *     (L~_scattering, T, D) per pixel, with per-ray jitter;
  *   - fine-step six-way reference lightmaps (training targets standing in for
@@ -176,6 +177,16 @@ static void top_light(const double* w, double* top) {
   v_normalize(top);
 }
 
+/* The ablation's alternative side lights (Section 5, guiding light
+ * directions): left = normalize(w x top), right = -left, i.e. the two
+ * directions perpendicular to both the view and the top/bottom pair. */
+static void left_light(const double* w, double* left) {
+  double top[3];
+  top_light(w, top);
+  v_cross(w, top, left);
+  v_normalize(left);
+}
+
 /* Transmittance from x toward unit direction l through the support box:
  * exp(-h sum_{k>=1} sigma(x + k h l)) over the in-box points, or 0 once the
  * partial optical depth exceeds tau_max. */
@@ -205,12 +216,15 @@ static double light_transmittance(const Vol* v, const double* x, const double* l
  * sum A_n = 1 - T).
  * stride > 1 computes only pixels whose row and column are multiples of it
  * (the others are left untouched), for spot checks of large images.
+ * light_set 0 uses the (top, bottom) side lights, 1 the (left, right) pair;
+ * light_w weighs (front, first side, second side).
  */
 ORC_EXPORT int orc_march(const float* rho, int nx, int ny, int nz, double sigma_scale, const double* cam,
                          double step_voxels, double depth_tau, double ert_eps, int jitter_on, uint64_t jitter_seed,
-                         uint32_t frame, int quadrature, const double* light_w, int unit_radiance, int stride,
-                         double* guide, double* d_margin, long long* counters) {
-  if (!rho || !cam || !guide || nx < 1 || ny < 1 || nz < 1 || step_voxels <= 0.0 || ert_eps < 0.0 || stride < 1)
+                         uint32_t frame, int quadrature, const double* light_w, int light_set, int unit_radiance,
+                         int stride, double* guide, double* d_margin, long long* counters) {
+  if (!rho || !cam || !guide || nx < 1 || ny < 1 || nz < 1 || step_voxels <= 0.0 || ert_eps < 0.0 || stride < 1 ||
+      light_set < 0 || light_set > 1)
     return 1;
   Vol v = {rho, nx, ny, nz, sigma_scale};
   Cam k;
@@ -226,7 +240,10 @@ ORC_EXPORT int orc_march(const float* rho, int nx, int ny, int nz, double sigma_
       double o[3], d[3], w[3], top[3], bot[3];
       cam_ray(&k, i, j, o, d);
       for (int a = 0; a < 3; ++a) w[a] = -d[a];
-      top_light(w, top);
+      if (light_set == 1)
+        left_light(w, top); /* the side pair is then (left, right) */
+      else
+        top_light(w, top);
       for (int a = 0; a < 3; ++a) bot[a] = -top[a];
       uint32_t pix = (uint32_t)j * (uint32_t)k.W + (uint32_t)i;
       double u = jitter_on ? orc_jitter(jitter_seed, frame, pix) : 0.0;
@@ -406,6 +423,99 @@ ORC_EXPORT int orc_composite(int H, int W, const double* lm, const double* guide
     rgba[4 * p + 0] = rgb[0]; rgba[4 * p + 1] = rgb[1]; rgba[4 * p + 2] = rgb[2];
     rgba[4 * p + 3] = 1.0 - guide[3 * p + 1];
   }
+  return 0;
+}
+
+/* ------------------------------------------------------- obstacle shadows */
+/*
+ * Depth-based screen-space obstacle shadowing (Section 4.5).  A directional
+ * light with unit direction l (toward the light) gets an orthographic
+ * light space: e1 = normalize(a x l) with a = y (x when |l . y| > 0.99),
+ * e2 = l x e1, coordinates (u, v, z) = ((p - origin) . e1, . e2, . l).  Its
+ * shadow map is an S x S grid over u, v in [-E, E] storing the largest z of
+ * the obstacle along each texel centre's light ray (the occluder surface
+ * nearest the light), -inf where the obstacle is absent.  A pixel's smoke
+ * surface point P = o + D d (D from the guiding map; no surface when D = 0)
+ * is shadowed when the texel containing (u, v) holds an occluder depth
+ * greater than z(P) + bias.
+ */
+static void light_basis(const double* l, double* e1, double* e2) {
+  double a[3] = {0, 1, 0};
+  if (fabs(l[1]) > 0.99) { a[0] = 1; a[1] = 0; }
+  v_cross(a, l, e1);
+  v_normalize(e1);
+  v_cross(l, e1, e2);
+}
+
+/* shadow map of a sphere (centre, radius): depth[j][i] over u (i) and v (j) */
+ORC_EXPORT void orc_shadow_map_sphere(int S, double E, const double* origin, const double* light, const double* centre,
+                                      double radius, double* depth) {
+  double l[3] = {light[0], light[1], light[2]}, e1[3], e2[3], c[3];
+  v_normalize(l);
+  light_basis(l, e1, e2);
+  v_sub(centre, origin, c);
+  const double cu = v_dot(c, e1), cv = v_dot(c, e2), cz = v_dot(c, l);
+  for (int j = 0; j < S; ++j)
+    for (int i = 0; i < S; ++i) {
+      const double u = -E + 2.0 * E * (i + 0.5) / S, v = -E + 2.0 * E * (j + 0.5) / S;
+      const double q = radius * radius - (u - cu) * (u - cu) - (v - cv) * (v - cv);
+      depth[(size_t)j * S + i] = q >= 0.0 ? cz + sqrt(q) : -INFINITY;
+    }
+}
+
+/* visibility[H][W] in {0, 1} of each pixel's smoke surface for one light.
+ * margin (optional, [H][W]) receives how far the decision is from flipping,
+ * in world units: the smaller of the distance of (u, v) to the nearest texel
+ * edge and |occluder depth - (z + bias)|; +inf where D = 0. */
+ORC_EXPORT void orc_shadow_visibility(int H, int W, const double* guide, const double* cam, const double* light, int S,
+                                      double E, const double* origin, const double* depth, double bias,
+                                      double* vis, double* margin) {
+  Cam k;
+  cam_setup(cam, &k);
+  double l[3] = {light[0], light[1], light[2]}, e1[3], e2[3];
+  v_normalize(l);
+  light_basis(l, e1, e2);
+  const double texel = 2.0 * E / S;
+  for (int j = 0; j < H; ++j)
+    for (int i = 0; i < W; ++i) {
+      const size_t p = (size_t)j * W + i;
+      const double D = guide[3 * p + 2];
+      double v = 1.0, mg = INFINITY;
+      if (D > 0.0) {
+        double o[3], d[3], P[3], q[3];
+        cam_ray(&k, i, j, o, d);
+        for (int a = 0; a < 3; ++a) P[a] = o[a] + D * d[a];
+        v_sub(P, origin, q);
+        const double u = v_dot(q, e1), w = v_dot(q, e2), z = v_dot(q, l);
+        const double su = (u + E) / (2.0 * E) * S, sw = (w + E) / (2.0 * E) * S;
+        const int ti = (int)floor(su), tj = (int)floor(sw);
+        mg = fmin(fabs(su - nearbyint(su)), fabs(sw - nearbyint(sw))) * texel;
+        if (ti >= 0 && ti < S && tj >= 0 && tj < S) {
+          const double occ = depth[(size_t)tj * S + ti];
+          if (occ > z + bias) v = 0.0;
+          if (isfinite(occ)) mg = fmin(mg, fabs(occ - (z + bias)));
+        }
+      }
+      vis[p] = v;
+      if (margin) margin[p] = mg;
+    }
+}
+
+/* Shading of orc_composite with each light's term multiplied by its
+ * visibility (vis[n_lights][H][W]). */
+ORC_EXPORT int orc_composite_shadowed(int H, int W, const double* lm, const double* guide, const double* cam,
+                                      const double* lights, int n_lights, const double* vis, double* rgba) {
+  if (n_lights > 16) return 1;
+  for (int q = 0; q < n_lights; ++q) {
+    double* one = malloc(sizeof(double) * (size_t)H * W * 4);
+    orc_composite(H, W, lm, guide, cam, lights + 6 * q, 1, one);
+    for (size_t p = 0; p < (size_t)H * W; ++p) {
+      for (int c = 0; c < 3; ++c) rgba[4 * p + c] = (q ? rgba[4 * p + c] : 0.0) + vis[(size_t)q * H * W + p] * one[4 * p + c];
+      rgba[4 * p + 3] = one[4 * p + 3];
+    }
+    free(one);
+  }
+  if (n_lights == 0) orc_composite(H, W, lm, guide, cam, lights, 0, rgba);
   return 0;
 }
 

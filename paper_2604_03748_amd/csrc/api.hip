@@ -98,7 +98,8 @@ static lnm_status march_setup(const lnm_volume* vol, const lnm_camera* cam, cons
   if (prm->quadrature != LNM_QUAD_ALPHA && prm->quadrature != LNM_QUAD_RIEMANN)
     return fail(LNM_ERR_ARG, "params.quadrature");
   if (!finite3(prm->light_w)) return fail(LNM_ERR_ARG, "params.light_w must be finite");
-  if (prm->reserved != 0) return fail(LNM_ERR_ARG, "params.reserved must be 0");
+  if (prm->light_set != LNM_LIGHTS_TOP_BOTTOM && prm->light_set != LNM_LIGHTS_LEFT_RIGHT)
+    return fail(LNM_ERR_ARG, "params.light_set");
   const int nmax = std::max(vol->nx, std::max(vol->ny, vol->nz));
   m->rho = vol->density;
   m->nx = vol->nx;
@@ -115,6 +116,9 @@ static lnm_status march_setup(const lnm_volume* vol, const lnm_camera* cam, cons
   m->wf = prm->light_w[0];
   m->wt = prm->light_w[1];
   m->wb = prm->light_w[2];
+  m->light_set = prm->light_set;
+  m->brick = nullptr;  // set by launch_march from its scratch
+  m->nbx = m->nby = m->nbz = 0;
   return LNM_OK;
 }
 
@@ -462,6 +466,7 @@ size_t lnm_abi_struct_size(int32_t which) {
     case 1: return sizeof(lnm_camera);
     case 2: return sizeof(lnm_march_params);
     case 3: return sizeof(lnm_light);
+    case 4: return sizeof(lnm_shadow_frame);
     default: return 0;
   }
 }
@@ -526,7 +531,7 @@ size_t lnm_march_workspace_bytes(const lnm_volume* vol, const lnm_camera* cam, c
   MarchDev m;
   CamDev c;
   if (march_setup(vol, cam, prm, &m, &c)) return 0;
-  return march_scratch_bytes(march_capacity(m), c.W * c.H);
+  return march_scratch_bytes(m, march_capacity(m), c.W * c.H);
 }
 
 lnm_status lnm_march(lnm_ctx ctx, const lnm_volume* vol, const lnm_camera* cam, const lnm_march_params* prm,
@@ -538,11 +543,11 @@ lnm_status lnm_march(lnm_ctx ctx, const lnm_volume* vol, const lnm_camera* cam, 
   lnm_status st = march_setup(vol, cam, prm, &m, &c);
   if (st) return st;
   const int K = march_capacity(m), P = c.W * c.H;
-  const size_t need = march_scratch_bytes(K, P);
+  const size_t need = march_scratch_bytes(m, K, P);
   if (!workspace || ws_bytes < need)
     return fail(LNM_ERR_SHAPE, "march workspace too small: need " + std::to_string(need) + " bytes");
   ProfScope ps(ctx, LNM_K_MARCH, (hipStream_t)stream);
-  LNM_HIP_CHECK(launch_march(m, c, march_buffers(workspace, K, P), guide, (hipStream_t)stream));
+  LNM_HIP_CHECK(launch_march(m, c, march_buffers(workspace, m, K, P), guide, (hipStream_t)stream));
   return LNM_OK;
 }
 
@@ -555,7 +560,7 @@ size_t lnm_frame_workspace_bytes(lnm_net net, const lnm_volume* vol, const lnm_c
   if (c.H % div || c.W % div) return 0;
   // the march's records are dead once the guide is written, so the U-Net
   // activations reuse the same bytes
-  return std::max(march_scratch_bytes(march_capacity(m), c.W * c.H), plan_workspace(net, 1, c.H, c.W).bytes);
+  return std::max(march_scratch_bytes(m, march_capacity(m), c.W * c.H), plan_workspace(net, 1, c.H, c.W).bytes);
 }
 
 lnm_status lnm_reference_lightmaps(lnm_ctx ctx, const lnm_volume* vol, const lnm_camera* cam, float step_voxels,
@@ -719,6 +724,88 @@ lnm_status lnm_composite(lnm_ctx ctx, const lnm_camera* cam, const lnm_light* li
   return LNM_OK;
 }
 
+// Light space of the shadow maps, in fp64 then rounded once.
+static void light_frame(const float* dir, float e1[3], float e2[3], float lw[3]) {
+  double l[3] = {dir[0], dir[1], dir[2]};
+  const double n = std::sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
+  for (double& x : l) x /= n;
+  const double a[3] = {std::fabs(l[1]) > 0.99 ? 1.0 : 0.0, std::fabs(l[1]) > 0.99 ? 0.0 : 1.0, 0.0};
+  double u[3] = {a[1] * l[2] - a[2] * l[1], a[2] * l[0] - a[0] * l[2], a[0] * l[1] - a[1] * l[0]};
+  const double un = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  for (double& x : u) x /= un;
+  const double v[3] = {l[1] * u[2] - l[2] * u[1], l[2] * u[0] - l[0] * u[2], l[0] * u[1] - l[1] * u[0]};
+  for (int q = 0; q < 3; ++q) {
+    e1[q] = (float)u[q];
+    e2[q] = (float)v[q];
+    lw[q] = (float)l[q];
+  }
+}
+
+static lnm_status check_shadow_frame(const lnm_shadow_frame* sf) {
+  if (!sf) return fail(LNM_ERR_ARG, "shadow frame is NULL");
+  if (!finite3(sf->origin)) return fail(LNM_ERR_ARG, "shadow frame origin must be finite");
+  if (!(sf->half_extent > 0.0f) || !std::isfinite(sf->half_extent))
+    return fail(LNM_ERR_ARG, "shadow frame half_extent must be > 0");
+  if (sf->size < 1 || sf->size > 16384) return fail(LNM_ERR_SHAPE, "shadow frame size must be in [1, 16384]");
+  if (!std::isfinite(sf->bias)) return fail(LNM_ERR_ARG, "shadow frame bias must be finite");
+  return LNM_OK;
+}
+
+static bool nonzero3(const float* v) { return v[0] != 0.0f || v[1] != 0.0f || v[2] != 0.0f; }
+
+lnm_status lnm_shadow_map_sphere(lnm_ctx ctx, const lnm_shadow_frame* sf, const float* light_dir, const float* centre,
+                                 float radius, float* depth, void* stream) {
+  if (!ctx || !light_dir || !centre || !depth) return fail(LNM_ERR_ARG, "NULL argument");
+  lnm_status st = check_shadow_frame(sf);
+  if (st) return st;
+  if (!finite3(light_dir) || !nonzero3(light_dir)) return fail(LNM_ERR_ARG, "light_dir must be finite and nonzero");
+  if (!finite3(centre) || !(radius >= 0.0f) || !std::isfinite(radius))
+    return fail(LNM_ERR_ARG, "centre must be finite and radius >= 0");
+  float e1[3], e2[3], lw[3];
+  light_frame(light_dir, e1, e2, lw);
+  double c[3];
+  for (int q = 0; q < 3; ++q) c[q] = (double)centre[q] - sf->origin[q];
+  auto dotd = [&](const float* e) { return c[0] * e[0] + c[1] * e[1] + c[2] * e[2]; };
+  ProfScope ps(ctx, LNM_K_COMPOSITE, (hipStream_t)stream);
+  LNM_HIP_CHECK(launch_shadow_map_sphere(sf->size, sf->half_extent, (float)dotd(e1), (float)dotd(e2), (float)dotd(lw),
+                                         radius * radius, depth, (hipStream_t)stream));
+  return LNM_OK;
+}
+
+lnm_status lnm_composite_shadowed(lnm_ctx ctx, const lnm_camera* cam, const lnm_light* lights, int32_t n_lights,
+                                  const lnm_shadow_frame* sf, const float* const* depth_maps, int32_t batch, int32_t H,
+                                  int32_t W, const float* lightmaps, const float* guide, float* rgba, float* vis,
+                                  void* stream) {
+  if (!ctx || !cam || !lightmaps || !guide || !rgba) return fail(LNM_ERR_ARG, "NULL argument");
+  if (batch < 1 || H < 1 || W < 1) return fail(LNM_ERR_SHAPE, "batch, H and W must be >= 1");
+  if ((long)batch * H * W > INT32_MAX / 4) return fail(LNM_ERR_SHAPE, "too many pixels");
+  lnm_status st = check_shadow_frame(sf);
+  if (st) return st;
+  ShadowArgs a{};
+  std::string why;
+  if (!make_cam(*cam, &a.cam, &why)) return fail(LNM_ERR_ARG, why);
+  if (a.cam.W != W || a.cam.H != H) return fail(LNM_ERR_SHAPE, "H and W must match the camera's size");
+  st = light_setup(a.cam, lights, n_lights, &a.c);
+  if (st) return st;
+  for (int k = 0; k < n_lights; ++k) {
+    a.depth[k] = depth_maps ? depth_maps[k] : nullptr;
+    if (a.depth[k] && !nonzero3(lights[k].dir)) return fail(LNM_ERR_ARG, "a shadowed light needs a nonzero direction");
+    if (a.depth[k]) light_frame(lights[k].dir, a.e1[k], a.e2[k], a.lw[k]);
+  }
+  for (int q = 0; q < 3; ++q) a.origin[q] = sf->origin[q];
+  a.E = sf->half_extent;
+  a.S = sf->size;
+  a.bias = sf->bias;
+  a.c.lm = lightmaps;
+  a.c.guide = guide;
+  a.c.rgba = rgba;
+  a.c.P = batch * H * W;
+  a.vis = vis;
+  ProfScope ps(ctx, LNM_K_COMPOSITE, (hipStream_t)stream);
+  LNM_HIP_CHECK(launch_composite_shadowed(a, (hipStream_t)stream));
+  return LNM_OK;
+}
+
 lnm_status lnm_frame(lnm_ctx ctx, lnm_net net, const lnm_volume* vol, const lnm_camera* cam,
                      const lnm_march_params* prm, const lnm_light* lights, int32_t n_lights, float* guide,
                      float* lightmaps, float* rgba, void* workspace, size_t ws_bytes, void* stream) {
@@ -731,7 +818,7 @@ lnm_status lnm_frame(lnm_ctx ctx, lnm_net net, const lnm_volume* vol, const lnm_
   st = check_infer(net, 1, c.H, c.W, ws_bytes, workspace);
   if (st) return st;
   const int K = march_capacity(m), P = c.W * c.H;
-  const size_t need = march_scratch_bytes(K, P);
+  const size_t need = march_scratch_bytes(m, K, P);
   if (ws_bytes < need) return fail(LNM_ERR_SHAPE, "workspace too small for the march: need " + std::to_string(need));
   CompositeArgs a{};
   if (rgba) {
@@ -741,7 +828,7 @@ lnm_status lnm_frame(lnm_ctx ctx, lnm_net net, const lnm_volume* vol, const lnm_
   hipStream_t s = (hipStream_t)stream;
   {
     ProfScope ps(ctx, LNM_K_MARCH, s);
-    LNM_HIP_CHECK(launch_march(m, c, march_buffers(workspace, K, P), guide, s));
+    LNM_HIP_CHECK(launch_march(m, c, march_buffers(workspace, m, K, P), guide, s));
   }
   st = run_unet(ctx, net, 1, c.H, c.W, guide, lightmaps, nullptr, static_cast<char*>(workspace), s);
   if (st) return st;

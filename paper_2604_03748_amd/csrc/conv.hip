@@ -60,8 +60,10 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a) {
   constexpr int NF = kBN / 16;
   constexpr int MF = TH / 4;
   constexpr int PIN = Pad<CK>::in, PW = Pad<CK>::w;
-  __shared__ __attribute__((aligned(16))) float s_in[(TH + 2) * kHW * PIN];
-  __shared__ __attribute__((aligned(16))) float s_w[9 * kBN * PW];
+  // two LDS buffers: the next chunk is fetched into registers while the
+  // matrix cores work on the current one
+  __shared__ __attribute__((aligned(16))) float s_in[2][(TH + 2) * kHW * PIN];
+  __shared__ __attribute__((aligned(16))) float s_w[2][9 * kBN * PW];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tiles_y = (a.H + TH - 1) / TH;
@@ -80,25 +82,51 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a) {
 #pragma unroll
     for (int nf = 0; nf < NF; ++nf) acc[mf][nf] = f4{0.f, 0.f, 0.f, 0.f};
 
+  // per chunk: the (TH+2) x 18 input halo and the weight slab [tap][n][c]
+  constexpr int NQ = (TH + 2) * kHW * (CK / 4), NW = 9 * kBN * CK / 4;
+  constexpr int RQ = (NQ + 255) / 256, RW = (NW + 255) / 256;
+  f4 rq[RQ], rw[RW];
+#define LNM_FETCH(CH)                                                                          \
+  do {                                                                                         \
+    _Pragma("unroll") for (int r = 0; r < RQ; ++r) {                                           \
+      const int q = tid + 256 * r;                                                             \
+      f4 v = f4{0.f, 0.f, 0.f, 0.f};                                                           \
+      if (q < NQ) {                                                                            \
+        const int c4 = q % (CK / 4), p = q / (CK / 4);                                         \
+        const int y = y0 + p / kHW - 1, x = x0 + p % kHW - 1;                                  \
+        if (y >= 0 && y < a.H && x >= 0 && x < a.W) v = gather4<MODE>(a, b, y, x, (CH) * CK + 4 * c4); \
+      }                                                                                        \
+      rq[r] = v;                                                                               \
+    }                                                                                          \
+    const float* wsrc = wblk + (size_t)(CH) * 9 * kBN * CK;                                    \
+    _Pragma("unroll") for (int r = 0; r < RW; ++r) {                                           \
+      const int q = tid + 256 * r;                                                             \
+      if (q < NW) rw[r] = *reinterpret_cast<const f4*>(wsrc + 4 * q);                          \
+    }                                                                                          \
+  } while (0)
+#define LNM_COMMIT(BUF)                                                                        \
+  do {                                                                                         \
+    _Pragma("unroll") for (int r = 0; r < RQ; ++r) {                                           \
+      const int q = tid + 256 * r;                                                             \
+      if (q < NQ) *reinterpret_cast<f4*>(&s_in[BUF][(q / (CK / 4)) * PIN + 4 * (q % (CK / 4))]) = rq[r]; \
+    }                                                                                          \
+    _Pragma("unroll") for (int r = 0; r < RW; ++r) {                                           \
+      const int q = tid + 256 * r;                                                             \
+      if (q < NW) *reinterpret_cast<f4*>(&s_w[BUF][(q / (CK / 4)) * PW + 4 * (q % (CK / 4))]) = rw[r]; \
+    }                                                                                          \
+  } while (0)
+
+  if (ch_lo < ch_hi) {
+    LNM_FETCH(ch_lo);
+    LNM_COMMIT(0);
+  }
+  __syncthreads();
   for (int ch = ch_lo; ch < ch_hi; ++ch) {
-    // stage the input halo of this channel chunk
-    constexpr int NQ = (TH + 2) * kHW * (CK / 4);
-    for (int q = tid; q < NQ; q += 256) {
-      const int c4 = q % (CK / 4), p = q / (CK / 4);
-      const int hx = p % kHW, hy = p / kHW;
-      const int y = y0 + hy - 1, x = x0 + hx - 1;
-      f4 v = f4{0.f, 0.f, 0.f, 0.f};
-      if (y >= 0 && y < a.H && x >= 0 && x < a.W) v = gather4<MODE>(a, b, y, x, ch * CK + 4 * c4);
-      *reinterpret_cast<f4*>(&s_in[p * PIN + 4 * c4]) = v;
-    }
-    // stage the weight slab [tap][n][c] of this chunk
-    const float* wsrc = wblk + (size_t)ch * 9 * kBN * CK;
-    constexpr int NW = 9 * kBN * CK / 4;
-    for (int q = tid; q < NW; q += 256) {
-      const int c4 = q % (CK / 4), row = q / (CK / 4);
-      *reinterpret_cast<f4*>(&s_w[row * PW + 4 * c4]) = *reinterpret_cast<const f4*>(wsrc + 4 * q);
-    }
-    __syncthreads();
+    const int cur = (ch - ch_lo) & 1;
+    const bool more = ch + 1 < ch_hi;
+    if (more) LNM_FETCH(ch + 1);
+    const float* si = s_in[cur];
+    const float* sw = s_w[cur];
 #pragma unroll 1
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3, dx = tap - 3 * (tap / 3);
@@ -106,10 +134,10 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a) {
         f4 av[MF], bv[NF];
 #pragma unroll
         for (int mf = 0; mf < MF; ++mf)
-          av[mf] = *reinterpret_cast<const f4*>(&s_in[((wrow + mf + dy) * kHW + li + dx) * PIN + 4 * g]);
+          av[mf] = *reinterpret_cast<const f4*>(&si[((wrow + mf + dy) * kHW + li + dx) * PIN + 4 * g]);
 #pragma unroll
         for (int nf = 0; nf < NF; ++nf)
-          bv[nf] = *reinterpret_cast<const f4*>(&s_w[(tap * kBN + nf * 16 + li) * PW + 4 * g]);
+          bv[nf] = *reinterpret_cast<const f4*>(&sw[(tap * kBN + nf * 16 + li) * PW + 4 * g]);
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj)
 #pragma unroll
@@ -120,9 +148,9 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a) {
       } else {
         float av[MF], bv[NF];
 #pragma unroll
-        for (int mf = 0; mf < MF; ++mf) av[mf] = s_in[((wrow + mf + dy) * kHW + li + dx) * PIN + g];
+        for (int mf = 0; mf < MF; ++mf) av[mf] = si[((wrow + mf + dy) * kHW + li + dx) * PIN + g];
 #pragma unroll
-        for (int nf = 0; nf < NF; ++nf) bv[nf] = s_w[(tap * kBN + nf * 16 + li) * PW + g];
+        for (int nf = 0; nf < NF; ++nf) bv[nf] = sw[(tap * kBN + nf * 16 + li) * PW + g];
 #pragma unroll
         for (int mf = 0; mf < MF; ++mf)
 #pragma unroll
@@ -130,8 +158,11 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a) {
             acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mf], bv[nf], acc[mf][nf], 0, 0, 0);
       }
     }
+    if (more) LNM_COMMIT(cur ^ 1);
     __syncthreads();
   }
+#undef LNM_FETCH
+#undef LNM_COMMIT
 
   // epilogue: lane holds rows (pixels) 4g..4g+3 of each 16x16 block, column li
 #pragma unroll

@@ -102,8 +102,10 @@ __device__ __forceinline__ void store_tile(const ConvArgs& a, const f4 (&acc)[TH
 template <int MODE, int TH>
 __global__ __launch_bounds__(256) void conv3x3_bf16(ConvArgs a) {
   constexpr int MF = TH / 4;
-  __shared__ __attribute__((aligned(16))) uint16_t s_in[(TH + 2) * kHW * kPad];
-  __shared__ __attribute__((aligned(16))) uint16_t s_w[9 * kBN * kPad];
+  // two LDS buffers: the next chunk is fetched into registers while the
+  // matrix cores work on the current one
+  __shared__ __attribute__((aligned(16))) uint16_t s_in[2][(TH + 2) * kHW * kPad];
+  __shared__ __attribute__((aligned(16))) uint16_t s_w[2][9 * kBN * kPad];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tiles_y = (a.H + TH - 1) / TH;
@@ -120,39 +122,69 @@ __global__ __launch_bounds__(256) void conv3x3_bf16(ConvArgs a) {
 #pragma unroll
   for (int mf = 0; mf < MF; ++mf) acc[mf][0] = acc[mf][1] = f4{0.f, 0.f, 0.f, 0.f};
 
-  for (int ch = ch_lo; ch < ch_hi; ++ch) {
-    constexpr int NQ = (TH + 2) * kHW * (kCK / 8);
-    for (int q = tid; q < NQ; q += 256) {
-      const int c8 = q & 3, p = q >> 2;
-      const int hx = p % kHW, hy = p / kHW;
-      const int y = y0 + hy - 1, x = x0 + hx - 1, c = ch * kCK + 8 * c8;
+  constexpr int NQ = (TH + 2) * kHW * (kCK / 8), NW = 9 * kBN * kCK / 8;
+  constexpr int RQ = (NQ + 255) / 256, RW = (NW + 255) / 256;
+  uint4 rq[RQ], rw[RW];
+  auto fetch = [&](int ch) {
+#pragma unroll
+    for (int r = 0; r < RQ; ++r) {
+      const int q = tid + 256 * r;
       uint4 v = make_uint4(0, 0, 0, 0);
-      if (y >= 0 && y < a.H && x >= 0 && x < a.W && c < ci) v = gather8<MODE>(a, b, y, x, c);
-      *reinterpret_cast<uint4*>(&s_in[p * kPad + 8 * c8]) = v;
+      if (q < NQ) {
+        const int c8 = q & 3, p = q >> 2;
+        const int y = y0 + p / kHW - 1, x = x0 + p % kHW - 1, c = ch * kCK + 8 * c8;
+        if (y >= 0 && y < a.H && x >= 0 && x < a.W && c < ci) v = gather8<MODE>(a, b, y, x, c);
+      }
+      rq[r] = v;
     }
     const uint16_t* wsrc = wblk + (size_t)ch * 9 * kBN * kCK;
-    constexpr int NW = 9 * kBN * kCK / 8;
-    for (int q = tid; q < NW; q += 256) {
-      const int c8 = q & 3, row = q >> 2;
-      *reinterpret_cast<uint4*>(&s_w[row * kPad + 8 * c8]) = *reinterpret_cast<const uint4*>(wsrc + 8 * q);
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int q = tid + 256 * r;
+      if (q < NW) rw[r] = *reinterpret_cast<const uint4*>(wsrc + 8 * q);
     }
-    __syncthreads();
+  };
+  auto commit = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < RQ; ++r) {
+      const int q = tid + 256 * r;
+      if (q < NQ) *reinterpret_cast<uint4*>(&s_in[buf][(q >> 2) * kPad + 8 * (q & 3)]) = rq[r];
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int q = tid + 256 * r;
+      if (q < NW) *reinterpret_cast<uint4*>(&s_w[buf][(q >> 2) * kPad + 8 * (q & 3)]) = rw[r];
+    }
+  };
+
+  if (ch_lo < ch_hi) {
+    fetch(ch_lo);
+    commit(0);
+  }
+  __syncthreads();
+  for (int ch = ch_lo; ch < ch_hi; ++ch) {
+    const int cur = (ch - ch_lo) & 1;
+    const bool more = ch + 1 < ch_hi;
+    if (more) fetch(ch + 1);
+    const uint16_t* si = s_in[cur];
+    const uint16_t* sw = s_w[cur];
 #pragma unroll 3
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3, dx = tap - 3 * (tap / 3);
       bf16x8 av[MF], bv[2];
 #pragma unroll
       for (int mf = 0; mf < MF; ++mf)
-        av[mf] = *reinterpret_cast<const bf16x8*>(&s_in[((wrow + mf + dy) * kHW + li + dx) * kPad + 8 * g]);
+        av[mf] = *reinterpret_cast<const bf16x8*>(&si[((wrow + mf + dy) * kHW + li + dx) * kPad + 8 * g]);
 #pragma unroll
       for (int nf = 0; nf < 2; ++nf)
-        bv[nf] = *reinterpret_cast<const bf16x8*>(&s_w[(tap * kBN + nf * 16 + li) * kPad + 8 * g]);
+        bv[nf] = *reinterpret_cast<const bf16x8*>(&sw[(tap * kBN + nf * 16 + li) * kPad + 8 * g]);
 #pragma unroll
       for (int mf = 0; mf < MF; ++mf)
 #pragma unroll
         for (int nf = 0; nf < 2; ++nf)
           acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mf], bv[nf], acc[mf][nf], 0, 0, 0);
     }
+    if (more) commit(cur ^ 1);
     __syncthreads();
   }
   store_tile<TH>(a, acc, b, y0, x0, wrow, g, li, nt, ks);

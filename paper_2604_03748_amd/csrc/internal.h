@@ -33,7 +33,7 @@ bool make_cam(const lnm_camera& c, CamDev* out, std::string* why);
 
 // ---------------------------------------------------------------- march
 struct MarchDev {
-  const float* rho;
+  const float* rho;  // caller's linear grid, x fastest
   int nx, ny, nz;
   float sigma_scale;
   float h;        // world step
@@ -43,21 +43,31 @@ struct MarchDev {
   uint64_t seed;
   uint32_t frame;
   int quadrature;
-  float wf, wt, wb;
+  float wf, wt, wb;  // front and side light intensities
+  int light_set;     // lnm_light_set
+  const float* brick;  // bricked copy of rho (4^3 cells + apron per 128-float slot)
+  int nbx, nby, nbz;   // bricks per axis
 };
-// Per-sample records of the march (structure of arrays, index k * P + pixel).
+
 struct MarchBuf {
-  float* t;   // sample parameter t_n
-  float* a;   // weight A_n
-  float* tp;  // transmittance before the sample, T_{n-1}
-  float* tl;  // [2][K][P] transmittance toward the top / bottom light
+  float* t;   // [K][P] sample parameter t_n
+  float* a;   // [K][P] weight A_n
+  float* tp;  // [K][P] transmittance before the sample, T_{n-1}
+  float* al;  // [K][P] A_n L_n
   int* cnt;   // [P] recorded samples per pixel
-  int K, P;   // capacity per pixel, pixels
+  float* brick;
+  int nbx, nby, nbz;
+  int K, P;  // capacity per pixel, pixels
+};
+
+// XCD-aware order of 16x16 pixel tiles over a 1D grid of 8 * per_xcd blocks.
+struct TileMap {
+  int tiles_x, tiles_y, per_xcd, band_rows;
 };
 // Capacity per pixel: the most primary samples a ray can take in the support box.
 int march_capacity(const MarchDev& m);
-size_t march_scratch_bytes(int K, int P);
-MarchBuf march_buffers(void* ws, int K, int P);
+size_t march_scratch_bytes(const MarchDev& m, int K, int P);
+MarchBuf march_buffers(void* ws, const MarchDev& m, int K, int P);
 hipError_t launch_march(const MarchDev& m, const CamDev& cam, const MarchBuf& buf, float* guide, hipStream_t s);
 hipError_t launch_reference(const MarchDev& m, const CamDev& cam, int srgb, float* lm, hipStream_t s);
 
@@ -130,6 +140,22 @@ struct CompositeArgs {
   float rgb[16][3];
 };
 hipError_t launch_composite(const CompositeArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- shadows
+struct ShadowArgs {
+  CompositeArgs c;
+  CamDev cam;
+  float origin[3];
+  float E;  // half extent of the shadow maps
+  int S;    // texels per side
+  float bias;
+  float e1[16][3], e2[16][3], lw[16][3];  // light space of each light (world)
+  const float* depth[16];                 // [S][S] per light, NULL = unshadowed
+  float* vis;                             // optional [n_lights][P]
+};
+hipError_t launch_shadow_map_sphere(int S, float E, float cu, float cv, float cz, float r2, float* depth,
+                                    hipStream_t s);
+hipError_t launch_composite_shadowed(const ShadowArgs& a, hipStream_t s);
 
 }  // namespace lnm
 

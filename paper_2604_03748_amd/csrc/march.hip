@@ -1,28 +1,19 @@
 // Guiding-map ray march (Algorithm 1, Section 4.2) and fine-step six-way
-// reference lightmaps, fp32, one lane per pixel.
+// reference lightmaps, fp32.
 //
-// Work mapping: a 256-lane workgroup covers a 16x16 pixel tile and each
-// wavefront an 8x8 sub-tile, so the 64 rays of a wave are spatially coherent
-// and their trilinear gathers hit the same cache lines.  A wave retires when
-// its last ray terminates (early termination is per lane, so the wave's
-// lifetime is that of its longest ray).
+// The march first copies the density grid into 4^3-cell bricks (so the 8
+// corners of a trilinear sample are one short span of one 512-byte slot) and
+// then runs three kernels (see march_primary).  Pixels are handed out in
+// 16x16 tiles, an 8x8 sub-tile per wavefront, so the 64 rays of a wave are
+// spatially coherent and their gathers share cache lines; tiles are ordered
+// so that each XCD takes one band of the screen.
 #include <cmath>
 
 #include "internal.h"
+#include "ray.h"
 
 namespace lnm {
 namespace {
-
-struct V3 {
-  float x, y, z;
-};
-__device__ __forceinline__ V3 v3(float x, float y, float z) { return {x, y, z}; }
-__device__ __forceinline__ float dot3(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ V3 cross3(V3 a, V3 b) {
-  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
-}
-__device__ __forceinline__ V3 scale3(V3 a, float s) { return {a.x * s, a.y * s, a.z * s}; }
-__device__ __forceinline__ V3 normalize3(V3 a) { return scale3(a, 1.0f / sqrtf(dot3(a, a))); }
 
 // SplitMix64 output for state s: the finaliser applied to s + golden gamma.
 __device__ __forceinline__ uint64_t splitmix64(uint64_t s) {
@@ -33,9 +24,10 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t s) {
 }
 
 // sigma(p): sigma_scale x zero-border cell-centred trilinear interpolation.
-// Corner indices are clamped into the grid and corners outside it get weight
-// zero, so every load is in bounds.
-__device__ __forceinline__ float sample_sigma(const MarchDev& m, float px, float py, float pz) {
+// This form reads the caller's linear grid: corner indices are clamped into
+// the grid and corners outside it get weight zero, so every load is in
+// bounds.
+__device__ __forceinline__ float sample_sigma_linear(const MarchDev& m, float px, float py, float pz) {
   const float gx = px * (float)m.nx - 0.5f, gy = py * (float)m.ny - 0.5f, gz = pz * (float)m.nz - 0.5f;
   if (!(gx > -1.0f && gy > -1.0f && gz > -1.0f && gx < (float)m.nx && gy < (float)m.ny && gz < (float)m.nz))
     return 0.0f;
@@ -56,6 +48,51 @@ __device__ __forceinline__ float sample_sigma(const MarchDev& m, float px, float
   const float c11 = wx0 * r[zb + yb + ia] + wx1 * r[zb + yb + ib];
   const float v = wz0 * (wy0 * c00 + wy1 * c10) + wz1 * (wy0 * c01 + wy1 * c11);
   return m.sigma_scale * v;
+}
+
+// Bricked grid: index i' = i + 1 over [0, n + 1] (a zero layer on each side),
+// cut into bricks of 4 cells per axis that also store the next layer
+// (5 x 5 x 5 values in a 128-float slot).  The 8 corners of the cell holding
+// a point are then in one brick at fixed offsets, and the zero layers make
+// the grid's zero border explicit.  Same value as sample_sigma_linear.
+constexpr int kBrickSlot = 128;
+__device__ __forceinline__ float sample_sigma(const MarchDev& m, float px, float py, float pz) {
+  const float gx = px * (float)m.nx - 0.5f, gy = py * (float)m.ny - 0.5f, gz = pz * (float)m.nz - 0.5f;
+  if (!(gx > -1.0f && gy > -1.0f && gz > -1.0f && gx < (float)m.nx && gy < (float)m.ny && gz < (float)m.nz))
+    return 0.0f;
+  const float fx0 = floorf(gx), fy0 = floorf(gy), fz0 = floorf(gz);
+  const int i = (int)fx0 + 1, j = (int)fy0 + 1, k = (int)fz0 + 1;  // in [0, n]
+  const float fx = gx - fx0, fy = gy - fy0, fz = gz - fz0;
+  const int brick = ((k >> 2) * m.nby + (j >> 2)) * m.nbx + (i >> 2);
+  const float* r = m.brick + (size_t)brick * kBrickSlot + ((k & 3) * 25 + (j & 3) * 5 + (i & 3));
+  const float c00 = (1.0f - fx) * r[0] + fx * r[1];
+  const float c10 = (1.0f - fx) * r[5] + fx * r[6];
+  const float c01 = (1.0f - fx) * r[25] + fx * r[26];
+  const float c11 = (1.0f - fx) * r[30] + fx * r[31];
+  const float v = (1.0f - fz) * ((1.0f - fy) * c00 + fy * c10) + fz * ((1.0f - fy) * c01 + fy * c11);
+  return m.sigma_scale * v;
+}
+
+// Fill the bricked grid from the caller's linear grid (HBM-bound copy; once
+// per grid).  One lane per slot entry; entries 125..127 are padding.
+__global__ __launch_bounds__(256) void relayout_bricks(const float* __restrict__ rho, int nx, int ny, int nz, int nbx,
+                                                       int nby, int nbz, float* __restrict__ brick) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)nbx * nby * nbz * kBrickSlot) return;
+  const int s = e % kBrickSlot;
+  const long b = e / kBrickSlot;
+  float v = 0.0f;
+  if (s < 125) {
+    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / ((long)nbx * nby);
+    const int i = 4 * bx + s % 5 - 1, j = 4 * by + (s / 5) % 5 - 1, k = 4 * bz + s / 25 - 1;
+    if (i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz) v = rho[((size_t)k * ny + j) * nx + i];
+  }
+  brick[e] = v;
+}
+
+template <bool BRICK>
+__device__ __forceinline__ float sample(const MarchDev& m, float px, float py, float pz) {
+  return BRICK ? sample_sigma(m, px, py, pz) : sample_sigma_linear(m, px, py, pz);
 }
 
 // Parametric exit distance of x + s l from the support box (x assumed inside);
@@ -99,11 +136,16 @@ __device__ __forceinline__ bool clip_support(const MarchDev& m, V3 o, V3 d, floa
   return hi >= lo;
 }
 
+__device__ __forceinline__ int light_steps(const MarchDev& m, V3 x, V3 l, float h) {
+  const float s1 = exit_distance(m, x, l);
+  return s1 > 0.0f ? (int)floorf(s1 / h) : 0;
+}
+
 // Transmittance from x toward l: exp(-h sum_k sigma(x + k h l)) over the
 // points inside the support box, 0 once the optical depth passes tau_max.
+template <bool BRICK>
 __device__ __forceinline__ float light_transmittance(const MarchDev& m, V3 x, V3 l, float h, float tau_max) {
-  const float s1 = exit_distance(m, x, l);
-  const int kmax = s1 > 0.0f ? (int)floorf(s1 / h) : 0;
+  const int kmax = light_steps(m, x, l, h);
   const float lim = tau_max / h;
   float acc = 0.0f;
   // four samples' gathers are issued together; they are summed and tested
@@ -113,7 +155,7 @@ __device__ __forceinline__ float light_transmittance(const MarchDev& m, V3 x, V3
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float t = (float)(k + j) * h;
-      s[j] = k + j <= kmax ? sample_sigma(m, x.x + t * l.x, x.y + t * l.y, x.z + t * l.z) : 0.0f;
+      s[j] = k + j <= kmax ? sample<BRICK>(m, x.x + t * l.x, x.y + t * l.y, x.z + t * l.z) : 0.0f;
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -124,27 +166,67 @@ __device__ __forceinline__ float light_transmittance(const MarchDev& m, V3 x, V3
   return expf(-acc * h);
 }
 
-__device__ __forceinline__ void camera_ray(const CamDev& c, int i, int j, V3* o, V3* d) {
-  const float sx = 2.0f * ((float)i + 0.5f) / (float)c.W - 1.0f;
-  const float sy = 1.0f - 2.0f * ((float)j + 0.5f) / (float)c.H;
-  const V3 f = v3(c.f[0], c.f[1], c.f[2]), r = v3(c.r[0], c.r[1], c.r[2]), u = v3(c.u[0], c.u[1], c.u[2]);
-  const float a = sx * c.aspect;
-  if (c.proj == LNM_PERSPECTIVE) {
-    *o = v3(c.eye[0], c.eye[1], c.eye[2]);
-    *d = normalize3(v3(f.x + c.tan_half * (a * r.x + sy * u.x), f.y + c.tan_half * (a * r.y + sy * u.y),
-                       f.z + c.tan_half * (a * r.z + sy * u.z)));
-  } else {
-    const float e = c.half_extent;
-    *o = v3(c.eye[0] + e * (a * r.x + sy * u.x), c.eye[1] + e * (a * r.y + sy * u.y),
-            c.eye[2] + e * (a * r.z + sy * u.z));
-    *d = f;
+// The two side-light marches (+l and -l) of one point in one loop, two
+// samples of each per iteration, so that four gathers are in flight.  Each
+// march sums its samples in order and stops at its own termination limit;
+// the results equal two calls of light_transmittance.
+__device__ __forceinline__ void top_bottom_transmittance(const MarchDev& m, V3 x, V3 l, bool want_t, bool want_b,
+                                                         float* Tt, float* Tb) {
+  const float h = m.h, lim = m.tau_max / h;
+  int kt = want_t ? light_steps(m, x, l, h) : 0;
+  int kb = want_b ? light_steps(m, x, v3(-l.x, -l.y, -l.z), h) : 0;
+  float at = 0.0f, ab = 0.0f;
+  bool dead_t = false, dead_b = false;
+  for (int k = 1; k <= kt || k <= kb; k += 2) {
+    float st[2], sb[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const float t = (float)(k + q) * h;
+      st[q] = k + q <= kt ? sample<true>(m, x.x + t * l.x, x.y + t * l.y, x.z + t * l.z) : 0.0f;
+      sb[q] = k + q <= kb ? sample<true>(m, x.x - t * l.x, x.y - t * l.y, x.z - t * l.z) : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      at += st[q];
+      dead_t = dead_t || at > lim;
+      ab += sb[q];
+      dead_b = dead_b || ab > lim;
+    }
+    if (dead_t) kt = 0;
+    if (dead_b) kb = 0;
   }
+  *Tt = dead_t ? 0.0f : expf(-at * h);
+  *Tb = dead_b ? 0.0f : expf(-ab * h);
 }
 
 __device__ __forceinline__ void tile_pixel(int* i, int* j) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   *i = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
   *j = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
+}
+
+// Pixel of this lane under an XCD-aware tile order.  Workgroups are handed to
+// the 8 XCDs round robin by their linear id, so XCD e runs the blocks with
+// blockIdx.x = e (mod 8); the map gives those blocks one contiguous band of
+// 16x16 tiles (of screen columns, or rows when the light marches run
+// horizontally on screen), so each XCD's L2 holds the slab of the volume its
+// band sees instead of the whole grid.
+__device__ __forceinline__ bool banded_pixel(const TileMap& tm, int* i, int* j) {
+  const int b = blockIdx.x;
+  const int L = (b & 7) * tm.per_xcd + (b >> 3);
+  if (L >= tm.tiles_x * tm.tiles_y) return false;
+  int tx, ty;
+  if (tm.band_rows) {
+    ty = L / tm.tiles_x;
+    tx = L - ty * tm.tiles_x;
+  } else {
+    tx = L / tm.tiles_y;
+    ty = L - tx * tm.tiles_y;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  *i = tx * 16 + (wave & 1) * 8 + (lane & 7);
+  *j = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+  return true;
 }
 
 // Top surrogate light of a ray: normalize(w x z), or normalize(w x x) when w
@@ -156,18 +238,25 @@ __device__ __forceinline__ V3 top_light(V3 d) {
   return normalize3(top);
 }
 
+// First side light of the chosen set: top, or left = normalize(w x top).
+__device__ __forceinline__ V3 side_light(V3 d, int light_set) {
+  const V3 top = top_light(d);
+  return light_set == LNM_LIGHTS_LEFT_RIGHT ? normalize3(cross3(v3(-d.x, -d.y, -d.z), top)) : top;
+}
+
 // The march runs in three kernels so that its dominant cost, the light
 // marches (two per primary sample), is spread over one lane per
-// (pixel, sample, light) instead of serialised inside one lane per pixel:
+// (pixel, sample) instead of serialised inside one lane per pixel:
 //   1. march_primary: one lane per pixel walks the primary samples, writes
 //      T and D, and records (t_n, A_n, T_{n-1}) of every sample with A_n != 0;
-//   2. march_lights: one lane per recorded sample and light computes its
-//      transmittance toward the top or bottom light;
+//   2. march_lights: one lane per recorded sample marches toward the top and
+//      bottom lights and stores A_n L_n;
 //   3. march_accumulate: one lane per pixel sums A_n L_n in sample order.
-__global__ __launch_bounds__(256) void march_primary(MarchDev m, CamDev c, MarchBuf buf, float* __restrict__ guide) {
+// All three read the bricked grid filled by relayout_bricks.
+__global__ __launch_bounds__(256) void march_primary(MarchDev m, CamDev c, TileMap tm, MarchBuf buf,
+                                                     float* __restrict__ guide) {
   int i, j;
-  tile_pixel(&i, &j);
-  if (i >= c.W || j >= c.H) return;
+  if (!banded_pixel(tm, &i, &j) || i >= c.W || j >= c.H) return;
   V3 o, d;
   camera_ray(c, i, j, &o, &d);
   const uint32_t pix = (uint32_t)j * (uint32_t)c.W + (uint32_t)i;
@@ -190,7 +279,7 @@ __global__ __launch_bounds__(256) void march_primary(MarchDev m, CamDev c, March
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const float t = ((float)(nb + q) + u) * h;
-        sg[q] = nb + q <= n1 ? sample_sigma(m, o.x + t * d.x, o.y + t * d.y, o.z + t * d.z) : 0.0f;
+        sg[q] = nb + q <= n1 ? sample<true>(m, o.x + t * d.x, o.y + t * d.y, o.z + t * d.z) : 0.0f;
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -224,40 +313,47 @@ __global__ __launch_bounds__(256) void march_primary(MarchDev m, CamDev c, March
   g[2] = D;
 }
 
-// grid: (pixel tiles of 16x16, recorded sample index k, light 0 top / 1 bottom)
-__global__ __launch_bounds__(256) void march_lights(MarchDev m, CamDev c, MarchBuf buf, int tiles_x) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
-  const int i = tx * 16 + (wave & 1) * 8 + (lane & 7), j = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
-  if (i >= c.W || j >= c.H) return;
+// grid: (banded pixel tiles, recorded sample index k)
+__global__ __launch_bounds__(256) void march_lights(MarchDev m, CamDev c, TileMap tm, MarchBuf buf) {
+  int i, j;
+  if (!banded_pixel(tm, &i, &j) || i >= c.W || j >= c.H) return;
   const uint32_t pix = (uint32_t)j * (uint32_t)c.W + (uint32_t)i;
   const int k = blockIdx.y;
-  if ((blockIdx.z == 0 ? m.wt : m.wb) == 0.0f || k >= buf.cnt[pix]) return;
-  V3 o, d;
-  camera_ray(c, i, j, &o, &d);
-  V3 l = top_light(d);
-  if (blockIdx.z) l = v3(-l.x, -l.y, -l.z);
+  if (k >= buf.cnt[pix]) return;
   const size_t r = (size_t)k * buf.P + pix;
-  const float t = buf.t[r];
-  const V3 x = v3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
-  buf.tl[(size_t)blockIdx.z * buf.K * buf.P + r] = light_transmittance(m, x, l, m.h, m.tau_max);
+  // front light: marching toward w retraces the earlier primary samples, so
+  // its transmittance is T_{n-1}
+  float L = m.wf * buf.tp[r];
+  if (m.wt != 0.0f || m.wb != 0.0f) {
+    V3 o, d;
+    camera_ray(c, i, j, &o, &d);
+    const float t = buf.t[r];
+    const V3 x = v3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
+    float Tt, Tb;
+    top_bottom_transmittance(m, x, side_light(d, m.light_set), m.wt != 0.0f, m.wb != 0.0f, &Tt, &Tb);
+    if (m.wt != 0.0f) L += m.wt * Tt;
+    if (m.wb != 0.0f) L += m.wb * Tb;
+  }
+  buf.al[r] = buf.a[r] * L;
 }
 
-__global__ __launch_bounds__(256) void march_accumulate(MarchDev m, CamDev c, MarchBuf buf,
-                                                        float* __restrict__ guide) {
+__global__ __launch_bounds__(256) void march_accumulate(MarchBuf buf, float* __restrict__ guide) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= buf.P) return;
   const int cnt = buf.cnt[p];
+  const float* al = buf.al + p;
+  const size_t P = (size_t)buf.P;
   float Ls = 0.0f;
-  for (int k = 0; k < cnt; ++k) {
-    const size_t r = (size_t)k * buf.P + p;
-    // front light: marching toward w retraces the earlier primary samples,
-    // so its transmittance is T_{n-1}
-    float L = m.wf * buf.tp[r];
-    if (m.wt != 0.0f) L += m.wt * buf.tl[r];
-    if (m.wb != 0.0f) L += m.wb * buf.tl[(size_t)buf.K * buf.P + r];
-    Ls += buf.a[r] * L;
+  int k = 0;
+  // eight loads in flight, summed in sample order
+  for (; k + 8 <= cnt; k += 8) {
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = al[(size_t)(k + q) * P];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Ls += v[q];
   }
+  for (; k < cnt; ++k) Ls += al[(size_t)k * P];
   guide[3 * (size_t)p] = Ls;
 }
 
@@ -265,6 +361,7 @@ __device__ __forceinline__ float srgb_encode(float c) {
   return c <= 0.0031308f ? 12.92f * c : 1.055f * powf(c, 1.0f / 2.4f) - 0.055f;
 }
 
+// Fine-step reference: reads the caller's linear grid (it takes no scratch).
 __global__ __launch_bounds__(256) void reference_kernel(MarchDev m, CamDev c, int srgb, float* __restrict__ lm) {
   int i, j;
   tile_pixel(&i, &j);
@@ -282,12 +379,12 @@ __global__ __launch_bounds__(256) void reference_kernel(MarchDev m, CamDev c, in
     for (int n = n0; n <= n1; ++n) {
       const float t = (float)n * h;
       const V3 x = v3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
-      const float sig = sample_sigma(m, x.x, x.y, x.z);
+      const float sig = sample<false>(m, x.x, x.y, x.z);
       tau += sig * h;
       const float A = Tprev * -expm1f(-sig * h);
       if (A > 0.0f) {
 #pragma unroll
-        for (int a = 0; a < 6; ++a) acc[a] += A * light_transmittance(m, x, ax[a], h, m.tau_max);
+        for (int a = 0; a < 6; ++a) acc[a] += A * light_transmittance<false>(m, x, ax[a], h, m.tau_max);
       }
       Tprev = expf(-tau);
       if (tau > m.tau_max) break;
@@ -308,32 +405,67 @@ int march_capacity(const MarchDev& m) {
 }
 
 static size_t a256(size_t x) { return (x + 255) / 256 * 256; }
-
-size_t march_scratch_bytes(int K, int P) {
-  const size_t plane = a256(sizeof(float) * (size_t)K * P);
-  return 5 * plane + a256(sizeof(int) * (size_t)P);
+static int bricks_along(int n) { return (n >> 2) + 1; }
+static size_t brick_bytes(const MarchDev& m) {
+  return sizeof(float) * kBrickSlot * (size_t)bricks_along(m.nx) * bricks_along(m.ny) * bricks_along(m.nz);
 }
 
-MarchBuf march_buffers(void* ws, int K, int P) {
+size_t march_scratch_bytes(const MarchDev& m, int K, int P) {
+  const size_t plane = a256(sizeof(float) * (size_t)K * P);
+  return 4 * plane + a256(sizeof(int) * (size_t)P) + a256(brick_bytes(m));
+}
+
+MarchBuf march_buffers(void* ws, const MarchDev& m, int K, int P) {
   char* p = static_cast<char*>(ws);
   const size_t plane = a256(sizeof(float) * (size_t)K * P);
   MarchBuf b;
   b.t = reinterpret_cast<float*>(p);
   b.a = reinterpret_cast<float*>(p + plane);
   b.tp = reinterpret_cast<float*>(p + 2 * plane);
-  b.tl = reinterpret_cast<float*>(p + 3 * plane);  // two planes
-  b.cnt = reinterpret_cast<int*>(p + 5 * plane);
+  b.al = reinterpret_cast<float*>(p + 3 * plane);
+  b.cnt = reinterpret_cast<int*>(p + 4 * plane);
+  b.brick = reinterpret_cast<float*>(p + 4 * plane + a256(sizeof(int) * (size_t)P));
+  b.nbx = bricks_along(m.nx);
+  b.nby = bricks_along(m.ny);
+  b.nbz = bricks_along(m.nz);
   b.K = K;
   b.P = P;
   return b;
 }
 
-hipError_t launch_march(const MarchDev& m, const CamDev& cam, const MarchBuf& buf, float* guide, hipStream_t s) {
-  const int tiles_x = (cam.W + 15) / 16, tiles_y = (cam.H + 15) / 16;
-  hipLaunchKernelGGL(march_primary, dim3(tiles_x, tiles_y), dim3(256), 0, s, m, cam, buf, guide);
-  if (m.wt != 0.0f || m.wb != 0.0f)
-    hipLaunchKernelGGL(march_lights, dim3(tiles_x * tiles_y, buf.K, 2), dim3(256), 0, s, m, cam, buf, tiles_x);
-  hipLaunchKernelGGL(march_accumulate, dim3((buf.P + 255) / 256), dim3(256), 0, s, m, cam, buf, guide);
+// Band screen rows instead of columns when the top light of the central ray
+// runs more horizontally than vertically on screen.
+static TileMap tile_map(const CamDev& c) {
+  TileMap tm;
+  tm.tiles_x = (c.W + 15) / 16;
+  tm.tiles_y = (c.H + 15) / 16;
+  tm.per_xcd = (tm.tiles_x * tm.tiles_y + 7) / 8;
+  const double w[3] = {-c.f[0], -c.f[1], -c.f[2]};
+  double top[3] = {w[1], -w[0], 0.0};  // w x z
+  if (std::sqrt(top[0] * top[0] + top[1] * top[1]) < 1e-6) {
+    top[0] = 0.0;  // w x x
+    top[1] = w[2];
+    top[2] = -w[1];
+  }
+  const double along_r = std::fabs(top[0] * c.r[0] + top[1] * c.r[1] + top[2] * c.r[2]);
+  const double along_u = std::fabs(top[0] * c.u[0] + top[1] * c.u[1] + top[2] * c.u[2]);
+  tm.band_rows = along_r > along_u ? 1 : 0;
+  return tm;
+}
+
+hipError_t launch_march(const MarchDev& m0, const CamDev& cam, const MarchBuf& buf, float* guide, hipStream_t s) {
+  MarchDev m = m0;
+  m.brick = buf.brick;
+  m.nbx = buf.nbx;
+  m.nby = buf.nby;
+  m.nbz = buf.nbz;
+  const long entries = (long)buf.nbx * buf.nby * buf.nbz * kBrickSlot;
+  hipLaunchKernelGGL(relayout_bricks, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s, m.rho, m.nx, m.ny,
+                     m.nz, buf.nbx, buf.nby, buf.nbz, buf.brick);
+  const TileMap tm = tile_map(cam);
+  hipLaunchKernelGGL(march_primary, dim3(8 * tm.per_xcd), dim3(256), 0, s, m, cam, tm, buf, guide);
+  hipLaunchKernelGGL(march_lights, dim3(8 * tm.per_xcd, buf.K), dim3(256), 0, s, m, cam, tm, buf);
+  hipLaunchKernelGGL(march_accumulate, dim3((buf.P + 255) / 256), dim3(256), 0, s, buf, guide);
   return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@ LNM_OK, LNM_ERR_ARG, LNM_ERR_SHAPE, LNM_ERR_OOM, LNM_ERR_DEVICE, LNM_ERR_UNSUPPO
 FP32, BF16, FP8_E4M3 = 0, 1, 2
 ORTHOGRAPHIC, PERSPECTIVE = 0, 1
 QUAD_ALPHA, QUAD_RIEMANN = 0, 1
+LIGHTS_TOP_BOTTOM, LIGHTS_LEFT_RIGHT = 0, 1
 
 EXPORTS = [
     "lnm_abi_struct_size", "lnm_version", "lnm_ctx_create", "lnm_ctx_destroy", "lnm_last_error",
@@ -26,6 +27,7 @@ EXPORTS = [
     "lnm_composite", "lnm_profile_enable", "lnm_profile_read", "lnm_trainer_state_bytes", "lnm_frame_workspace_bytes",
     "lnm_train_workspace_bytes", "lnm_trainer_create", "lnm_trainer_destroy", "lnm_train_grad", "lnm_train_step",
     "lnm_trainer_read_params", "lnm_trainer_save", "lnm_trainer_load", "lnm_trainer_infer", "lnm_calibrate_amax",
+    "lnm_shadow_map_sphere", "lnm_composite_shadowed",
 ]
 K_MARCH, K_CONV, K_HEAD, K_COMPOSITE, K_REFERENCE = range(5)
 
@@ -50,11 +52,19 @@ class Camera(C.Structure):
 class MarchParams(C.Structure):
     _fields_ = [("step_voxels", C.c_float), ("depth_tau", C.c_float), ("ert_eps", C.c_float),
                 ("jitter_on", C.c_int32), ("jitter_seed", C.c_uint64), ("frame", C.c_uint32),
-                ("quadrature", C.c_int32), ("light_w", C.c_float * 3), ("reserved", C.c_int32)]
+                ("quadrature", C.c_int32), ("light_w", C.c_float * 3), ("light_set", C.c_int32)]
 
 
 class Light(C.Structure):
     _fields_ = [("dir", C.c_float * 3), ("rgb", C.c_float * 3)]
+
+
+class ShadowFrame(C.Structure):
+    _fields_ = [("origin", C.c_float * 3), ("half_extent", C.c_float), ("size", C.c_int32), ("bias", C.c_float)]
+
+
+def make_shadow_frame(origin, half_extent, size, bias) -> ShadowFrame:
+    return ShadowFrame((C.c_float * 3)(*[float(x) for x in origin]), float(half_extent), int(size), float(bias))
 
 
 _lib = None
@@ -100,6 +110,12 @@ def lib():
                                 C.POINTER(Light), i32, vp, vp, vp, vp, sz, vp]
         L.lnm_composite.restype = i32
         L.lnm_composite.argtypes = [vp, C.POINTER(Camera), C.POINTER(Light), i32, i32, i32, i32, vp, vp, vp, vp]
+        L.lnm_shadow_map_sphere.restype = i32
+        L.lnm_shadow_map_sphere.argtypes = [vp, C.POINTER(ShadowFrame), C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                            C.c_float, vp, vp]
+        L.lnm_composite_shadowed.restype = i32
+        L.lnm_composite_shadowed.argtypes = [vp, C.POINTER(Camera), C.POINTER(Light), i32, C.POINTER(ShadowFrame),
+                                             C.POINTER(vp), i32, i32, i32, vp, vp, vp, vp, vp]
         L.lnm_calibrate_amax.restype = i32
         L.lnm_calibrate_amax.argtypes = [vp, vp, i32, i32, i32, vp, vp, i32, vp, sz, vp]
         L.lnm_profile_enable.restype = i32
@@ -151,7 +167,7 @@ def make_camera(cam) -> Camera:
 
 
 def make_params(step_voxels, depth_tau=0.1, ert_eps=1e-6, jitter=True, seed=0, frame=0, quadrature=QUAD_ALPHA,
-                light_w=(1.0, 1.0, 1.0)) -> MarchParams:
+                light_w=(1.0, 1.0, 1.0), light_set=0) -> MarchParams:
     p = MarchParams()
     p.step_voxels = step_voxels
     p.depth_tau = depth_tau
@@ -161,7 +177,7 @@ def make_params(step_voxels, depth_tau=0.1, ert_eps=1e-6, jitter=True, seed=0, f
     p.frame = int(frame)
     p.quadrature = int(quadrature)
     p.light_w[:] = [float(v) for v in light_w]
-    p.reserved = 0
+    p.light_set = int(light_set)
     return p
 
 
@@ -255,6 +271,41 @@ class Context:
         arr, n = make_lights(lights)
         check(lib().lnm_composite(self.handle, C.byref(c), arr, n, B, H, W, _ptr(lightmaps), _ptr(guide), _ptr(out),
                                   _stream(stream)))
+        return out
+
+    def shadow_map_sphere(self, frame: ShadowFrame, light_dir, centre, radius, out=None, stream=None):
+        """[size][size] obstacle depths of a sphere seen from a directional light."""
+        import torch
+
+        S = frame.size
+        if out is None:
+            out = torch.empty((S, S), dtype=torch.float32, device="cuda")
+        _need(out, (S, S), "depth")
+        f3 = C.c_float * 3
+        check(lib().lnm_shadow_map_sphere(self.handle, C.byref(frame), f3(*map(float, light_dir)),
+                                          f3(*map(float, centre)), float(radius), _ptr(out), _stream(stream)))
+        return out
+
+    def composite_shadowed(self, cam, lights, frame: ShadowFrame, depth_maps, lightmaps, guide, out=None, vis=None,
+                           stream=None):
+        """Six-way shading with light k's term masked by the visibility of each
+        pixel's smoke surface in depth_maps[k] (a tensor, or None = unshadowed)."""
+        import torch
+
+        c = make_camera(cam)
+        B = lightmaps.shape[0] if lightmaps.dim() == 4 else 1
+        H, W = c.height, c.width
+        if out is None:
+            out = torch.empty(tuple(lightmaps.shape[:-1]) + (4,), dtype=torch.float32, device=lightmaps.device)
+        arr, n = make_lights(lights)
+        if len(depth_maps) != n:
+            raise ValueError("one depth map (or None) per light")
+        for d in depth_maps:
+            if d is not None:
+                _need(d, (frame.size, frame.size), "depth map")
+        ptrs = (C.c_void_p * max(n, 1))(*[None if d is None else d.data_ptr() for d in depth_maps])
+        check(lib().lnm_composite_shadowed(self.handle, C.byref(c), arr, n, C.byref(frame), ptrs, B, H, W,
+                                           _ptr(lightmaps), _ptr(guide), _ptr(out), _ptr(vis), _stream(stream)))
         return out
 
 

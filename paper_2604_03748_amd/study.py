@@ -1,0 +1,124 @@
+"""Training and evaluation studies run entirely on the GPU library: the
+guiding-light ablation and the density-scale robustness check (Section 5),
+and the gain of the trained network over the method without it.
+
+Data: seeded synthetic scenes (32^3 volumes of 6 Gaussian blobs seen from a
+random orbit, perspective or orthographic), guiding maps from lnm_march and
+targets from the fine-step reference lightmaps (lnm_reference_lightmaps, in
+sRGB).  Training: lnm_train_step (Adam) on the fp32 network.  Quality: PSNR
+of the predicted six lightmaps against the references on held-out scenes."""
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from synth.rng import substream
+from synth.scene import Camera, ORTHOGRAPHIC, PERSPECTIVE, make_volume
+from synth.weights import he_normal_params
+
+from . import lnm
+
+GRID, RES, STEP, REF_STEP, SIGMA = 32, 64, 2.0, 0.5, 8.0
+LEVELS, BASE = 3, 16
+TRAIN_SEEDS = range(100, 196)
+TEST_SEEDS = range(1000, 1016)
+
+# Guiding-light configurations of the ablation: (light_w, light_set)
+LIGHT_CONFIGS = {
+    "front": ((1.0, 0.0, 0.0), lnm.LIGHTS_TOP_BOTTOM),
+    "front+LR": ((1.0, 1.0, 1.0), lnm.LIGHTS_LEFT_RIGHT),
+    "front+TB": ((1.0, 1.0, 1.0), lnm.LIGHTS_TOP_BOTTOM),
+}
+
+
+def scene(seed: int):
+    """32^3 volume of 6 blobs and a camera on a random orbit around it."""
+    vol = make_volume(GRID, 6, seed)
+    u = substream(seed, "view").uniform(3)
+    az, el = 2 * math.pi * u[0], 0.5 * (u[1] - 0.5)
+    d = 2.5
+    eye = (0.5 + d * math.cos(el) * math.cos(az), 0.5 + d * math.sin(el), 0.5 + d * math.cos(el) * math.sin(az))
+    proj = PERSPECTIVE if u[2] < 0.5 else ORTHOGRAPHIC
+    cam = Camera(proj, eye, fov_y_deg=40.0, ortho_half_extent=0.8, width=RES, height=RES)
+    return vol, cam
+
+
+def make_set(ctx, seeds, light_w=(1.0, 1.0, 1.0), light_set=0, density_scale=1.0):
+    """Guiding maps [N][RES][RES][3] and sRGB reference lightmaps [N][RES][RES][6]
+    (device tensors).  density_scale multiplies the extinction of both."""
+    import torch
+
+    gs, ts = [], []
+    for s in seeds:
+        vol, cam = scene(s)
+        dens = torch.as_tensor(vol, device="cuda")
+        ss = SIGMA * density_scale
+        gs.append(ctx.march(dens, ss, cam, lnm.make_params(STEP, seed=s, light_w=light_w, light_set=light_set)))
+        ts.append(ctx.reference_lightmaps(dens, ss, cam, REF_STEP, srgb=True))
+    return torch.stack(gs), torch.stack(ts)
+
+
+def psnr(pred, ref) -> float:
+    mse = float(np.mean((np.asarray(pred, np.float64) - np.asarray(ref, np.float64)) ** 2))
+    return 10 * math.log10(1.0 / mse) if mse > 0 else math.inf
+
+
+@dataclass
+class TrainResult:
+    trainer: "lnm.Trainer"
+    losses: list
+
+
+def train(ctx, g, t, steps=600, batch=12, lr=1e-3, seed=0, init_seed=0) -> TrainResult:
+    """Adam on random minibatches drawn with a seeded generator."""
+    import torch
+
+    tr = lnm.Trainer(ctx, LEVELS, BASE, he_normal_params(LEVELS, BASE, seed=init_seed))
+    rng = np.random.default_rng(seed)
+    n = g.shape[0]
+    loss = torch.empty(1, dtype=torch.float32, device=g.device)
+    hist = []
+    for it in range(steps):
+        idx = torch.as_tensor(rng.choice(n, batch, replace=False), device=g.device)
+        tr.step(g[idx].contiguous(), t[idx].contiguous(), lr=lr, loss=loss)
+        if it % 100 == 0 or it == steps - 1:
+            hist.append(float(loss.cpu()[0]))
+    return TrainResult(tr, hist)
+
+
+def affine_baseline(tr_g, tr_t, te_g):
+    """The method without the network: each lightmap channel as a least-squares
+    affine function of the guiding map's in-scatter channel."""
+    Gh, Th = tr_g.cpu().numpy(), tr_t.cpu().numpy()
+    A = np.stack([Gh[..., 0].ravel(), np.ones(Gh[..., 0].size)], axis=1)
+    coef = [np.linalg.lstsq(A, Th[..., c].ravel(), rcond=None)[0] for c in range(6)]
+    Ge = te_g.cpu().numpy()
+    return np.stack([np.clip(coef[c][0] * Ge[..., 0] + coef[c][1], 0, 1) for c in range(6)], axis=-1)
+
+
+def light_ablation(ctx, steps=600, configs=None) -> dict:
+    """Held-out PSNR of a network trained and tested on guiding maps of each
+    light configuration (targets are the same reference lightmaps)."""
+    out = {}
+    for name in configs or LIGHT_CONFIGS:
+        w, ls = LIGHT_CONFIGS[name]
+        tr_g, tr_t = make_set(ctx, TRAIN_SEEDS, w, ls)
+        te_g, te_t = make_set(ctx, TEST_SEEDS, w, ls)
+        r = train(ctx, tr_g, tr_t, steps=steps)
+        out[name] = {"psnr": psnr(r.trainer.infer(te_g).cpu().numpy(), te_t.cpu().numpy()),
+                     "loss_first": r.losses[0], "loss_last": r.losses[-1]}
+    return out
+
+
+def density_robustness(ctx, steps=600, scales=(0.5, 1.0, 2.0)) -> dict:
+    """Train at density scale 1, evaluate on held-out scenes whose density is
+    scaled (guides and references both from the scaled field)."""
+    tr_g, tr_t = make_set(ctx, TRAIN_SEEDS)
+    r = train(ctx, tr_g, tr_t, steps=steps)
+    out = {}
+    for s in scales:
+        te_g, te_t = make_set(ctx, TEST_SEEDS, density_scale=s)
+        ref = te_t.cpu().numpy()
+        out[s] = {"psnr": psnr(r.trainer.infer(te_g).cpu().numpy(), ref),
+                  "psnr_affine": psnr(affine_baseline(tr_g, tr_t, te_g), ref)}
+    return out

@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol(L):
 
 def test_struct_sizes_match_binding(L):
     lib = L.lib()
-    for i, s in enumerate([L.Volume, L.Camera, L.MarchParams, L.Light]):
+    for i, s in enumerate([L.Volume, L.Camera, L.MarchParams, L.Light, L.ShadowFrame]):
         assert lib.lnm_abi_struct_size(i) == C.sizeof(s)
     assert lib.lnm_abi_struct_size(99) == 0
 

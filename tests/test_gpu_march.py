@@ -22,7 +22,8 @@ def _run(ctx, vol, ss, cam, step, **kw):
 
     p = lnm.make_params(step, depth_tau=kw.get("depth_tau", 0.1), ert_eps=kw.get("ert_eps", 1e-6),
                         jitter=kw.get("jitter", True), seed=kw.get("seed", 0), frame=kw.get("frame", 0),
-                        quadrature=kw.get("quadrature", 0), light_w=kw.get("light_w", (1.0, 1.0, 1.0)))
+                        quadrature=kw.get("quadrature", 0), light_w=kw.get("light_w", (1.0, 1.0, 1.0)),
+                        light_set=kw.get("light_set", 0))
     g = ctx.march(to_dev(vol), ss, cam, p)
     return to_host(g)
 
@@ -64,6 +65,17 @@ def test_riemann_weights_and_light_mix(ctx, orc):
     wl = small_ortho()
     _both(ctx, orc, wl.volume(), 8.0, wl.camera, 2.0, "riemann", quadrature=1, light_w=(0.5, 2.0, 0.0))
     _both(ctx, orc, wl.volume(), 8.0, wl.camera, 2.0, "top_only", light_w=(0.0, 1.0, 0.0), jitter=False)
+
+
+def test_left_right_light_set(ctx, orc):
+    """The guiding-light ablation's (left, right) side lights (Section 5)."""
+    wl = small_ortho()
+    _both(ctx, orc, wl.volume(), 8.0, wl.camera, 2.0, "left_right", light_set=1)
+    _both(ctx, orc, wl.volume(), 8.0, wl.camera, 2.0, "left_only", light_set=1, light_w=(0.0, 1.0, 0.0))
+    vol = make_volume((20, 28, 36), 5, 17, noise_amp=0.3)
+    cam = Camera(PERSPECTIVE, (-1.3, 2.1, 1.7), target=(0.55, 0.45, 0.5), up=(0.2, 0.1, 1.0), fov_y_deg=48.0,
+                 width=45, height=37)
+    _both(ctx, orc, vol, 6.0, cam, 1.5, "left_right_oblique", seed=5, light_set=1, light_w=(0.3, 0.5, 1.2))
 
 
 def test_ert_off_and_dense(ctx, orc):

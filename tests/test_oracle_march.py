@@ -194,6 +194,32 @@ def test_rotation_about_world_z(orc):
         np.testing.assert_allclose(gr, g, atol=1e-11)
 
 
+def test_left_right_lights_are_the_quarter_turned_top_bottom(orc):
+    """Guiding-light ablation (Section 5): viewing along -x, top = w x z = -y
+    and left = w x top = -z.  Turning the volume and the camera's up vector
+    by 90 degrees about the view axis (y -> z) makes the top light of the
+    turned scene the left light of the original, pixel for pixel."""
+    n = 20
+    vol = make_volume(n, 5, 11)
+    # V'(x, y, z) = V(x, 1 - z, y): V'[k][j][i] = V[j][n-1-k][i]
+    turned = np.ascontiguousarray(vol.transpose(1, 0, 2)[::-1, :, :])
+    cam_y = ortho_camera(18, 18)
+    cam_z = Camera(ORTHOGRAPHIC, cam_y.eye, up=(0.0, 0.0, 1.0), ortho_half_extent=cam_y.ortho_half_extent,
+                   width=18, height=18)
+    for w in ((0.0, 1.0, 0.0), (0.0, 0.0, 1.0), (0.4, 0.7, 0.2)):
+        lr, _, _ = orc.march(vol, 8.0, cam_z, 1.5, jitter=True, seed=2, light_w=w, light_set=1)
+        tb, _, _ = orc.march(turned, 8.0, cam_y, 1.5, jitter=True, seed=2, light_w=w, light_set=0)
+        np.testing.assert_allclose(lr, tb, atol=1e-11)
+    # the two sets differ on a generic volume, and agree with front light only
+    a = orc.march(vol, 8.0, cam_y, 1.5, jitter=False, light_set=0)[0]
+    b = orc.march(vol, 8.0, cam_y, 1.5, jitter=False, light_set=1)[0]
+    assert np.abs(a[..., 0] - b[..., 0]).max() > 1e-3
+    np.testing.assert_array_equal(a[..., 1:], b[..., 1:])
+    f0 = orc.march(vol, 8.0, cam_y, 1.5, jitter=False, light_w=(1, 0, 0), light_set=0)[0]
+    f1 = orc.march(vol, 8.0, cam_y, 1.5, jitter=False, light_w=(1, 0, 0), light_set=1)[0]
+    np.testing.assert_array_equal(f0, f1)
+
+
 def test_perspective_projection_of_a_point(orc):
     """A compact blob shows up at the pinhole projection of its centre."""
     n = 64
