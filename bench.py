@@ -1,13 +1,25 @@
 """Benchmark of the neural six-way lightmaps hot path on one MI355X.
 
-One step = one frame of the whole path through lnm_frame: guiding-map march
-of a 128^3 smoke grid (24 blobs + value noise) seen by a 60-degree perspective
-camera at 256x256 with a 4-voxel step, the 4-level base-32 U-Net, and six-way
-shading for one light.  Inputs (grid, weights, buffers) are resident in HBM
-before the timed region.  The same frame is timed with the fp32 network
-(`value`) and the bf16 network (`modes.bf16`).  Prints one JSON line.
+One step = one frame of the whole path through lnm_frame: brick relayout and
+guiding-map march of a 128^3 smoke grid (24 blobs + value noise) seen by a
+60-degree perspective camera at 256x256 with a 4-voxel step, the 4-level
+base-32 U-Net, and six-way shading for one light.  Inputs (grid, weights,
+buffers) are resident in HBM before the timed region.  The frame is timed
+with the fp32 network (`value`) and the bf16 and fp8 networks (`modes`).
+Per-kernel durations come from HIP events the library records on its stream
+in a second pass over the same frames; `roofline` is the 3x3 conv layers'
+(the dominant kernel) algorithmic FLOP rate against the dtype's MFMA peak,
+with HBM traffic from the committed rocprofv3 counter summary when it
+matches the current conv sources.
 
-Usage: python bench.py [--steps K] [--warmup W] [--dtype fp32|bf16] [--no-cpu-baseline]
+Further sections (each can be skipped): per-channel error of the three
+precisions against the fp64 oracle; the channel-adapter network; the dynamic
+256^3 / 1024^2 bf16 scene; the continuous-batching server (64 instances,
+Poisson arrivals, HBM budget); the oracle's CPU frame rate (`cpu_baseline`).
+Prints one JSON line.
+
+Usage: python bench.py [--steps K] [--warmup W] [--dtype fp32|bf16|fp8] [--only]
+       [--no-cpu-baseline] [--no-serve] [--no-dynamic] [--no-precision] [--no-adapters]
 """
 from __future__ import annotations
 
@@ -115,6 +127,8 @@ def served(lnm, ctx, params, seconds, warmup_s, rate_hz=2000.0, budget_gb=64.0, 
         insts[k] = Instance(k, make_volume_torch(n, 24, 1000 + k, 0.3, device="cuda"), res,
                             start_deg=(37.0 * k) % 360.0, seed=1000 + k,
                             light=(tuple(light_direction(1000 + k)), (1.0, 1.0, 1.0)))
+    for inst in insts.values():  # the grids are static: brick them once, like keeping them resident
+        inst.prepare(ctx)
     torch.cuda.synchronize()
     net = lnm.Net(ctx, 4, 32, params, precision=lnm.BF16)
     be = Backend(ctx, net, n_streams=4)
@@ -176,6 +190,43 @@ def dynamic_scene(lnm, ctx, frames, warmup=3):
             "density_regen_ms_mean": round(float(np.mean(gen_ms)), 4)}
 
 
+def adapters_mode(lnm, ctx, wl, params, dens, steps, warmup):
+    """The network with the four NAFBlock channel adapters in place of the
+    plain head (fp32), on the headline guiding map: U-Net trunk + adapters per
+    frame, and the adapters' own time from HIP events around their kernels."""
+    import torch
+
+    from synth.weights import adapter_flops, adapter_params
+
+    net = lnm.Net(ctx, wl.levels, wl.base, params)
+    ad = lnm.Adapters(net, adapter_params(wl.base, seed=0))
+    g = ctx.march(dens, 8.0, wl.camera, lnm.make_params(wl.step_voxels, seed=0))[None]
+    H, W = wl.camera.height, wl.camera.width
+    lm = torch.empty((1, H, W, 6), dtype=torch.float32, device=dens.device)
+    ex = torch.empty((1, H, W, 2), dtype=torch.float32, device=dens.device)
+    ws = ad.workspace(1, H, W)
+    for _ in range(warmup):
+        ad.infer(g, out=lm, extra=ex, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ad.infer(g, out=lm, extra=ex, workspace=ws)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    ctx.profile(True)
+    for _ in range(steps):
+        ad.infer(g, out=lm, extra=ex, workspace=ws)
+    torch.cuda.synchronize()
+    n, tot = ctx.profile_read(lnm.K_ADAPTERS)
+    ctx.profile(False)
+    us = 1e3 * tot / max(n, 1)
+    fl = adapter_flops(wl.base, 1, H, W)
+    return {"workload": "persp128_256px", "net": f"L{wl.levels} base {wl.base} fp32 + 4 NAFBlock adapters",
+            "ms_per_frame_net_plus_adapters": round(ms, 4), "adapters_us": round(us, 2),
+            "adapters_flops": fl, "adapters_tflops": round(fl / (us * 1e-6) / 1e12, 3),
+            "peak_fp32_vector_tflops": 157.3}
+
+
 def precision_report(lnm, ctx, wl, params, dens):
     """Max / mean abs error per lightmap channel of fp32, bf16 and fp8
     against the fp64 oracle, on one frame's guiding map."""
@@ -204,6 +255,38 @@ def precision_report(lnm, ctx, wl, params, dens):
     return out, amax
 
 
+# the conv kernels and their split-K choice (conv_splits lives in conv.hip)
+CONV_SOURCES = ("paper_2604_03748_amd/csrc/conv.hip", "paper_2604_03748_amd/csrc/conv_bf16.hip",
+                "paper_2604_03748_amd/csrc/conv_fp8.hip")
+
+
+def conv_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in CONV_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(dtype):
+    """HBM bytes per conv launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None
+    when there is none or the conv sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"conv3x3_{dtype}_persp128_256px_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    try:
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (IndexError, ValueError):
+        return None
+    if blob.get("source_hash") != conv_source_hash():
+        return None
+    return blob.get("bytes_per_launch")
+
+
 def conv_roofline(wl, stage, dtype):
     from synth.weights import unet_flops, unet_layers
 
@@ -216,7 +299,7 @@ def conv_roofline(wl, stage, dtype):
     kern = {"fp32": "conv3x3_f32 (v_mfma_f32_16x16x4_f32)", "bf16": "conv3x3_bf16 (v_mfma_f32_16x16x32_bf16)",
             "fp8": "conv3x3_fp8 (v_mfma_f32_16x16x32_fp8_fp8)"}[dtype]
     return {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_TFLOPS[dtype], 5), "traffic": None, "kernel": kern,
+            "frac": round(achieved / PEAK_TFLOPS[dtype], 5), "traffic": measured_traffic(dtype), "kernel": kern,
             "flops_per_launch": round(per_launch), "us_per_launch": round(us, 3), "launches_per_frame": n_conv}
 
 
@@ -232,9 +315,16 @@ def main():
     ap.add_argument("--no-precision", action="store_true", help="skip the per-channel error report")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--no-dynamic", action="store_true", help="skip the dynamic-scene mode")
+    ap.add_argument("--no-adapters", action="store_true", help="skip the channel-adapter mode")
     ap.add_argument("--dynamic-frames", type=int, default=60)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (reference for HBM counters)")
+    ap.add_argument("--source-hash", action="store_true", help="print the conv sources' hash and exit")
     args = ap.parse_args()
+    if args.source_hash:
+        print(conv_source_hash())
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: frames and smoke instances are "
               f"independent, so the path shards by frame or instance with no exchange", file=sys.stderr)
@@ -254,6 +344,13 @@ def main():
     ctx = lnm.Context(0)
     dens = torch.as_tensor(wl.volume(), device=dev)
     stream = torch.cuda.current_stream()
+    if args.copy_mb > 0:
+        # one elementwise kernel reading and writing copy_mb MiB each
+        a = torch.empty(args.copy_mb * 2**18, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
     prec = {"fp32": lnm.FP32, "bf16": lnm.BF16, "fp8": lnm.FP8_E4M3}
     order = [args.dtype] + ([] if args.only else [d for d in ("fp32", "bf16", "fp8") if d != args.dtype])
     # fp8 activation scales: maxima of the fp32 network over 4 jittered frames
@@ -300,6 +397,9 @@ def main():
     }
     if not args.no_precision:
         out["precision_error_vs_fp64_oracle"], _ = precision_report(lnm, ctx, wl, params, dens)
+    if not args.no_adapters:
+        out["adapters"] = adapters_mode(lnm, ctx, wl, params, dens, max(20, args.steps // 4), 5)
+        log(f"adapters: {out['adapters']}")
     if not args.no_dynamic:
         out["dynamic"] = dynamic_scene(lnm, ctx, args.dynamic_frames)
         log(f"dynamic: {out['dynamic']}")

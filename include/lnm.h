@@ -54,12 +54,18 @@ typedef struct lnm_net_s* lnm_net; /* host descriptor of a packed network */
 
 /* Density grid: the scattering coefficient sigma_s(x) = sigma_scale * rho~(x)
  * where rho~ is the zero-border, cell-centred trilinear interpolation of
- * `density` (Section 4.2 keeps sigma_s in a 3D texture).  sigma_t = sigma_s. */
+ * `density` (Section 4.2 keeps sigma_s in a 3D texture).  sigma_t = sigma_s.
+ * The march reads the grid as 4^3-cell bricks: by default each march call
+ * builds them in its workspace; a caller that marches the same grid many
+ * times may build them once with lnm_make_bricks and pass them in `bricks`
+ * (the march then trusts that they were made from `density` and these
+ * dimensions, and needs a smaller workspace). */
 typedef struct {
   const float* density; /* device, [nz][ny][nx], x fastest */
   int32_t nx, ny, nz;   /* each >= 1 */
   float sigma_scale;    /* >= 0 */
-} lnm_volume;           /* 24 bytes */
+  const float* bricks;  /* device, from lnm_make_bricks, or NULL */
+} lnm_volume;           /* 32 bytes */
 
 /* Pinhole or orthographic camera.  forward f = normalize(target - eye),
  * right r = normalize(f x up), up' = r x f.  Pixel (i, j) has screen
@@ -143,10 +149,20 @@ LNM_API void lnm_ctx_destroy(lnm_ctx ctx);
 LNM_API const char* lnm_last_error(void);
 
 /* ------------------------------------------------------------------ march */
+/* Bytes of the bricked copy of an nx x ny x nz grid: ((n >> 2) + 1) bricks
+ * per axis, 512 bytes each; 0 on invalid sizes. */
+LNM_API size_t lnm_bricks_bytes(int32_t nx, int32_t ny, int32_t nz);
+/* Build the bricked copy of vol->density into `bricks` (device, at least
+ * lnm_bricks_bytes): grid index i + 1 (a zero layer on each side) cut into
+ * bricks of 4 cells per axis, each storing its 5 x 5 x 5 values (the next
+ * layer included) x fastest in a 128-float slot, bricks x fastest.
+ * vol->bricks is ignored.  Stream ordered. */
+LNM_API lnm_status lnm_make_bricks(lnm_ctx ctx, const lnm_volume* vol, float* bricks, size_t bytes, void* stream);
+
 /* Device workspace (bytes) the march needs for this volume, camera and step:
  * per pixel, records of up to K primary samples (K bounded by the support
- * box diagonal over h) and their two light transmittances; 0 on invalid
- * arguments. */
+ * box diagonal over h) and their light terms, plus the bricked grid unless
+ * vol->bricks is given; 0 on invalid arguments. */
 LNM_API size_t lnm_march_workspace_bytes(const lnm_volume* vol, const lnm_camera* cam,
                                          const lnm_march_params* prm);
 
@@ -238,6 +254,43 @@ LNM_API lnm_status lnm_composite(lnm_ctx ctx, const lnm_camera* cam, const lnm_l
                          int32_t batch, int32_t H, int32_t W, const float* lightmaps, const float* guide, float* rgba,
                          void* stream);
 
+/* ----------------------------------------------------------- channel adapters */
+/* Channel adapters (Section 4.3): four NAFBlocks on the decoder output of a
+ * network (width c = its base), one per output group, each followed by a 1x1
+ * head to the group's two channels and a sigmoid; they replace the plain
+ * 6-channel head.  The NAFBlock (Chen et al. 2022) with both expansions 2:
+ *   x = LN1(in); x = conv1x1(c -> 2c); x = depthwise conv3x3 (zero pad);
+ *   x = x[:c] * x[c:]; x = x * (W_sca mean_image(x) + b_sca); x = conv1x1(c -> c);
+ *   y = in + beta * x; x = LN2(y); x = conv1x1(c -> 2c); x = x[:c] * x[c:];
+ *   x = conv1x1(c -> c); out = y + gamma * x.
+ * LN normalises the channels of each pixel (biased variance, eps 1e-6) with
+ * per-channel weight and bias; the mean is over each image of a batch.
+ * Parameters per adapter, fp32, in order: ln1 w[c] b[c]; conv1 W[2c][c]
+ * b[2c]; depthwise W[2c][3][3] b[2c]; sca W[c][c] b[c]; conv3 W[c][c] b[c];
+ * beta[c]; ln2 w[c] b[c]; conv4 W[2c][c] b[2c]; conv5 W[c][c] b[c]; gamma[c];
+ * head W[2][c] b[2]; the four adapters in group order front/back,
+ * left/right, up/down, alpha/emissive.  Outputs: lightmaps channels
+ * (+Z, -Z), (+X, -X), (+Y, -Y) from groups 0-2, extra[..][2] = (alpha,
+ * emissive) from group 3.  Widths 16, 32, 48 and 64 are supported. */
+typedef struct lnm_adapters_s* lnm_adapters;
+LNM_API size_t lnm_adapters_param_count(int32_t c);
+LNM_API size_t lnm_adapters_device_bytes(int32_t c);
+/* Bind adapters to `net` (which must outlive them) and upload the host
+ * parameters into dev_buf (caller-owned device memory, at least
+ * lnm_adapters_device_bytes(net base)).  Synchronises `stream`. */
+LNM_API lnm_status lnm_adapters_create(lnm_ctx ctx, lnm_net net, const float* host_params, size_t n_params,
+                                       void* dev_buf, size_t dev_bytes, void* stream, lnm_adapters* out);
+LNM_API void lnm_adapters_destroy(lnm_adapters ad);
+/* Workspace of lnm_infer_adapters: the network's plus the adapters'
+ * intermediates (about 12 c floats per pixel); 0 on invalid arguments. */
+LNM_API size_t lnm_adapters_workspace_bytes(lnm_adapters ad, int32_t batch, int32_t H, int32_t W);
+/* The network's trunk on guide[B][H][W][3] and the four adapters:
+ * lightmaps[B][H][W][6] and, when extra is not NULL, extra[B][H][W][2]
+ * (device). */
+LNM_API lnm_status lnm_infer_adapters(lnm_ctx ctx, lnm_adapters ad, int32_t batch, int32_t H, int32_t W,
+                                      const float* guide, float* lightmaps, float* extra, void* workspace,
+                                      size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------ obstacle shadows */
 /* Shadow map (see lnm_shadow_frame) of a sphere obstacle (centre, radius in
  * world units) for the light direction light_dir[3] (host, need not be unit):
@@ -315,7 +368,8 @@ typedef enum {
   LNM_K_HEAD = 2,       /* 1x1 head + sigmoid */
   LNM_K_COMPOSITE = 3,  /* six-way shading */
   LNM_K_REFERENCE = 4,  /* reference lightmaps */
-  LNM_K_COUNT = 5
+  LNM_K_ADAPTERS = 5,   /* channel adapters */
+  LNM_K_COUNT = 6
 } lnm_kernel_kind;
 
 /* on != 0: discard earlier records and, from now on, bracket every kernel

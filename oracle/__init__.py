@@ -73,6 +73,12 @@ def lib():
         L.orc_unet_forward.argtypes = [C.c_int, C.c_int, _F, C.c_long, C.c_int, C.c_int, C.c_int, _D, _D, _D]
         L.orc_unet_loss_grad.restype = C.c_int
         L.orc_unet_loss_grad.argtypes = [C.c_int, C.c_int, _F, C.c_long, C.c_int, C.c_int, C.c_int, _D, _D, _D, _D]
+        L.orc_unet_features.restype = C.c_int
+        L.orc_unet_features.argtypes = [C.c_int, C.c_int, _F, C.c_long, C.c_int, C.c_int, C.c_int, _D, _D]
+        L.orc_adapter_param_count.restype = C.c_long
+        L.orc_adapter_param_count.argtypes = [C.c_int]
+        L.orc_adapters_forward.restype = C.c_int
+        L.orc_adapters_forward.argtypes = [C.c_int, _F, C.c_long, C.c_int, C.c_int, C.c_int, _D, _D, _D]
         L.orc_adam.restype = None
         L.orc_adam.argtypes = [C.c_long, _D, _D, _D, _D, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
         L.orc_num_threads.restype = C.c_int
@@ -239,6 +245,42 @@ def unet_forward(params, levels, base, guide):
     if st:
         raise ValueError(f"orc_unet_forward status {st}")
     return (lm[0], lo[0]) if squeeze else (lm, lo)
+
+
+def unet_features(params, levels, base, guide):
+    """guide [B][H][W][3] (or [H][W][3]) -> decoder features [.., base] (the head's input)."""
+    g = _f64(guide)
+    squeeze = g.ndim == 3
+    if squeeze:
+        g = g[None]
+    B, H, W, _ = g.shape
+    p = _f32(params)
+    out = np.zeros((B, H, W, base), dtype=np.float64)
+    st = lib().orc_unet_features(levels, base, _fp(p), p.size, B, H, W, _dp(g), _dp(out))
+    if st:
+        raise ValueError(f"orc_unet_features status {st}")
+    return out[0] if squeeze else out
+
+
+def adapter_param_count(c) -> int:
+    return lib().orc_adapter_param_count(c)
+
+
+def adapters_forward(params, c, feat):
+    """Four NAFBlock channel adapters: feat [B][H][W][c] (or [H][W][c]) ->
+    (lightmaps [.., 6], extra [.., 2] = alpha, emissive)."""
+    f = _f64(feat)
+    squeeze = f.ndim == 3
+    if squeeze:
+        f = f[None]
+    B, H, W, _ = f.shape
+    p = _f32(params)
+    lm = np.zeros((B, H, W, 6), dtype=np.float64)
+    ex = np.zeros((B, H, W, 2), dtype=np.float64)
+    st = lib().orc_adapters_forward(c, _fp(p), p.size, B, H, W, _dp(f), _dp(lm), _dp(ex))
+    if st:
+        raise ValueError(f"orc_adapters_forward status {st}")
+    return (lm[0], ex[0]) if squeeze else (lm, ex)
 
 
 def unet_loss_grad(params, levels, base, guide, target):

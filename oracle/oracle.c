@@ -18,7 +18,9 @@
  *     the paper's offline single-scatter references, Section 5);
  *   - the U-Net forward and backward passes (Section 4.3), the pixel MSE in
  *     sRGB space (Section 4.4) and Adam (Section 5, "Training");
- *   - the six-way directional interpolation used for shading (Section 3).
+ *   - the four NAFBlock channel adapters on the decoder output (Section 4.3);
+ *   - the six-way directional interpolation used for shading (Section 3),
+ *     and the depth-based obstacle shadowing (Section 4.5).
  *
  * Readings of silent or garbled passages (all listed in the design notes):
  *   - A_n: Algorithm 1 writes T_{n-1} sigma_s with no step length.  The default
@@ -887,6 +889,146 @@ ORC_EXPORT int orc_unet_loss_grad(int levels, int base, const float* params, lon
   free(g);
   for (int lv = 0; lv < L - 1; ++lv) free(skip_grad[lv]);
   fwd_free(&f, net.n);
+  return 0;
+}
+
+/* Decoder output features of the U-Net (the input of its head):
+ * feat[B][H][W][base], after the last ReLU.  params as orc_unet_forward. */
+ORC_EXPORT int orc_unet_features(int levels, int base, const float* params, long n_params, int B, int H, int W,
+                                 const double* guide, double* feat) {
+  Net net;
+  int st = net_setup(levels, base, params, n_params, &net);
+  if (st) return st;
+  int div = 1 << (levels - 1);
+  if (B < 1 || H < 1 || W < 1 || H % div || W % div) return 3;
+  Fwd f;
+  unet_forward_saved(&net, B, H, W, guide, &f);
+  nchw_to_nhwc(f.x_in[net.n - 1], B, base, H, W, feat);
+  fwd_free(&f, net.n);
+  return 0;
+}
+
+/* ------------------------------------------------------- channel adapters */
+/*
+ * Four channel adapters on the decoder output (Section 4.3): one per output
+ * group (front/back, left/right, up/down, alpha/emissive), each a NAFBlock
+ * of width c followed by a 1x1 head to that group's two channels and a
+ * sigmoid.  The NAFBlock is the published one (Chen et al. 2022, "Simple
+ * Baselines for Image Restoration") with both expansion factors 2:
+ *   x = LN1(in); x = conv1x1(c -> 2c); x = depthwise conv3x3 (2c, zero pad);
+ *   x = x[:c] * x[c:] (simple gate); x = x * (W_sca mean_{H,W}(x) + b_sca)
+ *   (simplified channel attention, mean over each image); x = conv1x1(c -> c);
+ *   y = in + beta * x;
+ *   x = LN2(y); x = conv1x1(c -> 2c); x = x[:c] * x[c:]; x = conv1x1(c -> c);
+ *   out = y + gamma * x.
+ * LN is a layer norm over the channels of each pixel (biased variance,
+ * eps 1e-6) with per-channel weight and bias.
+ * Parameters of one adapter, in order: ln1 w[c] b[c]; conv1 W[2c][c] b[2c];
+ * dw W[2c][3][3] b[2c]; sca W[c][c] b[c]; conv3 W[c][c] b[c]; beta[c];
+ * ln2 w[c] b[c]; conv4 W[2c][c] b[2c]; conv5 W[c][c] b[c]; gamma[c];
+ * head W[2][c] b[2].  The four adapters follow each other in group order.
+ * Outputs: group 0 -> lightmaps (+Z, -Z), 1 -> (+X, -X), 2 -> (+Y, -Y),
+ * 3 -> (alpha, emissive).
+ */
+ORC_EXPORT long orc_adapter_param_count(int c) { return 4L * (7L * c * c + 35L * c + 2); }
+
+static void layer_norm_pixel(const double* x, int c, const float* w, const float* b, double* out) {
+  double mu = 0.0, var = 0.0;
+  for (int i = 0; i < c; ++i) mu += x[i];
+  mu /= c;
+  for (int i = 0; i < c; ++i) var += (x[i] - mu) * (x[i] - mu);
+  var /= c;
+  const double r = 1.0 / sqrt(var + 1e-6);
+  for (int i = 0; i < c; ++i) out[i] = (x[i] - mu) * r * w[i] + b[i];
+}
+
+/* out[o] = b[o] + sum_i W[o][i] x[i] */
+static void dense(const double* x, int ci, int co, const float* W, const float* b, double* out) {
+  for (int o = 0; o < co; ++o) {
+    double s = b[o];
+    for (int i = 0; i < ci; ++i) s += (double)W[(size_t)o * ci + i] * x[i];
+    out[o] = s;
+  }
+}
+
+/* One NAFBlock + head on feat[B][H][W][c] -> two sigmoid outputs [B][H][W][2]. */
+static void adapter_forward(int c, const float* P, int B, int H, int W, const double* feat, double* out2) {
+  const float *ln1w = P, *ln1b = ln1w + c, *c1w = ln1b + c, *c1b = c1w + 2 * c * c, *dww = c1b + 2 * c,
+              *dwb = dww + 18 * c, *scaw = dwb + 2 * c, *scab = scaw + c * c, *c3w = scab + c, *c3b = c3w + c * c,
+              *beta = c3b + c, *ln2w = beta + c, *ln2b = ln2w + c, *c4w = ln2b + c, *c4b = c4w + 2 * c * c,
+              *c5w = c4b + 2 * c, *c5b = c5w + c * c, *gamma = c5b + c, *hw = gamma + c, *hb = hw + 2 * c;
+  const size_t HW = (size_t)H * W;
+  double* u = malloc(sizeof(double) * HW * 2 * c); /* conv1 output of one image */
+  double* g = malloc(sizeof(double) * HW * c);     /* gated, then attended */
+  double* t = malloc(sizeof(double) * 2 * c);
+  double* t2 = malloc(sizeof(double) * 2 * c);
+  double* pooled = malloc(sizeof(double) * c);
+  double* sca = malloc(sizeof(double) * c);
+  for (int b = 0; b < B; ++b) {
+    const double* f = feat + (size_t)b * HW * c;
+    for (size_t q = 0; q < HW; ++q) {
+      layer_norm_pixel(f + q * c, c, ln1w, ln1b, t);
+      dense(t, c, 2 * c, c1w, c1b, u + q * 2 * c);
+    }
+    for (int y = 0; y < H; ++y)
+      for (int x = 0; x < W; ++x) {
+        for (int ch = 0; ch < 2 * c; ++ch) {
+          double s = dwb[ch];
+          for (int dy = 0; dy < 3; ++dy)
+            for (int dx = 0; dx < 3; ++dx) {
+              const int yy = y + dy - 1, xx = x + dx - 1;
+              if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+              s += (double)dww[ch * 9 + dy * 3 + dx] * u[((size_t)yy * W + xx) * 2 * c + ch];
+            }
+          t[ch] = s;
+        }
+        for (int ch = 0; ch < c; ++ch) g[((size_t)y * W + x) * c + ch] = t[ch] * t[c + ch];
+      }
+    for (int ch = 0; ch < c; ++ch) {
+      double s = 0.0;
+      for (size_t q = 0; q < HW; ++q) s += g[q * c + ch];
+      pooled[ch] = s / (double)HW;
+    }
+    dense(pooled, c, c, scaw, scab, sca);
+    for (size_t q = 0; q < HW; ++q) {
+      double* gq = g + q * c;
+      for (int ch = 0; ch < c; ++ch) gq[ch] *= sca[ch];
+      dense(gq, c, c, c3w, c3b, t);
+      double yv[512];
+      for (int ch = 0; ch < c; ++ch) yv[ch] = f[q * c + ch] + (double)beta[ch] * t[ch];
+      layer_norm_pixel(yv, c, ln2w, ln2b, t);
+      dense(t, c, 2 * c, c4w, c4b, t2);
+      for (int ch = 0; ch < c; ++ch) t[ch] = t2[ch] * t2[c + ch];
+      dense(t, c, c, c5w, c5b, t2);
+      for (int ch = 0; ch < c; ++ch) yv[ch] += (double)gamma[ch] * t2[ch];
+      double z[2];
+      dense(yv, c, 2, hw, hb, z);
+      for (int k = 0; k < 2; ++k) out2[((size_t)b * HW + q) * 2 + k] = 1.0 / (1.0 + exp(-z[k]));
+    }
+  }
+  free(u); free(g); free(t); free(t2); free(pooled); free(sca);
+}
+
+/* Adapters on feat[B][H][W][c]: lightmaps[B][H][W][6] (+X, -X, +Y, -Y, +Z,
+ * -Z) and extra[B][H][W][2] (alpha, emissive).  c <= 512. */
+ORC_EXPORT int orc_adapters_forward(int c, const float* params, long n_params, int B, int H, int W,
+                                    const double* feat, double* lightmaps, double* extra) {
+  if (c < 1 || c > 512 || n_params != orc_adapter_param_count(c) || B < 1 || H < 1 || W < 1) return 1;
+  static const int dst[4][2] = {{4, 5}, {0, 1}, {2, 3}, {-1, -2}};
+  const long per = 7L * c * c + 35L * c + 2;
+  const size_t n = (size_t)B * H * W;
+  double* o2 = malloc(sizeof(double) * n * 2);
+  for (int grp = 0; grp < 4; ++grp) {
+    adapter_forward(c, params + grp * per, B, H, W, feat, o2);
+    for (size_t q = 0; q < n; ++q)
+      for (int k = 0; k < 2; ++k) {
+        if (dst[grp][k] >= 0)
+          lightmaps[q * 6 + dst[grp][k]] = o2[q * 2 + k];
+        else
+          extra[q * 2 + k] = o2[q * 2 + k];
+      }
+  }
+  free(o2);
   return 0;
 }
 

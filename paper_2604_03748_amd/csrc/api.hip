@@ -79,6 +79,8 @@ static lnm_status check_volume(const lnm_volume* v) {
   if (!v->density) return fail(LNM_ERR_ARG, "volume.density is NULL");
   if (v->nx < 1 || v->ny < 1 || v->nz < 1) return fail(LNM_ERR_SHAPE, "volume dimensions must be >= 1");
   if ((double)v->nx * v->ny * v->nz > 4.0e9) return fail(LNM_ERR_SHAPE, "volume larger than 2^32 voxels");
+  if (bricks_bytes(v->nx, v->ny, v->nz) > 0xFFFFFFFFull)
+    return fail(LNM_ERR_SHAPE, "volume too large for the march's bricked grid (4 GiB, about 1000^3 voxels)");
   if (!(v->sigma_scale >= 0.0f) || !std::isfinite(v->sigma_scale))
     return fail(LNM_ERR_ARG, "volume.sigma_scale must be finite and >= 0");
   return LNM_OK;
@@ -117,7 +119,7 @@ static lnm_status march_setup(const lnm_volume* vol, const lnm_camera* cam, cons
   m->wt = prm->light_w[1];
   m->wb = prm->light_w[2];
   m->light_set = prm->light_set;
-  m->brick = nullptr;  // set by launch_march from its scratch
+  m->brick = vol->bricks;  // NULL: launch_march builds them in its scratch
   m->nbx = m->nby = m->nbz = 0;
   return LNM_OK;
 }
@@ -531,7 +533,7 @@ size_t lnm_march_workspace_bytes(const lnm_volume* vol, const lnm_camera* cam, c
   MarchDev m;
   CamDev c;
   if (march_setup(vol, cam, prm, &m, &c)) return 0;
-  return march_scratch_bytes(m, march_capacity(m), c.W * c.H);
+  return march_scratch_bytes(m, march_capacity(m), c.W, c.H);
 }
 
 lnm_status lnm_march(lnm_ctx ctx, const lnm_volume* vol, const lnm_camera* cam, const lnm_march_params* prm,
@@ -542,12 +544,12 @@ lnm_status lnm_march(lnm_ctx ctx, const lnm_volume* vol, const lnm_camera* cam, 
   CamDev c;
   lnm_status st = march_setup(vol, cam, prm, &m, &c);
   if (st) return st;
-  const int K = march_capacity(m), P = c.W * c.H;
-  const size_t need = march_scratch_bytes(m, K, P);
+  const int K = march_capacity(m);
+  const size_t need = march_scratch_bytes(m, K, c.W, c.H);
   if (!workspace || ws_bytes < need)
     return fail(LNM_ERR_SHAPE, "march workspace too small: need " + std::to_string(need) + " bytes");
   ProfScope ps(ctx, LNM_K_MARCH, (hipStream_t)stream);
-  LNM_HIP_CHECK(launch_march(m, c, march_buffers(workspace, m, K, P), guide, (hipStream_t)stream));
+  LNM_HIP_CHECK(launch_march(m, c, march_buffers(workspace, m, K, c.W, c.H), guide, (hipStream_t)stream));
   return LNM_OK;
 }
 
@@ -560,7 +562,7 @@ size_t lnm_frame_workspace_bytes(lnm_net net, const lnm_volume* vol, const lnm_c
   if (c.H % div || c.W % div) return 0;
   // the march's records are dead once the guide is written, so the U-Net
   // activations reuse the same bytes
-  return std::max(march_scratch_bytes(m, march_capacity(m), c.W * c.H), plan_workspace(net, 1, c.H, c.W).bytes);
+  return std::max(march_scratch_bytes(m, march_capacity(m), c.W, c.H), plan_workspace(net, 1, c.H, c.W).bytes);
 }
 
 lnm_status lnm_reference_lightmaps(lnm_ctx ctx, const lnm_volume* vol, const lnm_camera* cam, float step_voxels,
@@ -724,6 +726,118 @@ lnm_status lnm_composite(lnm_ctx ctx, const lnm_camera* cam, const lnm_light* li
   return LNM_OK;
 }
 
+// ---------------------------------------------------------------- channel adapters
+static size_t adapters_params(int c) { return c >= 1 ? 4 * (7 * (size_t)c * c + 35 * (size_t)c + 2) : 0; }
+
+struct AdapterPlan {
+  size_t net_bytes, u_off, v_off, part_off, sca_off, bytes;
+  int n_blk;
+};
+static AdapterPlan adapter_plan(const lnm_adapters_s* ad, int B, int H, int W) {
+  AdapterPlan p;
+  const size_t P = (size_t)B * H * W, c = ad->c;
+  p.n_blk = (H * W + 255) / 256;
+  p.net_bytes = plan_workspace(ad->net, B, H, W).bytes;
+  p.u_off = align256(p.net_bytes);
+  p.v_off = align256(p.u_off + sizeof(float) * 8 * c * P);
+  p.part_off = align256(p.v_off + sizeof(float) * 4 * c * P);
+  p.sca_off = align256(p.part_off + sizeof(float) * (size_t)B * 4 * c * p.n_blk);
+  p.bytes = p.sca_off + sizeof(float) * (size_t)B * 4 * c;
+  return p;
+}
+
+size_t lnm_adapters_param_count(int32_t c) { return adapter_width_supported(c) ? adapters_params(c) : 0; }
+
+size_t lnm_adapters_device_bytes(int32_t c) {
+  return adapter_width_supported(c) ? align256(sizeof(float) * adapters_params(c)) : 0;
+}
+
+lnm_status lnm_adapters_create(lnm_ctx ctx, lnm_net net, const float* host_params, size_t n_params, void* dev_buf,
+                               size_t dev_bytes, void* stream, lnm_adapters* out) {
+  if (!ctx || !net || !host_params || !dev_buf || !out) return fail(LNM_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  const int c = net->base;
+  if (!adapter_width_supported(c)) return fail(LNM_ERR_UNSUPPORTED, "adapters need a base width of 16, 32, 48 or 64");
+  if (n_params != adapters_params(c))
+    return fail(LNM_ERR_SHAPE, "adapter parameters: expected " + std::to_string(adapters_params(c)));
+  if (dev_bytes < lnm_adapters_device_bytes(c)) return fail(LNM_ERR_SHAPE, "adapter device buffer too small");
+  for (size_t i = 0; i < n_params; ++i)
+    if (!std::isfinite(host_params[i])) return fail(LNM_ERR_ARG, "adapter parameters must be finite");
+  hipStream_t s = (hipStream_t)stream;
+  LNM_HIP_CHECK(hipMemcpyAsync(dev_buf, host_params, sizeof(float) * n_params, hipMemcpyHostToDevice, s));
+  LNM_HIP_CHECK(hipStreamSynchronize(s));
+  lnm_adapters_s* ad = new (std::nothrow) lnm_adapters_s;
+  if (!ad) return fail(LNM_ERR_OOM, "out of host memory");
+  ad->net = net;
+  ad->c = c;
+  ad->dev = static_cast<float*>(dev_buf);
+  *out = ad;
+  return LNM_OK;
+}
+
+void lnm_adapters_destroy(lnm_adapters ad) { delete ad; }
+
+size_t lnm_adapters_workspace_bytes(lnm_adapters ad, int32_t batch, int32_t H, int32_t W) {
+  if (!ad || check_infer(ad->net, batch, H, W, SIZE_MAX, reinterpret_cast<void*>(1))) return 0;
+  return adapter_plan(ad, batch, H, W).bytes;
+}
+
+lnm_status lnm_infer_adapters(lnm_ctx ctx, lnm_adapters ad, int32_t batch, int32_t H, int32_t W, const float* guide,
+                              float* lightmaps, float* extra, void* workspace, size_t ws_bytes, void* stream) {
+  if (!ctx || !ad) return fail(LNM_ERR_ARG, "ctx or adapters is NULL");
+  if (!guide || !lightmaps) return fail(LNM_ERR_ARG, "guide or lightmaps is NULL");
+  lnm_status st = check_infer(ad->net, batch, H, W, ws_bytes, workspace);
+  if (st) return st;
+  const AdapterPlan ap = adapter_plan(ad, batch, H, W);
+  if (ws_bytes < ap.bytes) return fail(LNM_ERR_SHAPE, "workspace too small: need " + std::to_string(ap.bytes));
+  char* ws = static_cast<char*>(workspace);
+  hipStream_t s = (hipStream_t)stream;
+  st = run_unet(ctx, ad->net, batch, H, W, guide, nullptr, nullptr, ws, s);  // trunk only
+  if (st) return st;
+  const lnm_net_s* net = ad->net;
+  const int n_conv = (int)net->layers.size() - 1;
+  AdapterArgs a{};
+  a.feat = ws + plan_workspace(net, batch, H, W).out_off[n_conv - 1];
+  a.feat_scale = net->precision == LNM_FP8_E4M3 ? net->act_scale[n_conv - 1] : 1.0f;
+  a.prm = ad->dev;
+  a.B = batch;
+  a.H = H;
+  a.W = W;
+  a.P = (size_t)batch * H * W;
+  a.u = reinterpret_cast<float*>(ws + ap.u_off);
+  a.v = reinterpret_cast<float*>(ws + ap.v_off);
+  a.part = reinterpret_cast<float*>(ws + ap.part_off);
+  a.n_blk = ap.n_blk;
+  a.sca = reinterpret_cast<float*>(ws + ap.sca_off);
+  a.lm = lightmaps;
+  a.extra = extra;
+  const int in_type = net->precision == LNM_FP8_E4M3 ? 2 : net->precision == LNM_BF16 ? 1 : 0;
+  ProfScope ps(ctx, LNM_K_ADAPTERS, s);
+  LNM_HIP_CHECK(launch_adapters(ad->c, a, in_type, s));
+  return LNM_OK;
+}
+
+size_t lnm_bricks_bytes(int32_t nx, int32_t ny, int32_t nz) {
+  if (nx < 1 || ny < 1 || nz < 1 || (double)nx * ny * nz > 4.0e9) return 0;
+  return bricks_bytes(nx, ny, nz);
+}
+
+lnm_status lnm_make_bricks(lnm_ctx ctx, const lnm_volume* vol, float* bricks, size_t bytes, void* stream) {
+  if (!ctx || !bricks) return fail(LNM_ERR_ARG, "NULL argument");
+  lnm_status st = check_volume(vol);
+  if (st) return st;
+  if (bytes < bricks_bytes(vol->nx, vol->ny, vol->nz))
+    return fail(LNM_ERR_SHAPE, "bricks buffer too small: need " + std::to_string(bricks_bytes(vol->nx, vol->ny, vol->nz)));
+  MarchDev m{};
+  m.rho = vol->density;
+  m.nx = vol->nx;
+  m.ny = vol->ny;
+  m.nz = vol->nz;
+  ProfScope ps(ctx, LNM_K_MARCH, (hipStream_t)stream);
+  LNM_HIP_CHECK(launch_relayout(m, bricks, nullptr, (hipStream_t)stream));
+  return LNM_OK;
+}
+
 // Light space of the shadow maps, in fp64 then rounded once.
 static void light_frame(const float* dir, float e1[3], float e2[3], float lw[3]) {
   double l[3] = {dir[0], dir[1], dir[2]};
@@ -817,8 +931,8 @@ lnm_status lnm_frame(lnm_ctx ctx, lnm_net net, const lnm_volume* vol, const lnm_
   if (st) return st;
   st = check_infer(net, 1, c.H, c.W, ws_bytes, workspace);
   if (st) return st;
-  const int K = march_capacity(m), P = c.W * c.H;
-  const size_t need = march_scratch_bytes(m, K, P);
+  const int K = march_capacity(m);
+  const size_t need = march_scratch_bytes(m, K, c.W, c.H);
   if (ws_bytes < need) return fail(LNM_ERR_SHAPE, "workspace too small for the march: need " + std::to_string(need));
   CompositeArgs a{};
   if (rgba) {
@@ -828,7 +942,7 @@ lnm_status lnm_frame(lnm_ctx ctx, lnm_net net, const lnm_volume* vol, const lnm_
   hipStream_t s = (hipStream_t)stream;
   {
     ProfScope ps(ctx, LNM_K_MARCH, s);
-    LNM_HIP_CHECK(launch_march(m, c, march_buffers(workspace, m, K, P), guide, s));
+    LNM_HIP_CHECK(launch_march(m, c, march_buffers(workspace, m, K, c.W, c.H), guide, s));
   }
   st = run_unet(ctx, net, 1, c.H, c.W, guide, lightmaps, nullptr, static_cast<char*>(workspace), s);
   if (st) return st;

@@ -45,29 +45,36 @@ struct MarchDev {
   int quadrature;
   float wf, wt, wb;  // front and side light intensities
   int light_set;     // lnm_light_set
-  const float* brick;  // bricked copy of rho (4^3 cells + apron per 128-float slot)
+  const float* brick;  // bricked copy of rho (4^3 cells + apron per 128-float slot); caller's or scratch
   int nbx, nby, nbz;   // bricks per axis
 };
 
 struct MarchBuf {
-  float* t;   // [K][P] sample parameter t_n
-  float* a;   // [K][P] weight A_n
-  float* tp;  // [K][P] transmittance before the sample, T_{n-1}
-  float* al;  // [K][P] A_n L_n
-  int* cnt;   // [P] recorded samples per pixel
+  float* t;    // [K][P] sample parameter t_n
+  float* a;    // [K][P] weight A_n
+  float* tp;   // [K][P] transmittance before the sample, T_{n-1}
+  float* tl;   // [2][K][P] transmittance toward the top / bottom (first / second side) light
+  int* cnt;    // [P] recorded samples per pixel
+  int* ctr;    // [8] entries in each band's work list
+  int2* rec;   // [8][cap] (pixel, k) work lists of the light marches
+  size_t cap;  // entries per band list
   float* brick;
   int nbx, nby, nbz;
   int K, P;  // capacity per pixel, pixels
 };
 
-// XCD-aware order of 16x16 pixel tiles over a 1D grid of 8 * per_xcd blocks.
+// XCD-aware order of 8x8 pixel tiles over a 1D grid of 8 * per_xcd blocks.
 struct TileMap {
   int tiles_x, tiles_y, per_xcd, band_rows;
 };
 // Capacity per pixel: the most primary samples a ray can take in the support box.
 int march_capacity(const MarchDev& m);
-size_t march_scratch_bytes(const MarchDev& m, int K, int P);
-MarchBuf march_buffers(void* ws, const MarchDev& m, int K, int P);
+// Scratch of one march; the bricked grid is part of it unless m.brick is set.
+size_t march_scratch_bytes(const MarchDev& m, int K, int W, int H);
+MarchBuf march_buffers(void* ws, const MarchDev& m, int K, int W, int H);
+size_t bricks_bytes(int nx, int ny, int nz);
+// ctr (optional): band counters zeroed by the same launch.
+hipError_t launch_relayout(const MarchDev& m, float* bricks, int* ctr, hipStream_t s);
 hipError_t launch_march(const MarchDev& m, const CamDev& cam, const MarchBuf& buf, float* guide, hipStream_t s);
 hipError_t launch_reference(const MarchDev& m, const CamDev& cam, int srgb, float* lm, hipStream_t s);
 
@@ -141,6 +148,24 @@ struct CompositeArgs {
 };
 hipError_t launch_composite(const CompositeArgs& a, hipStream_t s);
 
+// ---------------------------------------------------------------- channel adapters
+struct AdapterArgs {
+  const void* feat;   // decoder output [P][c] in the network's precision
+  float feat_scale;   // e4m3 features: their scale
+  const float* prm;   // four adapters' parameters (parameter-file order)
+  int B, H, W;
+  size_t P;           // B H W
+  float* u;           // [4][2c][P] conv1 outputs
+  float* v;           // [4][c][P] gated depthwise outputs
+  float* part;        // [B][4][c][n_blk] per-block sums of v
+  int n_blk;          // 256-pixel blocks per image
+  float* sca;         // [B][4][c] attention scales
+  float* lm;          // [P][6]
+  float* extra;       // [P][2] or NULL
+};
+bool adapter_width_supported(int c);
+hipError_t launch_adapters(int c, const AdapterArgs& a, int in_type, hipStream_t s);
+
 // ---------------------------------------------------------------- shadows
 struct ShadowArgs {
   CompositeArgs c;
@@ -187,6 +212,12 @@ class ProfScope {
   int idx_ = -1;
 };
 }  // namespace lnm
+
+struct lnm_adapters_s {
+  const lnm_net_s* net;
+  int c;
+  float* dev;  // caller-owned parameter buffer
+};
 
 struct lnm_net_s {
   int levels, base, precision;

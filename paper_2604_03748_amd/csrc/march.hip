@@ -28,9 +28,11 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t s) {
 // the grid and corners outside it get weight zero, so every load is in
 // bounds.
 __device__ __forceinline__ float sample_sigma_linear(const MarchDev& m, float px, float py, float pz) {
-  const float gx = px * (float)m.nx - 0.5f, gy = py * (float)m.ny - 0.5f, gz = pz * (float)m.nz - 0.5f;
-  if (!(gx > -1.0f && gy > -1.0f && gz > -1.0f && gx < (float)m.nx && gy < (float)m.ny && gz < (float)m.nz))
-    return 0.0f;
+  const float gx0 = px * (float)m.nx - 0.5f, gy0 = py * (float)m.ny - 0.5f, gz0 = pz * (float)m.nz - 0.5f;
+  const bool inside = gx0 > -1.0f && gy0 > -1.0f && gz0 > -1.0f && gx0 < (float)m.nx && gy0 < (float)m.ny &&
+                      gz0 < (float)m.nz;
+  // branch-free: outside points are moved to the origin for the loads and give 0
+  const float gx = inside ? gx0 : 0.0f, gy = inside ? gy0 : 0.0f, gz = inside ? gz0 : 0.0f;
   const float fx0 = floorf(gx), fy0 = floorf(gy), fz0 = floorf(gz);
   const int i = (int)fx0, j = (int)fy0, k = (int)fz0;
   const float fx = gx - fx0, fy = gy - fy0, fz = gz - fz0;
@@ -47,7 +49,7 @@ __device__ __forceinline__ float sample_sigma_linear(const MarchDev& m, float px
   const float c01 = wx0 * r[zb + ya + ia] + wx1 * r[zb + ya + ib];
   const float c11 = wx0 * r[zb + yb + ia] + wx1 * r[zb + yb + ib];
   const float v = wz0 * (wy0 * c00 + wy1 * c10) + wz1 * (wy0 * c01 + wy1 * c11);
-  return m.sigma_scale * v;
+  return m.sigma_scale * v * (inside ? 1.0f : 0.0f);
 }
 
 // Bricked grid: index i' = i + 1 over [0, n + 1] (a zero layer on each side),
@@ -55,39 +57,114 @@ __device__ __forceinline__ float sample_sigma_linear(const MarchDev& m, float px
 // (5 x 5 x 5 values in a 128-float slot).  The 8 corners of the cell holding
 // a point are then in one brick at fixed offsets, and the zero layers make
 // the grid's zero border explicit.  Same value as sample_sigma_linear.
+//
+// The sample is branch-free so that a caller's batch of samples issues all
+// its loads before waiting on any: a point outside the support box is
+// moved to the grid origin for the loads and its value discarded.  Slot
+// offsets are 32-bit (the bricked grid is limited to 4 GiB).
 constexpr int kBrickSlot = 128;
-__device__ __forceinline__ float sample_sigma(const MarchDev& m, float px, float py, float pz) {
+
+// Address and interpolation weights of one bricked sample (split from the
+// loads so that callers can issue the loads of several samples together).
+struct BrickTap {
+  const float* r;    // corner (0,0,0) in its slot; the others at +1, +5, +6, +25, +26, +30, +31
+  float fx, fy, fz;  // fractions
+  float mask;        // 1 inside the support box, else 0
+};
+
+__device__ __forceinline__ BrickTap brick_tap(const MarchDev& m, float px, float py, float pz) {
   const float gx = px * (float)m.nx - 0.5f, gy = py * (float)m.ny - 0.5f, gz = pz * (float)m.nz - 0.5f;
-  if (!(gx > -1.0f && gy > -1.0f && gz > -1.0f && gx < (float)m.nx && gy < (float)m.ny && gz < (float)m.nz))
-    return 0.0f;
-  const float fx0 = floorf(gx), fy0 = floorf(gy), fz0 = floorf(gz);
-  const int i = (int)fx0 + 1, j = (int)fy0 + 1, k = (int)fz0 + 1;  // in [0, n]
-  const float fx = gx - fx0, fy = gy - fy0, fz = gz - fz0;
-  const int brick = ((k >> 2) * m.nby + (j >> 2)) * m.nbx + (i >> 2);
-  const float* r = m.brick + (size_t)brick * kBrickSlot + ((k & 3) * 25 + (j & 3) * 5 + (i & 3));
-  const float c00 = (1.0f - fx) * r[0] + fx * r[1];
-  const float c10 = (1.0f - fx) * r[5] + fx * r[6];
-  const float c01 = (1.0f - fx) * r[25] + fx * r[26];
-  const float c11 = (1.0f - fx) * r[30] + fx * r[31];
-  const float v = (1.0f - fz) * ((1.0f - fy) * c00 + fy * c10) + fz * ((1.0f - fy) * c01 + fy * c11);
-  return m.sigma_scale * v;
+  const bool inside = gx > -1.0f && gy > -1.0f && gz > -1.0f && gx < (float)m.nx && gy < (float)m.ny &&
+                      gz < (float)m.nz;
+  // outside points are moved to the origin for the loads (their value is masked)
+  const float cx = inside ? gx : 0.0f, cy = inside ? gy : 0.0f, cz = inside ? gz : 0.0f;
+  const float fx0 = floorf(cx), fy0 = floorf(cy), fz0 = floorf(cz);
+  const uint32_t i = (uint32_t)((int)fx0 + 1), j = (uint32_t)((int)fy0 + 1), k = (uint32_t)((int)fz0 + 1);
+  const uint32_t brick = ((k >> 2) * (uint32_t)m.nby + (j >> 2)) * (uint32_t)m.nbx + (i >> 2);
+  BrickTap t;
+  t.r = m.brick + (brick * (uint32_t)kBrickSlot + ((k & 3u) * 25u + (j & 3u) * 5u + (i & 3u)));
+  t.fx = cx - fx0;
+  t.fy = cy - fy0;
+  t.fz = cz - fz0;
+  t.mask = inside ? 1.0f : 0.0f;
+  return t;
+}
+
+struct BrickVals {
+  float v[8];
+};
+__device__ __forceinline__ BrickVals brick_load(const BrickTap& t) {
+  BrickVals c;
+  c.v[0] = t.r[0];
+  c.v[1] = t.r[1];
+  c.v[2] = t.r[5];
+  c.v[3] = t.r[6];
+  c.v[4] = t.r[25];
+  c.v[5] = t.r[26];
+  c.v[6] = t.r[30];
+  c.v[7] = t.r[31];
+  return c;
+}
+// sigma_scale x the trilinear value, times the inside mask (a multiply, not a
+// select, which the compiler would turn back into a branch around the loads)
+__device__ __forceinline__ float brick_lerp(const MarchDev& m, const BrickTap& t, const BrickVals& c) {
+  const float c00 = (1.0f - t.fx) * c.v[0] + t.fx * c.v[1];
+  const float c10 = (1.0f - t.fx) * c.v[2] + t.fx * c.v[3];
+  const float c01 = (1.0f - t.fx) * c.v[4] + t.fx * c.v[5];
+  const float c11 = (1.0f - t.fx) * c.v[6] + t.fx * c.v[7];
+  const float v = (1.0f - t.fz) * ((1.0f - t.fy) * c00 + t.fy * c10) + t.fz * ((1.0f - t.fy) * c01 + t.fy * c11);
+  return m.sigma_scale * v * t.mask;
+}
+
+__device__ __forceinline__ float sample_sigma(const MarchDev& m, float px, float py, float pz) {
+  const BrickTap t = brick_tap(m, px, py, pz);
+  return brick_lerp(m, t, brick_load(t));
+}
+
+// N samples: all addresses, then all loads, then all interpolations.
+template <int N>
+__device__ __forceinline__ void sample_batch(const MarchDev& m, const float (&px)[N], const float (&py)[N],
+                                             const float (&pz)[N], float (&out)[N]) {
+  BrickTap t[N];
+  BrickVals c[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) t[q] = brick_tap(m, px[q], py[q], pz[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) c[q] = brick_load(t[q]);
+  // keep the scheduler from sinking the loads next to their uses
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int q = 0; q < N; ++q) out[q] = brick_lerp(m, t[q], c[q]);
 }
 
 // Fill the bricked grid from the caller's linear grid (HBM-bound copy; once
-// per grid).  One lane per slot entry; entries 125..127 are padding.
+// per march).  Workgroup = 32 consecutive bricks along x at one (by, bz): it
+// stages the 25 source rows they cover (5 y x 5 z, 4*32+1 floats each) in
+// LDS with coalesced reads, then writes the 32 slots (16 KB, contiguous)
+// with coalesced stores.  Slot entries 125..127 are zero padding.
+constexpr int kRelayBricks = 32, kRelayRow = 4 * kRelayBricks + 1;
 __global__ __launch_bounds__(256) void relayout_bricks(const float* __restrict__ rho, int nx, int ny, int nz, int nbx,
-                                                       int nby, int nbz, float* __restrict__ brick) {
-  const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (long)nbx * nby * nbz * kBrickSlot) return;
-  const int s = e % kBrickSlot;
-  const long b = e / kBrickSlot;
-  float v = 0.0f;
-  if (s < 125) {
-    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / ((long)nbx * nby);
-    const int i = 4 * bx + s % 5 - 1, j = 4 * by + (s / 5) % 5 - 1, k = 4 * bz + s / 25 - 1;
+                                                       int nby, float* __restrict__ brick, int* __restrict__ ctr) {
+  __shared__ float rows[25][kRelayRow];
+  // the march's band counters (if any) start at zero
+  if (ctr && threadIdx.x < 8 && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) ctr[threadIdx.x] = 0;
+  const int bx0 = blockIdx.x * kRelayBricks, by = blockIdx.y, bz = blockIdx.z;
+  for (int e = threadIdx.x; e < 25 * kRelayRow; e += 256) {
+    const int r = e / kRelayRow, x = e - r * kRelayRow;
+    const int i = 4 * bx0 + x - 1, j = 4 * by + r % 5 - 1, k = 4 * bz + r / 5 - 1;
+    float v = 0.0f;
     if (i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz) v = rho[((size_t)k * ny + j) * nx + i];
+    rows[r][x] = v;
   }
-  brick[e] = v;
+  __syncthreads();
+  const int nb = min(kRelayBricks, nbx - bx0);
+  float* out = brick + (((size_t)bz * nby + by) * nbx + bx0) * kBrickSlot;
+  for (int e = threadIdx.x; e < nb * kBrickSlot; e += 256) {
+    const int b = e / kBrickSlot, s = e - b * kBrickSlot;
+    float v = 0.0f;
+    if (s < 125) v = rows[(s / 25) * 5 + (s / 5) % 5][4 * b + s % 5];
+    out[e] = v;
+  }
 }
 
 template <bool BRICK>
@@ -155,7 +232,8 @@ __device__ __forceinline__ float light_transmittance(const MarchDev& m, V3 x, V3
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float t = (float)(k + j) * h;
-      s[j] = k + j <= kmax ? sample<BRICK>(m, x.x + t * l.x, x.y + t * l.y, x.z + t * l.z) : 0.0f;
+      const float v = sample<BRICK>(m, x.x + t * l.x, x.y + t * l.y, x.z + t * l.z);
+      s[j] = k + j <= kmax ? v : 0.0f;
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -166,37 +244,31 @@ __device__ __forceinline__ float light_transmittance(const MarchDev& m, V3 x, V3
   return expf(-acc * h);
 }
 
-// The two side-light marches (+l and -l) of one point in one loop, two
-// samples of each per iteration, so that four gathers are in flight.  Each
-// march sums its samples in order and stops at its own termination limit;
-// the results equal two calls of light_transmittance.
-__device__ __forceinline__ void top_bottom_transmittance(const MarchDev& m, V3 x, V3 l, bool want_t, bool want_b,
-                                                         float* Tt, float* Tb) {
+// Transmittance toward one light on the bricked grid: the samples of the
+// march are gathered four at a time (all loads issued before any is used)
+// and summed in order; the march stops at the termination limit.  Same
+// result as light_transmittance<true>.
+__device__ __forceinline__ float light_transmittance_batched(const MarchDev& m, V3 x, V3 l) {
   const float h = m.h, lim = m.tau_max / h;
-  int kt = want_t ? light_steps(m, x, l, h) : 0;
-  int kb = want_b ? light_steps(m, x, v3(-l.x, -l.y, -l.z), h) : 0;
-  float at = 0.0f, ab = 0.0f;
-  bool dead_t = false, dead_b = false;
-  for (int k = 1; k <= kt || k <= kb; k += 2) {
-    float st[2], sb[2];
+  const int kmax = light_steps(m, x, l, h);
+  float acc = 0.0f;
+  for (int k = 1; k <= kmax; k += 4) {
+    float px[4], py[4], pz[4], sv[4];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < 4; ++q) {
       const float t = (float)(k + q) * h;
-      st[q] = k + q <= kt ? sample<true>(m, x.x + t * l.x, x.y + t * l.y, x.z + t * l.z) : 0.0f;
-      sb[q] = k + q <= kb ? sample<true>(m, x.x - t * l.x, x.y - t * l.y, x.z - t * l.z) : 0.0f;
+      px[q] = x.x + t * l.x;
+      py[q] = x.y + t * l.y;
+      pz[q] = x.z + t * l.z;
     }
+    sample_batch<4>(m, px, py, pz, sv);
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      at += st[q];
-      dead_t = dead_t || at > lim;
-      ab += sb[q];
-      dead_b = dead_b || ab > lim;
+    for (int q = 0; q < 4; ++q) {
+      acc += k + q <= kmax ? sv[q] : 0.0f;
+      if (acc > lim) return 0.0f;
     }
-    if (dead_t) kt = 0;
-    if (dead_b) kb = 0;
   }
-  *Tt = dead_t ? 0.0f : expf(-at * h);
-  *Tb = dead_b ? 0.0f : expf(-ab * h);
+  return expf(-acc * h);
 }
 
 __device__ __forceinline__ void tile_pixel(int* i, int* j) {
@@ -205,13 +277,16 @@ __device__ __forceinline__ void tile_pixel(int* i, int* j) {
   *j = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
 }
 
-// Pixel of this lane under an XCD-aware tile order.  Workgroups are handed to
-// the 8 XCDs round robin by their linear id, so XCD e runs the blocks with
-// blockIdx.x = e (mod 8); the map gives those blocks one contiguous band of
-// 16x16 tiles (of screen columns, or rows when the light marches run
-// horizontally on screen), so each XCD's L2 holds the slab of the volume its
-// band sees instead of the whole grid.
-__device__ __forceinline__ bool banded_pixel(const TileMap& tm, int* i, int* j) {
+// Pixel of this lane's quad under an XCD-aware tile order.  Workgroups are
+// handed to the 8 XCDs round robin by their linear id, so XCD e runs the
+// blocks with blockIdx.x = e (mod 8); the map gives those blocks one
+// contiguous band of 8x8 pixel tiles (of screen columns, or rows when the
+// light marches run horizontally on screen), so each XCD's L2 holds the slab
+// of the volume its band sees instead of the whole grid.  A workgroup of 256
+// lanes covers one tile with four lanes per pixel; each wavefront an 8x2
+// block.
+constexpr int kTile = 8;
+__device__ __forceinline__ bool banded_quad_pixel(const TileMap& tm, int* i, int* j) {
   const int b = blockIdx.x;
   const int L = (b & 7) * tm.per_xcd + (b >> 3);
   if (L >= tm.tiles_x * tm.tiles_y) return false;
@@ -223,9 +298,9 @@ __device__ __forceinline__ bool banded_pixel(const TileMap& tm, int* i, int* j) 
     tx = L / tm.tiles_y;
     ty = L - tx * tm.tiles_y;
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  *i = tx * 16 + (wave & 1) * 8 + (lane & 7);
-  *j = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+  const int q = threadIdx.x >> 2;
+  *i = tx * kTile + (q & 7);
+  *j = ty * kTile + (q >> 3);
   return true;
 }
 
@@ -244,116 +319,237 @@ __device__ __forceinline__ V3 side_light(V3 d, int light_set) {
   return light_set == LNM_LIGHTS_LEFT_RIGHT ? normalize3(cross3(v3(-d.x, -d.y, -d.z), top)) : top;
 }
 
+// Sum and maximum over the 64 lanes of a wavefront.
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
 // The march runs in three kernels so that its dominant cost, the light
-// marches (two per primary sample), is spread over one lane per
-// (pixel, sample) instead of serialised inside one lane per pixel:
-//   1. march_primary: one lane per pixel walks the primary samples, writes
-//      T and D, and records (t_n, A_n, T_{n-1}) of every sample with A_n != 0;
-//   2. march_lights: one lane per recorded sample marches toward the top and
-//      bottom lights and stores A_n L_n;
+// marches (two per primary sample), is spread over one lane per recorded
+// sample and light instead of serialised inside one lane per pixel:
+//   1. march_primary: four lanes per pixel walk the primary samples, write
+//      T and D, and record (t_n, A_n, T_{n-1}) of every sample with a
+//      nonzero weight in [k][P] planes; each wavefront then appends
+//      (pixel, k) of its records, k-major, to its XCD band's work list;
+//   2. march_lights: one lane per work-list entry and light marches toward
+//      that light and stores its transmittance at (light, k, pixel);
 //   3. march_accumulate: one lane per pixel sums A_n L_n in sample order.
-// All three read the bricked grid filled by relayout_bricks.
+// The work lists keep the light-march lanes dense and spatially coherent (a
+// wave takes neighbouring pixels at similar depths) whatever the per-pixel
+// sample counts are; all three kernels read the bricked grid.
+// One optical-depth step, the same float operations in both passes.
+__device__ __forceinline__ float depth_step(float L, float sig, float h) { return L + sig * h; }
+
+// Primary march with four lanes per pixel: lane s of the quad takes the s-th
+// quarter of the pixel's samples.  Pass 1 sums each segment's optical depth
+// (in sample order) and counts its records; a prefix over the quad gives
+// each lane the depth before its segment and its first record index.
+// Pass 2 re-gathers the segment (cache hits) and forms, per sample, the
+// depth tau_n = tau_before + (running sum), T_{n-1}, A_n, the depth D and
+// early termination, writing the records.  The depth before segment s + 1
+// is the same float sum as lane s's last tau_n, and the running sums only
+// grow, so a segment starts only if no earlier one terminated.
 __global__ __launch_bounds__(256) void march_primary(MarchDev m, CamDev c, TileMap tm, MarchBuf buf,
                                                      float* __restrict__ guide) {
   int i, j;
-  if (!banded_pixel(tm, &i, &j) || i >= c.W || j >= c.H) return;
-  V3 o, d;
-  camera_ray(c, i, j, &o, &d);
+  if (!banded_quad_pixel(tm, &i, &j)) return;  // whole workgroup past the last tile
+  const int s = threadIdx.x & 3;
+  const bool inside = i < c.W && j < c.H;
   const uint32_t pix = (uint32_t)j * (uint32_t)c.W + (uint32_t)i;
-  float u = 0.0f;
-  if (m.jitter_on) {
-    const uint64_t key = m.seed ^ ((uint64_t)m.frame << 32) ^ (uint64_t)pix;
-    u = (float)(uint32_t)(splitmix64(key) >> 40) * (1.0f / 16777216.0f);
-  }
   const float h = m.h;
-  float tau = 0.0f, Tprev = 1.0f, Tout = 1.0f, D = 0.0f;
-  int cnt = 0;
-  float t0, t1;
-  if (clip_support(m, o, d, &t0, &t1)) {
-    const int n0 = max(1, (int)ceilf(t0 / h - u)), n1 = (int)floorf(t1 / h - u);
-    bool done = false;
-    // gathers of four samples are issued together, then the samples are
-    // processed one at a time in order
-    for (int nb = n0; nb <= n1 && !done; nb += 4) {
-      float sg[4];
+  V3 o = v3(0.0f, 0.0f, 0.0f), d = v3(0.0f, 0.0f, 1.0f);
+  float u = 0.0f;
+  int n0 = 1, n1 = 0;  // sample range [n0, n1] (empty by default)
+  if (inside) {
+    camera_ray(c, i, j, &o, &d);
+    if (m.jitter_on) {
+      const uint64_t key = m.seed ^ ((uint64_t)m.frame << 32) ^ (uint64_t)pix;
+      u = (float)(uint32_t)(splitmix64(key) >> 40) * (1.0f / 16777216.0f);
+    }
+    float t0, t1;
+    if (clip_support(m, o, d, &t0, &t1)) {
+      n0 = max(1, (int)ceilf(t0 / h - u));
+      n1 = (int)floorf(t1 / h - u);
+    }
+  }
+  const int len = max(0, n1 - n0 + 1), seg = (len + 3) >> 2;
+  const int a0 = n0 + s * seg, a1 = min(n1, a0 + seg - 1);
+  const bool riemann = m.quadrature == LNM_QUAD_RIEMANN;
+  // pass 1: the segment's optical depth and record count
+  float L = 0.0f;
+  int nrec = 0;
+  for (int nb = a0; nb <= a1; nb += 4) {
+    float px[4], py[4], pz[4], sg[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float t = ((float)(nb + q) + u) * h;
+      px[q] = o.x + t * d.x;
+      py[q] = o.y + t * d.y;
+      pz[q] = o.z + t * d.z;
+    }
+    sample_batch<4>(m, px, py, pz, sg);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (nb + q > a1) break;
+      L = depth_step(L, sg[q], h);
+      const float alpha = riemann ? sg[q] * h : -expm1f(-sg[q] * h);
+      nrec += alpha != 0.0f;
+    }
+  }
+  // prefix over the quad (lanes 4q .. 4q+3 of the wave)
+  const float L0 = __shfl(L, 0, 4), L1 = __shfl(L, 1, 4), L2 = __shfl(L, 2, 4), L3 = __shfl(L, 3, 4);
+  const int c0 = __shfl(nrec, 0, 4), c1 = __shfl(nrec, 1, 4), c2 = __shfl(nrec, 2, 4);
+  float tb = 0.0f;
+  int kb = 0;
+  if (s > 0) { tb = tb + L0; kb += c0; }
+  if (s > 1) { tb = tb + L1; kb += c1; }
+  if (s > 2) { tb = tb + L2; kb += c2; }
+  const float tau_all = ((0.0f + L0) + L1) + L2 + L3;  // depth after the last sample
+  // pass 2: samples, records, depth, termination
+  int k = kb, dn = 0;
+  bool term = false;
+  if (tb <= m.tau_max) {
+    float Lr = 0.0f, Tprev = expf(-tb);
+    for (int nb = a0; nb <= a1 && !term; nb += 4) {
+      float px[4], py[4], pz[4], sg[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const float t = ((float)(nb + q) + u) * h;
-        sg[q] = nb + q <= n1 ? sample<true>(m, o.x + t * d.x, o.y + t * d.y, o.z + t * d.z) : 0.0f;
+        px[q] = o.x + t * d.x;
+        py[q] = o.y + t * d.y;
+        pz[q] = o.z + t * d.z;
       }
+      sample_batch<4>(m, px, py, pz, sg);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int n = nb + q;
-        if (done || n > n1) break;
-        const float t = ((float)n + u) * h;
+        if (term || n > a1) break;
         const float sig = sg[q];
-        if (D == 0.0f && sig > m.depth_tau) D = (float)n * h;
-        tau += sig * h;
-        const float T = expf(-tau);
-        const float A = m.quadrature == LNM_QUAD_RIEMANN ? Tprev * sig * h : Tprev * -expm1f(-sig * h);
-        if (A != 0.0f && cnt < buf.K) {
-          const size_t r = (size_t)cnt * buf.P + pix;
-          buf.t[r] = t;
-          buf.a[r] = A;
+        if (dn == 0 && sig > m.depth_tau) dn = n;
+        Lr = depth_step(Lr, sig, h);
+        const float tau = tb + Lr;
+        const float alpha = riemann ? sig * h : -expm1f(-sig * h);
+        if (alpha != 0.0f && k < buf.K) {
+          const size_t r = (size_t)k * buf.P + pix;
+          buf.t[r] = ((float)n + u) * h;
+          buf.a[r] = Tprev * alpha;
           buf.tp[r] = Tprev;
-          ++cnt;
+          ++k;
         }
-        Tprev = T;
-        Tout = T;
-        if (tau > m.tau_max) {
-          Tout = 0.0f;
-          done = true;
-        }
+        Tprev = expf(-tau);
+        if (tau > m.tau_max) term = true;
       }
     }
   }
-  buf.cnt[pix] = cnt;
-  float* g = guide + 3 * (size_t)pix;
-  g[1] = Tout;
-  g[2] = D;
-}
-
-// grid: (banded pixel tiles, recorded sample index k)
-__global__ __launch_bounds__(256) void march_lights(MarchDev m, CamDev c, TileMap tm, MarchBuf buf) {
-  int i, j;
-  if (!banded_pixel(tm, &i, &j) || i >= c.W || j >= c.H) return;
-  const uint32_t pix = (uint32_t)j * (uint32_t)c.W + (uint32_t)i;
-  const int k = blockIdx.y;
-  if (k >= buf.cnt[pix]) return;
-  const size_t r = (size_t)k * buf.P + pix;
-  // front light: marching toward w retraces the earlier primary samples, so
-  // its transmittance is T_{n-1}
-  float L = m.wf * buf.tp[r];
-  if (m.wt != 0.0f || m.wb != 0.0f) {
-    V3 o, d;
-    camera_ray(c, i, j, &o, &d);
-    const float t = buf.t[r];
-    const V3 x = v3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
-    float Tt, Tb;
-    top_bottom_transmittance(m, x, side_light(d, m.light_set), m.wt != 0.0f, m.wb != 0.0f, &Tt, &Tb);
-    if (m.wt != 0.0f) L += m.wt * Tt;
-    if (m.wb != 0.0f) L += m.wb * Tb;
+  // quad results: records, depth, transmittance
+  const int w0 = __shfl(k - kb, 0, 4), w1 = __shfl(k - kb, 1, 4), w2 = __shfl(k - kb, 2, 4),
+            w3 = __shfl(k - kb, 3, 4);
+  const int cnt = w0 + w1 + w2 + w3;
+  const int big = 0x7fffffff;
+  int dmin = dn ? dn : big;
+  dmin = min(dmin, __shfl_xor(dmin, 1, 4));
+  dmin = min(dmin, __shfl_xor(dmin, 2, 4));
+  const int any_term = __shfl_xor((int)term, 1, 4) | __shfl_xor((int)term, 2, 4) | __shfl_xor((int)term, 3, 4) |
+                       (int)term;
+  if (inside && s == 0) {
+    buf.cnt[pix] = cnt;
+    float* g = guide + 3 * (size_t)pix;
+    g[1] = any_term ? 0.0f : expf(-tau_all);
+    g[2] = dmin == big ? 0.0f : (float)dmin * h;
   }
-  buf.al[r] = buf.a[r] * L;
+  // append this wave's records to the band's list: one atomic per wave, then
+  // k-major order; record k of a pixel is held by the quad lane whose
+  // [kb, k) range contains it
+  const int total = wave_sum(s == 0 ? cnt : 0);
+  if (total == 0) return;
+  const int band = blockIdx.x & 7, lane = threadIdx.x & 63;
+  int base = 0;
+  if (lane == 0) base = atomicAdd(buf.ctr + band, total);
+  base = __shfl(base, 0);
+  int2* rec = buf.rec + (size_t)band * buf.cap;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int kmax = wave_max(k);
+  int off = base;
+  for (int kk = 0; kk < kmax; ++kk) {
+    const bool mine = kk >= kb && kk < k;
+    const unsigned long long has = __ballot(mine);
+    if (mine) rec[off + __popcll(has & below)] = make_int2((int)pix, kk);
+    off += __popcll(has);
+  }
 }
 
-__global__ __launch_bounds__(256) void march_accumulate(MarchBuf buf, float* __restrict__ guide) {
+// One lane per (work-list entry, light).  Grid: 8 bands x `slots`
+// workgroups; block b serves band b % 8 (the XCD that ran that band's
+// primary waves under round-robin placement).  The band's list is cut into
+// 256-entry chunks and each chunk into two units, one per light, so a
+// workgroup marches one light direction; block b takes units b / 8,
+// b / 8 + slots, ...  Result: T toward the top (or first side) light in
+// tl[0][k][pixel], toward the bottom (second side) light in tl[1][k][pixel].
+__global__ __launch_bounds__(256) void march_lights(MarchDev m, CamDev c, MarchBuf buf, int slots) {
+  const int band = blockIdx.x & 7;
+  const int n = buf.ctr[band];
+  const int units = 2 * ((n + 255) / 256);
+  const int2* rec = buf.rec + (size_t)band * buf.cap;
+  for (int unit = blockIdx.x >> 3; unit < units; unit += slots) {
+    const int light = unit & 1;
+    if ((light ? m.wb : m.wt) == 0.0f) continue;
+    const int r = (unit >> 1) * 256 + threadIdx.x;
+    if (r >= n) continue;
+    const int2 e = rec[r];
+    const int pix = e.x, k = e.y;
+    const size_t q = (size_t)k * buf.P + pix;
+    V3 o, d;
+    camera_ray(c, pix % c.W, pix / c.W, &o, &d);
+    const float t = buf.t[q];
+    V3 l = side_light(d, m.light_set);
+    if (light) l = v3(-l.x, -l.y, -l.z);
+    buf.tl[(size_t)light * buf.K * buf.P + q] =
+        light_transmittance_batched(m, v3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z), l);
+  }
+}
+
+// Zero the band counters (when no relayout kernel runs first to do it).
+__global__ void march_clear(int* __restrict__ ctr) {
+  if (threadIdx.x < 8) ctr[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(256) void march_accumulate(MarchDev m, MarchBuf buf, float* __restrict__ guide) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= buf.P) return;
   const int cnt = buf.cnt[p];
-  const float* al = buf.al + p;
-  const size_t P = (size_t)buf.P;
+  const size_t P = (size_t)buf.P, KP = (size_t)buf.K * P;
+  const float wf = m.wf, wt = m.wt, wb = m.wb;
   float Ls = 0.0f;
-  int k = 0;
-  // eight loads in flight, summed in sample order
-  for (; k + 8 <= cnt; k += 8) {
-    float v[8];
+  // eight records' loads issued together, then summed in sample order; the
+  // front light's transmittance is T_{n-1} (marching toward w retraces the
+  // earlier primary samples)
+  for (int k0 = 0; k0 < cnt; k0 += 8) {
+    float a[8], tp[8], t0[8], t1[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = al[(size_t)(k + q) * P];
+    for (int q = 0; q < 8; ++q) {
+      const size_t r = (size_t)min(k0 + q, cnt - 1) * P + p;
+      a[q] = buf.a[r];
+      tp[q] = buf.tp[r];
+      t0[q] = wt != 0.0f ? buf.tl[r] : 0.0f;
+      t1[q] = wb != 0.0f ? buf.tl[KP + r] : 0.0f;
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) Ls += v[q];
+    for (int q = 0; q < 8; ++q) {
+      if (k0 + q >= cnt) break;
+      float L = wf * tp[q];
+      if (wt != 0.0f) L += wt * t0[q];
+      if (wb != 0.0f) L += wb * t1[q];
+      Ls += a[q] * L;
+    }
   }
-  for (; k < cnt; ++k) Ls += al[(size_t)k * P];
   guide[3 * (size_t)p] = Ls;
 }
 
@@ -406,39 +602,61 @@ int march_capacity(const MarchDev& m) {
 
 static size_t a256(size_t x) { return (x + 255) / 256 * 256; }
 static int bricks_along(int n) { return (n >> 2) + 1; }
-static size_t brick_bytes(const MarchDev& m) {
-  return sizeof(float) * kBrickSlot * (size_t)bricks_along(m.nx) * bricks_along(m.ny) * bricks_along(m.nz);
+size_t bricks_bytes(int nx, int ny, int nz) {
+  return sizeof(float) * kBrickSlot * (size_t)bricks_along(nx) * bricks_along(ny) * bricks_along(nz);
 }
 
-size_t march_scratch_bytes(const MarchDev& m, int K, int P) {
-  const size_t plane = a256(sizeof(float) * (size_t)K * P);
-  return 4 * plane + a256(sizeof(int) * (size_t)P) + a256(brick_bytes(m));
+constexpr size_t kLightSlots = 512;  // workgroups per band in march_lights
+static int tiles_per_band(int W, int H) { return (((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) + 7) / 8; }
+
+// Scratch: [K][P] planes t, A, T_{n-1}, T_top, T_bottom; per-pixel counts; 8 band
+// counters; 8 band work lists of (pixel, k) with room for every sample of
+// the band's pixels; the bricked grid unless the caller supplies it.
+size_t march_scratch_bytes(const MarchDev& m, int K, int W, int H) {
+  const size_t P = (size_t)W * H, plane = a256(sizeof(float) * (size_t)K * P);
+  const size_t cap = (size_t)tiles_per_band(W, H) * kTile * kTile * K;
+  return 5 * plane + a256(sizeof(int) * P) + 256 + a256(8 * cap * sizeof(int2)) +
+         (m.brick ? 0 : a256(bricks_bytes(m.nx, m.ny, m.nz)));
 }
 
-MarchBuf march_buffers(void* ws, const MarchDev& m, int K, int P) {
+MarchBuf march_buffers(void* ws, const MarchDev& m, int K, int W, int H) {
   char* p = static_cast<char*>(ws);
-  const size_t plane = a256(sizeof(float) * (size_t)K * P);
+  const size_t P = (size_t)W * H, plane = a256(sizeof(float) * (size_t)K * P);
   MarchBuf b;
   b.t = reinterpret_cast<float*>(p);
   b.a = reinterpret_cast<float*>(p + plane);
   b.tp = reinterpret_cast<float*>(p + 2 * plane);
-  b.al = reinterpret_cast<float*>(p + 3 * plane);
-  b.cnt = reinterpret_cast<int*>(p + 4 * plane);
-  b.brick = reinterpret_cast<float*>(p + 4 * plane + a256(sizeof(int) * (size_t)P));
+  b.tl = reinterpret_cast<float*>(p + 3 * plane);  // two planes
+  p += 5 * plane;
+  b.cnt = reinterpret_cast<int*>(p);
+  p += a256(sizeof(int) * P);
+  b.ctr = reinterpret_cast<int*>(p);
+  p += 256;
+  b.cap = (size_t)tiles_per_band(W, H) * kTile * kTile * K;
+  b.rec = reinterpret_cast<int2*>(p);
+  p += a256(8 * b.cap * sizeof(int2));
+  b.brick = m.brick ? nullptr : reinterpret_cast<float*>(p);
   b.nbx = bricks_along(m.nx);
   b.nby = bricks_along(m.ny);
   b.nbz = bricks_along(m.nz);
   b.K = K;
-  b.P = P;
+  b.P = (int)P;
   return b;
+}
+
+hipError_t launch_relayout(const MarchDev& m, float* bricks, int* ctr, hipStream_t s) {
+  const int nbx = bricks_along(m.nx), nby = bricks_along(m.ny), nbz = bricks_along(m.nz);
+  hipLaunchKernelGGL(relayout_bricks, dim3((nbx + kRelayBricks - 1) / kRelayBricks, nby, nbz), dim3(256), 0, s, m.rho,
+                     m.nx, m.ny, m.nz, nbx, nby, bricks, ctr);
+  return hipGetLastError();
 }
 
 // Band screen rows instead of columns when the top light of the central ray
 // runs more horizontally than vertically on screen.
 static TileMap tile_map(const CamDev& c) {
   TileMap tm;
-  tm.tiles_x = (c.W + 15) / 16;
-  tm.tiles_y = (c.H + 15) / 16;
+  tm.tiles_x = (c.W + kTile - 1) / kTile;
+  tm.tiles_y = (c.H + kTile - 1) / kTile;
   tm.per_xcd = (tm.tiles_x * tm.tiles_y + 7) / 8;
   const double w[3] = {-c.f[0], -c.f[1], -c.f[2]};
   double top[3] = {w[1], -w[0], 0.0};  // w x z
@@ -455,17 +673,22 @@ static TileMap tile_map(const CamDev& c) {
 
 hipError_t launch_march(const MarchDev& m0, const CamDev& cam, const MarchBuf& buf, float* guide, hipStream_t s) {
   MarchDev m = m0;
-  m.brick = buf.brick;
   m.nbx = buf.nbx;
   m.nby = buf.nby;
   m.nbz = buf.nbz;
-  const long entries = (long)buf.nbx * buf.nby * buf.nbz * kBrickSlot;
-  hipLaunchKernelGGL(relayout_bricks, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s, m.rho, m.nx, m.ny,
-                     m.nz, buf.nbx, buf.nby, buf.nbz, buf.brick);
+  if (!m.brick) {  // build the bricks in the scratch (this also zeroes the band counters)
+    hipError_t e = launch_relayout(m, buf.brick, buf.ctr, s);
+    if (e != hipSuccess) return e;
+    m.brick = buf.brick;
+  } else {
+    hipLaunchKernelGGL(march_clear, dim3(1), dim3(64), 0, s, buf.ctr);
+  }
   const TileMap tm = tile_map(cam);
   hipLaunchKernelGGL(march_primary, dim3(8 * tm.per_xcd), dim3(256), 0, s, m, cam, tm, buf, guide);
-  hipLaunchKernelGGL(march_lights, dim3(8 * tm.per_xcd, buf.K), dim3(256), 0, s, m, cam, tm, buf);
-  hipLaunchKernelGGL(march_accumulate, dim3((buf.P + 255) / 256), dim3(256), 0, s, buf, guide);
+  // enough workgroups to fill the chip a few times over; each loops over its band
+  const int slots = (int)std::min<size_t>((buf.cap + 255) / 256, kLightSlots);
+  hipLaunchKernelGGL(march_lights, dim3(8 * slots), dim3(256), 0, s, m, cam, buf, slots);
+  hipLaunchKernelGGL(march_accumulate, dim3((buf.P + 255) / 256), dim3(256), 0, s, m, buf, guide);
   return hipGetLastError();
 }
 

@@ -27,9 +27,11 @@ EXPORTS = [
     "lnm_composite", "lnm_profile_enable", "lnm_profile_read", "lnm_trainer_state_bytes", "lnm_frame_workspace_bytes",
     "lnm_train_workspace_bytes", "lnm_trainer_create", "lnm_trainer_destroy", "lnm_train_grad", "lnm_train_step",
     "lnm_trainer_read_params", "lnm_trainer_save", "lnm_trainer_load", "lnm_trainer_infer", "lnm_calibrate_amax",
-    "lnm_shadow_map_sphere", "lnm_composite_shadowed",
+    "lnm_shadow_map_sphere", "lnm_composite_shadowed", "lnm_bricks_bytes", "lnm_make_bricks",
+    "lnm_adapters_param_count", "lnm_adapters_device_bytes", "lnm_adapters_create", "lnm_adapters_destroy",
+    "lnm_adapters_workspace_bytes", "lnm_infer_adapters",
 ]
-K_MARCH, K_CONV, K_HEAD, K_COMPOSITE, K_REFERENCE = range(5)
+K_MARCH, K_CONV, K_HEAD, K_COMPOSITE, K_REFERENCE, K_ADAPTERS = range(6)
 
 
 class LnmError(RuntimeError):
@@ -40,7 +42,7 @@ class LnmError(RuntimeError):
 
 class Volume(C.Structure):
     _fields_ = [("density", C.c_void_p), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
-                ("sigma_scale", C.c_float)]
+                ("sigma_scale", C.c_float), ("bricks", C.c_void_p)]
 
 
 class Camera(C.Structure):
@@ -116,6 +118,21 @@ def lib():
         L.lnm_composite_shadowed.restype = i32
         L.lnm_composite_shadowed.argtypes = [vp, C.POINTER(Camera), C.POINTER(Light), i32, C.POINTER(ShadowFrame),
                                              C.POINTER(vp), i32, i32, i32, vp, vp, vp, vp, vp]
+        L.lnm_adapters_param_count.restype = sz
+        L.lnm_adapters_param_count.argtypes = [i32]
+        L.lnm_adapters_device_bytes.restype = sz
+        L.lnm_adapters_device_bytes.argtypes = [i32]
+        L.lnm_adapters_create.restype = i32
+        L.lnm_adapters_create.argtypes = [vp, vp, vp, sz, vp, sz, vp, C.POINTER(vp)]
+        L.lnm_adapters_destroy.argtypes = [vp]
+        L.lnm_adapters_workspace_bytes.restype = sz
+        L.lnm_adapters_workspace_bytes.argtypes = [vp, i32, i32, i32]
+        L.lnm_infer_adapters.restype = i32
+        L.lnm_infer_adapters.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, sz, vp]
+        L.lnm_bricks_bytes.restype = sz
+        L.lnm_bricks_bytes.argtypes = [i32, i32, i32]
+        L.lnm_make_bricks.restype = i32
+        L.lnm_make_bricks.argtypes = [vp, C.POINTER(Volume), vp, sz, vp]
         L.lnm_calibrate_amax.restype = i32
         L.lnm_calibrate_amax.argtypes = [vp, vp, i32, i32, i32, vp, vp, i32, vp, sz, vp]
         L.lnm_profile_enable.restype = i32
@@ -181,7 +198,8 @@ def make_params(step_voxels, depth_tau=0.1, ert_eps=1e-6, jitter=True, seed=0, f
     return p
 
 
-def make_volume(density, sigma_scale) -> Volume:
+def make_volume(density, sigma_scale, bricks=None) -> Volume:
+    """bricks: optional device tensor from Context.make_bricks(density)."""
     import torch
 
     if not isinstance(density, torch.Tensor) or density.dtype != torch.float32 or not density.is_cuda \
@@ -191,6 +209,12 @@ def make_volume(density, sigma_scale) -> Volume:
     v.density = density.data_ptr()
     v.nz, v.ny, v.nx = (int(s) for s in density.shape)
     v.sigma_scale = float(sigma_scale)
+    if bricks is not None:
+        need = int(lib().lnm_bricks_bytes(v.nx, v.ny, v.nz))
+        if not isinstance(bricks, torch.Tensor) or not bricks.is_cuda or not bricks.is_contiguous() \
+                or bricks.numel() * bricks.element_size() < need:
+            raise ValueError(f"bricks must be a contiguous CUDA tensor of at least {need} bytes")
+        v.bricks = bricks.data_ptr()
     return v
 
 
@@ -227,15 +251,28 @@ class Context:
         return n.value, ms.value
 
     # -- march
-    def march_workspace_bytes(self, density, sigma_scale, cam, params: MarchParams) -> int:
-        vol = make_volume(density, sigma_scale)
+    def make_bricks(self, density, out=None, stream=None):
+        """Bricked copy of a density grid for repeated marches (lnm_make_bricks)."""
+        import torch
+
+        vol = make_volume(density, 1.0)
+        n = int(lib().lnm_bricks_bytes(vol.nx, vol.ny, vol.nz))
+        if out is None:
+            out = torch.empty(n // 4, dtype=torch.float32, device=density.device)
+        check(lib().lnm_make_bricks(self.handle, C.byref(vol), _ptr(out), out.numel() * out.element_size(),
+                                    _stream(stream)))
+        return out
+
+    def march_workspace_bytes(self, density, sigma_scale, cam, params: MarchParams, bricks=None) -> int:
+        vol = make_volume(density, sigma_scale, bricks)
         c = make_camera(cam)
         return int(lib().lnm_march_workspace_bytes(C.byref(vol), C.byref(c), C.byref(params)))
 
-    def march(self, density, sigma_scale, cam, params: MarchParams, out=None, workspace=None, stream=None):
+    def march(self, density, sigma_scale, cam, params: MarchParams, out=None, workspace=None, stream=None,
+              bricks=None):
         import torch
 
-        vol = make_volume(density, sigma_scale)
+        vol = make_volume(density, sigma_scale, bricks)
         c = make_camera(cam)
         if out is None:
             out = torch.empty((c.height, c.width, 3), dtype=torch.float32, device=density.device)
@@ -374,10 +411,10 @@ class Net:
                               _ptr(workspace), workspace.numel(), _stream(stream)))
         return out if guide.dim() == 4 else out[0]
 
-    def frame_workspace(self, density, sigma_scale, cam, params: MarchParams):
+    def frame_workspace(self, density, sigma_scale, cam, params: MarchParams, bricks=None):
         import torch
 
-        vol = make_volume(density, sigma_scale)
+        vol = make_volume(density, sigma_scale, bricks)
         c = make_camera(cam)
         n = int(lib().lnm_frame_workspace_bytes(self.handle, C.byref(vol), C.byref(c), C.byref(params)))
         if n == 0:
@@ -385,10 +422,10 @@ class Net:
         return torch.empty(n, dtype=torch.uint8, device=density.device)
 
     def frame(self, density, sigma_scale, cam, params: MarchParams, lights=(), guide=None, lightmaps=None, rgba=None,
-              workspace=None, stream=None, shade=True):
+              workspace=None, stream=None, shade=True, bricks=None):
         import torch
 
-        vol = make_volume(density, sigma_scale)
+        vol = make_volume(density, sigma_scale, bricks)
         c = make_camera(cam)
         H, W = c.height, c.width
         dev = density.device
@@ -397,7 +434,7 @@ class Net:
         if shade and rgba is None:
             rgba = torch.empty((H, W, 4), dtype=torch.float32, device=dev)
         if workspace is None:
-            workspace = self.frame_workspace(density, sigma_scale, cam, params)
+            workspace = self.frame_workspace(density, sigma_scale, cam, params, bricks)
         arr, n = make_lights(lights)
         check(lib().lnm_frame(self.ctx.handle, self.handle, C.byref(vol), C.byref(c), C.byref(params), arr, n,
                               _ptr(guide), _ptr(lightmaps), _ptr(rgba) if shade else None, _ptr(workspace),
@@ -533,3 +570,54 @@ def save_checkpoint(path, ck: dict):
 def load_checkpoint(path) -> dict:
     with np.load(path, allow_pickle=False) as z:
         return {k: z[k] if z[k].ndim else z[k].item() for k in z.files}
+
+
+class Adapters:
+    """Four NAFBlock channel adapters bound to a Net (lnm_adapters_*)."""
+
+    def __init__(self, net: Net, params, stream=None):
+        import torch
+
+        self.net, self.ctx = net, net.ctx
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        nbytes = int(lib().lnm_adapters_device_bytes(net.base))
+        if nbytes == 0:
+            raise LnmError(LNM_ERR_UNSUPPORTED, f"no adapters for base width {net.base}")
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=net.buf.device)
+        h = C.c_void_p()
+        check(lib().lnm_adapters_create(self.ctx.handle, net.handle, p.ctypes.data_as(C.c_void_p), p.size,
+                                        _ptr(self.buf), nbytes, _stream(stream), C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.lnm_adapters_destroy(self.handle)
+            self.handle = None
+
+    def workspace(self, batch, H, W):
+        import torch
+
+        n = int(lib().lnm_adapters_workspace_bytes(self.handle, batch, H, W))
+        if n == 0:
+            raise LnmError(LNM_ERR_SHAPE, "no adapter workspace for these sizes")
+        return torch.empty(n, dtype=torch.uint8, device=self.buf.device)
+
+    def infer(self, guide, out=None, extra=None, with_extra=True, workspace=None, stream=None):
+        """guide [B][H][W][3] -> (lightmaps [B][H][W][6], extra [B][H][W][2] or None)."""
+        import torch
+
+        g = guide if guide.dim() == 4 else guide.unsqueeze(0)
+        B, H, W, _ = g.shape
+        _need(g, (B, H, W, 3), "guide")
+        if out is None:
+            out = torch.empty((B, H, W, 6), dtype=torch.float32, device=g.device)
+        if with_extra and extra is None:
+            extra = torch.empty((B, H, W, 2), dtype=torch.float32, device=g.device)
+        if workspace is None:
+            workspace = self.workspace(B, H, W)
+        check(lib().lnm_infer_adapters(self.ctx.handle, self.handle, B, H, W, _ptr(g), _ptr(out),
+                                       _ptr(extra) if with_extra else None, _ptr(workspace), workspace.numel(),
+                                       _stream(stream)))
+        if guide.dim() == 4:
+            return out, extra
+        return out[0], (extra[0] if extra is not None else None)

@@ -1,7 +1,7 @@
 """Continuous-batching frame server for many smoke instances.
 
-Each request asks for the next frame of one smoke instance (its density grid
-stays resident on the device).  The scheduler admits pending requests in
+Each request asks for the next frame of one smoke instance (its density grid,
+and optionally the march's bricked copy of it, stay resident on the device).  The scheduler admits pending requests in
 arrival order as stream slots and HBM budget free up: requests of the same
 view resolution are grouped into a batch, each is marched from its own grid
 and camera, the batch goes through one U-Net call, and each result is shaded
@@ -40,6 +40,12 @@ class Instance:
     start_deg: float = 0.0
     light: tuple = ((0.0, 1.0, 0.0), (1.0, 1.0, 1.0))
     seed: int = 0
+    bricks: object = None  # optional bricked copy of the grid (lnm_make_bricks), resident like the grid
+
+    def prepare(self, ctx):
+        """Build the march's bricked copy of the (static) grid once, so each
+        frame's march skips the relayout."""
+        self.bricks = ctx.make_bricks(self.density)
 
     def camera(self, frame: int):
         a = math.radians(self.start_deg + self.deg_per_frame * frame)
@@ -93,7 +99,8 @@ class Backend:
 
     def _march_bytes(self, inst, frame):
         prm = lnm.make_params(inst.step_voxels, seed=inst.seed, frame=frame)
-        return self.ctx.march_workspace_bytes(inst.density, inst.sigma_scale, inst.camera(frame), prm)
+        return self.ctx.march_workspace_bytes(inst.density, inst.sigma_scale, inst.camera(frame), prm,
+                                              bricks=inst.bricks)
 
     def launch(self, slot: int, reqs, instances, keep_ids=()):
         import torch
@@ -111,7 +118,7 @@ class Backend:
                 inst = instances[r.instance]
                 prm = lnm.make_params(inst.step_voxels, seed=inst.seed, frame=r.frame)
                 self.ctx.march(inst.density, inst.sigma_scale, inst.camera(r.frame), prm, out=guide[b],
-                               workspace=mws, stream=st)
+                               workspace=mws, stream=st, bricks=inst.bricks)
             self.net.infer(guide, out=lm, workspace=ws, stream=st)
             for b, r in enumerate(reqs):
                 inst = instances[r.instance]

@@ -79,3 +79,66 @@ def unet_flops(levels: int, base: int, batch: int, h: int, w: int) -> float:
     for _, div, n, k in flops_per_pixel_table(levels, base):
         total += 2.0 * batch * (h * w / div) * n * k
     return total
+
+
+# ---------------------------------------------------------- channel adapters
+ADAPTER_GROUPS = ("front/back", "left/right", "up/down", "alpha/emissive")
+
+
+def adapter_tensors(c: int):
+    """[(name, shape, fan_in or None)] of one adapter (NAFBlock of width c +
+    1x1 head to 2 channels) in parameter-file order; fan_in None marks
+    layer-norm weights/biases, the residual scales and biases."""
+    return [("ln1_w", (c,), None), ("ln1_b", (c,), None),
+            ("conv1_w", (2 * c, c), c), ("conv1_b", (2 * c,), None),
+            ("dw_w", (2 * c, 3, 3), 9), ("dw_b", (2 * c,), None),
+            ("sca_w", (c, c), c), ("sca_b", (c,), None),
+            ("conv3_w", (c, c), c), ("conv3_b", (c,), None),
+            ("beta", (c,), None),
+            ("ln2_w", (c,), None), ("ln2_b", (c,), None),
+            ("conv4_w", (2 * c, c), c), ("conv4_b", (2 * c,), None),
+            ("conv5_w", (c, c), c), ("conv5_b", (c,), None),
+            ("gamma", (c,), None),
+            ("head_w", (2, c), c), ("head_b", (2,), None)]
+
+
+def adapter_param_count(c: int) -> int:
+    return 4 * sum(int(np.prod(s)) for _, s, _ in adapter_tensors(c))
+
+
+def adapter_params(c: int, seed: int = 0, init: str = "random") -> np.ndarray:
+    """Parameters of the four adapters (group order of ADAPTER_GROUPS).
+
+    init='identity': conv weights He-normal, biases 0, layer norms (1, 0) and
+    beta = gamma = 0, so each NAFBlock starts as the identity (its published
+    initialisation).  init='random' (parity tests): layer-norm weights
+    U[0.8, 1.2], biases U[-0.1, 0.1], beta and gamma U[-0.5, 0.5], so every
+    term of the block is exercised."""
+    ws = substream(seed, "adapter_weights")
+    us = substream(seed, "adapter_other")
+    parts = []
+    for _ in range(4):
+        for name, shape, fan_in in adapter_tensors(c):
+            n = int(np.prod(shape))
+            if fan_in is not None:
+                parts.append(ws.normal(n) * np.sqrt(2.0 / fan_in))
+            elif init == "identity":
+                parts.append(np.ones(n) if name in ("ln1_w", "ln2_w") else np.zeros(n))
+            elif init == "random":
+                u = us.uniform(n)
+                if name in ("ln1_w", "ln2_w"):
+                    parts.append(0.8 + 0.4 * u)
+                elif name in ("beta", "gamma"):
+                    parts.append(u - 0.5)
+                else:
+                    parts.append(0.2 * u - 0.1)
+            else:
+                raise ValueError(init)
+    return np.ascontiguousarray(np.concatenate(parts).astype(np.float32))
+
+
+def adapter_flops(c: int, batch: int, h: int, w: int) -> float:
+    """Algorithmic FLOPs of the four adapters (2 per multiply-add of the
+    1x1 and depthwise convolutions and the head)."""
+    per_px = 2 * c * c + 18 * c + c * c + 2 * c * c + c * c + 2 * c  # conv1, dw, conv3, conv4, conv5, head
+    return 2.0 * 4 * batch * h * w * per_px

@@ -120,3 +120,37 @@ def test_dynamic_scene_full_size_sampled(ctx, orc):
 
     cam = orbit_camera(37)
     _both(ctx, orc, vol, 8.0, cam, wl.step_voxels, "dynamic256_1024px_stride16", stride=16, frame=37)
+
+
+def _bricks_numpy(vol):
+    """The bricked layout as documented for lnm_make_bricks, built with numpy."""
+    nz, ny, nx = vol.shape
+    nb = [(n >> 2) + 1 for n in (nx, ny, nz)]
+    pad = np.zeros((4 * nb[2] + 1, 4 * nb[1] + 1, 4 * nb[0] + 1), np.float32)
+    pad[1:nz + 1, 1:ny + 1, 1:nx + 1] = vol
+    out = np.zeros((nb[2], nb[1], nb[0], 128), np.float32)
+    for bz in range(nb[2]):
+        for by in range(nb[1]):
+            for bx in range(nb[0]):
+                blk = pad[4 * bz:4 * bz + 5, 4 * by:4 * by + 5, 4 * bx:4 * bx + 5]
+                out[bz, by, bx, :125] = blk.ravel()
+    return out.ravel()
+
+
+def test_prebuilt_bricks(ctx, orc):
+    """lnm_make_bricks writes the documented layout, and a march on prebuilt
+    bricks equals the march that builds them itself, with a smaller workspace."""
+    from paper_2604_03748_amd import lnm
+
+    for shape in ((20, 28, 36), (5, 3, 9), (64, 64, 64)):
+        vol = make_volume(shape, 5, 17, noise_amp=0.3)
+        log(f"bricks of {shape}")
+        dens = to_dev(vol)
+        br = ctx.make_bricks(dens)
+        assert np.array_equal(to_host(br), _bricks_numpy(vol))
+        cam = Camera(PERSPECTIVE, (-1.3, 2.1, 1.7), target=(0.55, 0.45, 0.5), up=(0.2, 0.1, 1.0), width=45, height=37)
+        p = lnm.make_params(1.5, seed=5)
+        a = to_host(ctx.march(dens, 6.0, cam, p))
+        b = to_host(ctx.march(dens, 6.0, cam, p, bricks=br))
+        assert np.array_equal(a, b)
+        assert ctx.march_workspace_bytes(dens, 6.0, cam, p, bricks=br) < ctx.march_workspace_bytes(dens, 6.0, cam, p)
