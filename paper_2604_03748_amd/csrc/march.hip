@@ -138,32 +138,43 @@ __device__ __forceinline__ void sample_batch(const MarchDev& m, const float (&px
 }
 
 // Fill the bricked grid from the caller's linear grid (HBM-bound copy; once
-// per march).  Workgroup = 32 consecutive bricks along x at one (by, bz): it
-// stages the 25 source rows they cover (5 y x 5 z, 4*32+1 floats each) in
-// LDS with coalesced reads, then writes the 32 slots (16 KB, contiguous)
+// per march, or once per grid with lnm_make_bricks).  Workgroup = 31
+// consecutive bricks along x at one (by, bz): it stages the 25 source rows
+// they cover (5 y x 5 z rows of 4*31+1 = 125 floats) in LDS, each lane
+// issuing its 12 or 13 row loads together (out-of-grid entries read a valid
+// address and are zeroed), then writes the 31 slots (15.5 KB, contiguous)
 // with coalesced stores.  Slot entries 125..127 are zero padding.
-constexpr int kRelayBricks = 32, kRelayRow = 4 * kRelayBricks + 1;
+constexpr int kRelayBricks = 31, kRelayRow = 4 * kRelayBricks + 1;
 __global__ __launch_bounds__(256) void relayout_bricks(const float* __restrict__ rho, int nx, int ny, int nz, int nbx,
                                                        int nby, float* __restrict__ brick, int* __restrict__ ctr) {
   __shared__ float rows[25][kRelayRow];
   // the march's band counters (if any) start at zero
   if (ctr && threadIdx.x < 8 && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) ctr[threadIdx.x] = 0;
   const int bx0 = blockIdx.x * kRelayBricks, by = blockIdx.y, bz = blockIdx.z;
-  for (int e = threadIdx.x; e < 25 * kRelayRow; e += 256) {
-    const int r = e / kRelayRow, x = e - r * kRelayRow;
-    const int i = 4 * bx0 + x - 1, j = 4 * by + r % 5 - 1, k = 4 * bz + r / 5 - 1;
-    float v = 0.0f;
-    if (i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz) v = rho[((size_t)k * ny + j) * nx + i];
-    rows[r][x] = v;
+  const int x = threadIdx.x & 127, r0 = threadIdx.x >> 7;  // column, first row (rows r0, r0 + 2, ...)
+  const int i = 4 * bx0 + x - 1;
+  float v[13];
+#pragma unroll
+  for (int q = 0; q < 13; ++q) {
+    const int r = r0 + 2 * q;
+    const int j = 4 * by + r % 5 - 1, k = 4 * bz + r / 5 - 1;
+    const bool ok = x < kRelayRow && r < 25 && i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
+    const size_t src = ok ? ((size_t)k * ny + j) * nx + i : 0;
+    v[q] = rho[src] * (ok ? 1.0f : 0.0f);
+  }
+#pragma unroll
+  for (int q = 0; q < 13; ++q) {
+    const int r = r0 + 2 * q;
+    if (x < kRelayRow && r < 25) rows[r][x] = v[q];
   }
   __syncthreads();
   const int nb = min(kRelayBricks, nbx - bx0);
   float* out = brick + (((size_t)bz * nby + by) * nbx + bx0) * kBrickSlot;
   for (int e = threadIdx.x; e < nb * kBrickSlot; e += 256) {
     const int b = e / kBrickSlot, s = e - b * kBrickSlot;
-    float v = 0.0f;
-    if (s < 125) v = rows[(s / 25) * 5 + (s / 5) % 5][4 * b + s % 5];
-    out[e] = v;
+    float val = 0.0f;
+    if (s < 125) val = rows[(s / 25) * 5 + (s / 5) % 5][4 * b + s % 5];
+    out[e] = val;
   }
 }
 

@@ -73,11 +73,19 @@ _lib = None
 
 
 def lib():
-    """Load liblnm.so; raises if it has not been built."""
+    """Load liblnm.so; raises if it has not been built.
+
+    torch is imported first: the library and torch's ROCm build both need
+    the HIP runtime libamdhip64.so.7, and the process must end up with
+    torch's copy (the one torch's device memory and streams belong to).
+    Loading the library first would bind the runtime from the library's own
+    search path, and torch would then find no GPU."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        import torch  # noqa: F401  (binds torch's HIP runtime before the library's)
+
         L = C.CDLL(LIB_PATH)
         vp, i32, sz = C.c_void_p, C.c_int32, C.c_size_t
         L.lnm_abi_struct_size.restype = sz
