@@ -20,6 +20,7 @@ Prints one JSON line.
 
 Usage: python bench.py [--steps K] [--warmup W] [--dtype fp32|bf16|fp8] [--only]
        [--no-cpu-baseline] [--no-serve] [--no-dynamic] [--no-precision] [--no-adapters]
+       [--no-two-streams]
 """
 from __future__ import annotations
 
@@ -350,6 +351,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--no-dynamic", action="store_true", help="skip the dynamic-scene mode")
     ap.add_argument("--no-adapters", action="store_true", help="skip the channel-adapter mode")
+    ap.add_argument("--no-two-streams", action="store_true", help="skip the two-stream throughput pass")
     ap.add_argument("--dynamic-frames", type=int, default=60)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -399,11 +401,12 @@ def main():
                       act_scales=amax if dt == "fp8" else None)
         r = measure(lnm, ctx, net, dens, wl, light, args.steps, args.warmup, stream)
         r["roofline"] = conv_roofline(wl, r["stage"], dt)
-        r["two_streams"] = measure_two_streams(lnm, net, dens, wl, light, args.steps, args.warmup)
+        if not args.no_two_streams:
+            r["two_streams"] = measure_two_streams(lnm, net, dens, wl, light, args.steps, args.warmup)
         res[dt] = r
         stages = ", ".join("%s: %.1f us" % (k, v["us_per_frame"]) for k, v in r["stage"].items())
-        log(f"{dt}: {r['ms_per_step']:.4f} ms/frame, {r['fps']:.1f} frames/s "
-            f"({r['two_streams']['fps']:.1f} on two streams), stages {stages}")
+        two = f" ({r['two_streams']['fps']:.1f} on two streams)" if "two_streams" in r else ""
+        log(f"{dt}: {r['ms_per_step']:.4f} ms/frame, {r['fps']:.1f} frames/s{two}, stages {stages}")
         del net
 
     main_r = res[args.dtype]
@@ -426,9 +429,9 @@ def main():
                    "unet_base": wl.base, "batch": 1, "lights": 1},
         "roofline": main_r["roofline"],
         "stages_us_per_frame": {k: round(v["us_per_frame"], 2) for k, v in main_r["stage"].items()},
-        "frames_per_s_two_streams": round(main_r["two_streams"]["fps"], 2),
+        "frames_per_s_two_streams": round(main_r["two_streams"]["fps"], 2) if "two_streams" in main_r else None,
         "modes": {dt: {"value": round(r["fps"], 2), "ms_per_step": round(r["ms_per_step"], 5),
-                       "frames_per_s_two_streams": round(r["two_streams"]["fps"], 2),
+                       "frames_per_s_two_streams": round(r["two_streams"]["fps"], 2) if "two_streams" in r else None,
                        "roofline": r["roofline"],
                        "stages_us_per_frame": {k: round(v["us_per_frame"], 2) for k, v in r["stage"].items()}}
                   for dt, r in res.items() if dt != args.dtype},

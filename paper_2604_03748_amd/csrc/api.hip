@@ -295,12 +295,15 @@ static void pack_layer(const LayerDesc& d, int precision, const float* w, const 
 }
 
 // Split-K factor of conv layer i at level size h x w (tiles of 8 x 16 pixels
-// x 32 output channels); the 3-channel input layer is never split.
+// x 32 output channels); the 3-channel input layer is never split.  The
+// split grows until the layer has 256 workgroups (fp32) or 512 (bf16, fp8),
+// the targets measured fastest per precision with the split-K reductions
+// counted.
 static int layer_splits(const lnm_net_s* net, int i, int B, int h, int w) {
   const LayerDesc& d = net->layers[i];
   if (d.ci == 3) return 1;
   const long wgs = (long)((w + 15) / 16) * ((h + 7) / 8) * B * (d.co_pad / kBN);
-  return conv_splits(wgs, d.ci_pad / d.ck);
+  return conv_splits(wgs, d.ci_pad / d.ck, net->precision == LNM_FP32 ? 256 : 512);
 }
 
 static int layer_level(int L, int i) { return i < 2 * L ? i / 2 : L - 2 - (i - 2 * L) / 2; }
@@ -834,7 +837,7 @@ lnm_status lnm_make_bricks(lnm_ctx ctx, const lnm_volume* vol, float* bricks, si
   m.ny = vol->ny;
   m.nz = vol->nz;
   ProfScope ps(ctx, LNM_K_MARCH, (hipStream_t)stream);
-  LNM_HIP_CHECK(launch_relayout(m, bricks, nullptr, (hipStream_t)stream));
+  LNM_HIP_CHECK(launch_relayout(m, bricks, (hipStream_t)stream));
   return LNM_OK;
 }
 

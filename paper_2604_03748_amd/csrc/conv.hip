@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a) {
     if (more) LNM_FETCH(ch + 1);
     const float* si = s_in[cur];
     const float* sw = s_w[cur];
-#pragma unroll 1
+#pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3, dx = tap - 3 * (tap / 3);
       if constexpr (CK == 16) {
@@ -405,10 +405,11 @@ hipError_t launch_splitk_reduce(const ConvArgs& a, int out_type, hipStream_t s) 
   return hipGetLastError();
 }
 
-int conv_splits(long wgs, int nchunks) {
-  // aim for about two workgroups per CU; keep at least two chunks per split
+int conv_splits(long wgs, int nchunks, int target) {
+  // grow the split until the layer has `target` workgroups; keep at least
+  // two chunks per split
   int s = 1;
-  while (wgs * s < 512 && 2 * (s * 2) <= nchunks && s < 16) s *= 2;
+  while (wgs * s < target && 2 * (s * 2) <= nchunks && s < 16) s *= 2;
   return s;
 }
 

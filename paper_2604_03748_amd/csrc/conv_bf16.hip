@@ -168,7 +168,7 @@ __global__ __launch_bounds__(256) void conv3x3_bf16(ConvArgs a) {
     if (more) fetch(ch + 1);
     const uint16_t* si = s_in[cur];
     const uint16_t* sw = s_w[cur];
-#pragma unroll 3
+#pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3, dx = tap - 3 * (tap / 3);
       bf16x8 av[MF], bv[2];

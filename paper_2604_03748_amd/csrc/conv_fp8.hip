@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void conv3x3_fp8(ConvArgs a) {
     if (more) fetch(ch + 1);
     const uint8_t* si = s_in[cur];
     const uint8_t* sw = s_w[cur];
-#pragma unroll 3
+#pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3, dx = tap - 3 * (tap / 3);
       long av[MF], bv[2];

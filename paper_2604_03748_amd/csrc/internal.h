@@ -55,15 +55,16 @@ struct MarchBuf {
   float* tp;   // [K][P] transmittance before the sample, T_{n-1}
   float* tl;   // [2][K][P] transmittance toward the top / bottom (first / second side) light
   int* cnt;    // [P] recorded samples per pixel
-  int* ctr;    // [8] entries in each band's work list
-  int2* rec;   // [8][cap] (pixel, k) work lists of the light marches
-  size_t cap;  // entries per band list
+  int* ctr;    // [8] entries in each band's work list, then start[0..9) of the bands' tile ranges
+  int2* rec;   // work lists of the light marches, (pixel, k); band e's from entry start[e] * 64 * K
+  size_t cap;  // entries per band at equal bands (the lists hold 8 * cap)
   float* brick;
   int nbx, nby, nbz;
   int K, P;  // capacity per pixel, pixels
 };
 
-// XCD-aware order of 8x8 pixel tiles over a 1D grid of 8 * per_xcd blocks.
+// Band order of the 8x8 pixel tiles; per_xcd = tiles / 8 rounded up, the
+// primary march's workgroups per band.
 struct TileMap {
   int tiles_x, tiles_y, per_xcd, band_rows;
 };
@@ -74,7 +75,7 @@ size_t march_scratch_bytes(const MarchDev& m, int K, int W, int H);
 MarchBuf march_buffers(void* ws, const MarchDev& m, int K, int W, int H);
 size_t bricks_bytes(int nx, int ny, int nz);
 // ctr (optional): band counters zeroed by the same launch.
-hipError_t launch_relayout(const MarchDev& m, float* bricks, int* ctr, hipStream_t s);
+hipError_t launch_relayout(const MarchDev& m, float* bricks, hipStream_t s);
 hipError_t launch_march(const MarchDev& m, const CamDev& cam, const MarchBuf& buf, float* guide, hipStream_t s);
 hipError_t launch_reference(const MarchDev& m, const CamDev& cam, int srgb, float* lm, hipStream_t s);
 
@@ -117,7 +118,7 @@ struct ConvArgs {
 // output conversion of out_type (0 fp32, 1 bf16, 2 fp8).
 hipError_t launch_splitk_reduce(const ConvArgs& a, int out_type, hipStream_t s);
 // Splits for a layer launched with `wgs` workgroups over `nchunks` input chunks.
-int conv_splits(long wgs, int nchunks);
+int conv_splits(long wgs, int nchunks, int target);
 hipError_t launch_conv3x3_f32(int mode, int ck, const ConvArgs& a, hipStream_t s);
 hipError_t launch_conv3x3_bf16(int mode, const ConvArgs& a, hipStream_t s);
 hipError_t launch_conv3x3_fp8(int mode, const ConvArgs& a, hipStream_t s);

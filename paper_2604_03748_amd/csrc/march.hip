@@ -145,12 +145,10 @@ __device__ __forceinline__ void sample_batch(const MarchDev& m, const float (&px
 // address and are zeroed), then writes the 31 slots (15.5 KB, contiguous)
 // with coalesced stores.  Slot entries 125..127 are zero padding.
 constexpr int kRelayBricks = 31, kRelayRow = 4 * kRelayBricks + 1;
-__global__ __launch_bounds__(256) void relayout_bricks(const float* __restrict__ rho, int nx, int ny, int nz, int nbx,
-                                                       int nby, float* __restrict__ brick, int* __restrict__ ctr) {
-  __shared__ float rows[25][kRelayRow];
-  // the march's band counters (if any) start at zero
-  if (ctr && threadIdx.x < 8 && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) ctr[threadIdx.x] = 0;
-  const int bx0 = blockIdx.x * kRelayBricks, by = blockIdx.y, bz = blockIdx.z;
+__device__ __forceinline__ void relayout_block(const float* __restrict__ rho, int nx, int ny, int nz, int nbx, int nby,
+                                               float* __restrict__ brick, float (&rows)[25][kRelayRow], int bxb,
+                                               int by, int bz) {
+  const int bx0 = bxb * kRelayBricks;
   const int x = threadIdx.x & 127, r0 = threadIdx.x >> 7;  // column, first row (rows r0, r0 + 2, ...)
   const int i = 4 * bx0 + x - 1;
   float v[13];
@@ -176,6 +174,12 @@ __global__ __launch_bounds__(256) void relayout_bricks(const float* __restrict__
     if (s < 125) val = rows[(s / 25) * 5 + (s / 5) % 5][4 * b + s % 5];
     out[e] = val;
   }
+}
+
+__global__ __launch_bounds__(256) void relayout_bricks(const float* __restrict__ rho, int nx, int ny, int nz, int nbx,
+                                                       int nby, float* __restrict__ brick) {
+  __shared__ float rows[25][kRelayRow];
+  relayout_block(rho, nx, ny, nz, nbx, nby, brick, rows, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 template <bool BRICK>
@@ -288,31 +292,31 @@ __device__ __forceinline__ void tile_pixel(int* i, int* j) {
   *j = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
 }
 
-// Pixel of this lane's quad under an XCD-aware tile order.  Workgroups are
-// handed to the 8 XCDs round robin by their linear id, so XCD e runs the
-// blocks with blockIdx.x = e (mod 8); the map gives those blocks one
-// contiguous band of 8x8 pixel tiles (of screen columns, or rows when the
-// light marches run horizontally on screen), so each XCD's L2 holds the slab
-// of the volume its band sees instead of the whole grid.  A workgroup of 256
+// Screen tiles of 8x8 pixels are numbered in band order: L runs down the
+// screen columns of tiles (or along the rows when the light marches run
+// horizontally on screen), so a contiguous range of L is a screen band whose
+// light marches stay inside one slab of the volume.  A workgroup of 256
 // lanes covers one tile with four lanes per pixel; each wavefront an 8x2
 // block.
 constexpr int kTile = 8;
-__device__ __forceinline__ bool banded_quad_pixel(const TileMap& tm, int* i, int* j) {
-  const int b = blockIdx.x;
-  const int L = (b & 7) * tm.per_xcd + (b >> 3);
-  if (L >= tm.tiles_x * tm.tiles_y) return false;
-  int tx, ty;
+// start[0..8] of the band tile ranges, after the 8 band counters in the
+// march's 256-byte counter block
+constexpr int kBandStart = 16;
+__device__ __forceinline__ void tile_origin(const TileMap& tm, int L, int* tx, int* ty) {
   if (tm.band_rows) {
-    ty = L / tm.tiles_x;
-    tx = L - ty * tm.tiles_x;
+    *ty = L / tm.tiles_x;
+    *tx = L - *ty * tm.tiles_x;
   } else {
-    tx = L / tm.tiles_y;
-    ty = L - tx * tm.tiles_y;
+    *tx = L / tm.tiles_y;
+    *ty = L - *tx * tm.tiles_y;
   }
+}
+__device__ __forceinline__ void quad_pixel(const TileMap& tm, int L, int* i, int* j) {
+  int tx, ty;
+  tile_origin(tm, L, &tx, &ty);
   const int q = threadIdx.x >> 2;
   *i = tx * kTile + (q & 7);
   *j = ty * kTile + (q >> 3);
-  return true;
 }
 
 // Top surrogate light of a ray: normalize(w x z), or normalize(w x x) when w
@@ -367,10 +371,12 @@ __device__ __forceinline__ float depth_step(float L, float sig, float h) { retur
 // early termination, writing the records.  The depth before segment s + 1
 // is the same float sum as lane s's last tau_n, and the running sums only
 // grow, so a segment starts only if no earlier one terminated.
-__global__ __launch_bounds__(256) void march_primary(MarchDev m, CamDev c, TileMap tm, MarchBuf buf,
-                                                     float* __restrict__ guide) {
+// Tile `tile` (band order) of band `band`, whose work list starts at `list`.
+__device__ __forceinline__ void primary_tile(const MarchDev& m, const CamDev& c, const TileMap& tm,
+                                             const MarchBuf& buf, float* __restrict__ guide, int tile, int band,
+                                             int2* __restrict__ list) {
   int i, j;
-  if (!banded_quad_pixel(tm, &i, &j)) return;  // whole workgroup past the last tile
+  quad_pixel(tm, tile, &i, &j);
   const int s = threadIdx.x & 3;
   const bool inside = i < c.W && j < c.H;
   const uint32_t pix = (uint32_t)j * (uint32_t)c.W + (uint32_t)i;
@@ -480,41 +486,162 @@ __global__ __launch_bounds__(256) void march_primary(MarchDev m, CamDev c, TileM
   // [kb, k) range contains it
   const int total = wave_sum(s == 0 ? cnt : 0);
   if (total == 0) return;
-  const int band = blockIdx.x & 7, lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63;
   int base = 0;
   if (lane == 0) base = atomicAdd(buf.ctr + band, total);
   base = __shfl(base, 0);
-  int2* rec = buf.rec + (size_t)band * buf.cap;
   const unsigned long long below = (1ull << lane) - 1ull;
   const int kmax = wave_max(k);
   int off = base;
   for (int kk = 0; kk < kmax; ++kk) {
     const bool mine = kk >= kb && kk < k;
     const unsigned long long has = __ballot(mine);
-    if (mine) rec[off + __popcll(has & below)] = make_int2((int)pix, kk);
+    if (mine) list[off + __popcll(has & below)] = make_int2((int)pix, kk);
     off += __popcll(has);
   }
 }
 
-// One lane per (work-list entry, light).  Grid: 8 bands x `slots`
-// workgroups; block b serves band b % 8 (the XCD that ran that band's
-// primary waves under round-robin placement).  The band's list is cut into
-// 256-entry chunks and each chunk into two units, one per light, so a
-// workgroup marches one light direction; block b takes units b / 8,
-// b / 8 + slots, ...  Result: T toward the top (or first side) light in
-// tl[0][k][pixel], toward the bottom (second side) light in tl[1][k][pixel].
+// Band e = blockIdx.x % 8 (the XCD the block runs on under round-robin
+// placement) owns tiles [start[e], start[e + 1]) of the band order, chosen by
+// march_balance so that the bands carry equal estimated work; its work list
+// starts at entry start[e] * 64 * K, room for K records of every pixel it
+// owns.  The band's blocks take its tiles in turn.
+__global__ __launch_bounds__(256) void march_primary(MarchDev m, CamDev c, TileMap tm, MarchBuf buf,
+                                                     float* __restrict__ guide) {
+  const int band = blockIdx.x & 7, slots = gridDim.x >> 3;
+  const int* start = buf.ctr + kBandStart;
+  const int lo = start[band], hi = start[band + 1];
+  int2* list = buf.rec + (size_t)lo * (kTile * kTile) * (size_t)buf.K;
+  for (int L = lo + (int)(blockIdx.x >> 3); L < hi; L += slots) primary_tile(m, c, tm, buf, guide, L, band, list);
+}
+
+// Estimated cost of tile L: the primary samples of its centre ray (every
+// sample in the support box is taken, dense or empty) plus a fixed share.
+__device__ __forceinline__ int tile_cost(const MarchDev& m, const CamDev& c, const TileMap& tm, int L) {
+  int tx, ty;
+  tile_origin(tm, L, &tx, &ty);
+  const int i = min(tx * kTile + kTile / 2, c.W - 1), j = min(ty * kTile + kTile / 2, c.H - 1);
+  V3 o, d;
+  camera_ray(c, i, j, &o, &d);
+  float t0, t1;
+  const int n = clip_support(m, o, d, &t0, &t1) ? (int)fminf((t1 - t0) / m.h, 1e6f) : 0;
+  return n + 2;
+}
+
+// Zero the band counters and cut the band order of tiles into 8 ranges of
+// about equal estimated cost (start[0..8] after the counters).  The smoke
+// often covers a small part of the screen; equal screen bands would leave
+// most XCDs idle.  One workgroup of 256 lanes: per-lane sums over contiguous
+// tile runs, an LDS scan, then each tile goes to range floor(8 (prefix +
+// cost / 2) / total); all sums are integers, so the ranges are exact and
+// contiguous.  The first kCostCache tile costs are kept in LDS for the
+// second pass.
+constexpr int kBalanceThreads = 256, kCostCache = 2048;
+struct BalanceLds {
+  long long scan[2][kBalanceThreads];
+  int cost[kCostCache];
+  int first[8];
+};
+__device__ void balance_tiles(const MarchDev& m, const CamDev& c, const TileMap& tm, int* __restrict__ ctr,
+                              BalanceLds& sh) {
+  const int tid = threadIdx.x, ntiles = tm.tiles_x * tm.tiles_y;
+  const int per = (ntiles + kBalanceThreads - 1) / kBalanceThreads;
+  const int a = min(ntiles, tid * per), b = min(ntiles, a + per);
+  if (tid < 8) {
+    ctr[tid] = 0;
+    sh.first[tid] = ntiles;
+  }
+  long long sum = 0;
+  for (int L = a; L < b; ++L) {
+    const int cst = tile_cost(m, c, tm, L);
+    if (L < kCostCache) sh.cost[L] = cst;
+    sum += cst;
+  }
+  sh.scan[0][tid] = sum;
+  __syncthreads();
+  int cur = 0;
+  for (int o = 1; o < kBalanceThreads; o <<= 1) {  // inclusive scan (Hillis-Steele)
+    const long long v = sh.scan[cur][tid] + (tid >= o ? sh.scan[cur][tid - o] : 0);
+    sh.scan[cur ^ 1][tid] = v;
+    cur ^= 1;
+    __syncthreads();
+  }
+  const long long total = sh.scan[cur][kBalanceThreads - 1];
+  long long run = sh.scan[cur][tid] - sum;
+  for (int L = a; L < b; ++L) {
+    const int cst = L < kCostCache ? sh.cost[L] : tile_cost(m, c, tm, L);
+    const int e = (int)min(7LL, (8 * (2 * run + cst)) / (2 * total));
+    atomicMin(&sh.first[e], L);
+    run += cst;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int* start = ctr + kBandStart;
+    start[8] = ntiles;
+    for (int e = 7; e >= 1; --e) start[e] = min(sh.first[e], start[e + 1]);
+    start[0] = 0;
+  }
+}
+
+// The balance alone, when the march reads prebuilt bricks (otherwise it runs
+// in an extra workgroup of the relayout launch).
+__global__ __launch_bounds__(256) void march_balance(MarchDev m, CamDev c, TileMap tm, int* __restrict__ ctr) {
+  __shared__ BalanceLds sh;
+  balance_tiles(m, c, tm, ctr, sh);
+}
+
+// The march's relayout: the same blocks plus one z slice whose first block
+// cuts the screen tiles into the balanced band ranges (the others exit).
+__global__ __launch_bounds__(256) void relayout_balance(MarchDev m, CamDev c, TileMap tm, int* __restrict__ ctr,
+                                                        float* __restrict__ brick, int nbz) {
+  __shared__ union {
+    float rows[25][kRelayRow];
+    BalanceLds bal;
+  } sh;
+  if ((int)blockIdx.z == nbz) {
+    if (blockIdx.x == 0 && blockIdx.y == 0) balance_tiles(m, c, tm, ctr, sh.bal);
+    return;
+  }
+  relayout_block(m.rho, m.nx, m.ny, m.nz, m.nbx, m.nby, brick, sh.rows, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// One lane per (work-list entry, light).  The band lists, concatenated in
+// band order, are one spatially ordered sequence of N records; it is cut
+// into 8 equal contiguous ranges, one per XCD (block b serves range b % 8,
+// the XCD that runs it under round-robin placement), so every XCD and its
+// L2 take an eighth of the light marches even when the smoke covers only a
+// few screen bands, and each range is still a compact slab of the volume.
+// A range is cut into 256-entry chunks and each chunk into two units, one
+// per light, so a workgroup marches one light direction; block b takes
+// units b / 8, b / 8 + slots, ...  Result: T toward the top (or first side)
+// light in tl[0][k][pixel], toward the bottom (second side) light in
+// tl[1][k][pixel].
 __global__ __launch_bounds__(256) void march_lights(MarchDev m, CamDev c, MarchBuf buf, int slots) {
-  const int band = blockIdx.x & 7;
-  const int n = buf.ctr[band];
-  const int units = 2 * ((n + 255) / 256);
-  const int2* rec = buf.rec + (size_t)band * buf.cap;
+  int count[8], total = 0;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    count[e] = buf.ctr[e];
+    total += count[e];
+  }
+  const int part = blockIdx.x & 7;
+  const int lo = (int)((long)total * part / 8), hi = (int)((long)total * (part + 1) / 8);
+  const int units = 2 * ((hi - lo + 255) / 256);
   for (int unit = blockIdx.x >> 3; unit < units; unit += slots) {
     const int light = unit & 1;
     if ((light ? m.wb : m.wt) == 0.0f) continue;
-    const int r = (unit >> 1) * 256 + threadIdx.x;
-    if (r >= n) continue;
-    const int2 e = rec[r];
-    const int pix = e.x, k = e.y;
+    const int r = lo + (unit >> 1) * 256 + threadIdx.x;
+    if (r >= hi) continue;
+    // band and position of record r in the concatenated lists
+    int band = 0, off = r;
+#pragma unroll
+    for (int e = 0; e < 7; ++e) {
+      if (band == e && off >= count[e]) {
+        off -= count[e];
+        band = e + 1;
+      }
+    }
+    const int2 en = buf.rec[(size_t)buf.ctr[kBandStart + band] * (kTile * kTile) * (size_t)buf.K + off];
+    const int pix = en.x, k = en.y;
     const size_t q = (size_t)k * buf.P + pix;
     V3 o, d;
     camera_ray(c, pix % c.W, pix / c.W, &o, &d);
@@ -524,11 +651,6 @@ __global__ __launch_bounds__(256) void march_lights(MarchDev m, CamDev c, MarchB
     buf.tl[(size_t)light * buf.K * buf.P + q] =
         light_transmittance_batched(m, v3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z), l);
   }
-}
-
-// Zero the band counters (when no relayout kernel runs first to do it).
-__global__ void march_clear(int* __restrict__ ctr) {
-  if (threadIdx.x < 8) ctr[threadIdx.x] = 0;
 }
 
 __global__ __launch_bounds__(256) void march_accumulate(MarchDev m, MarchBuf buf, float* __restrict__ guide) {
@@ -655,10 +777,10 @@ MarchBuf march_buffers(void* ws, const MarchDev& m, int K, int W, int H) {
   return b;
 }
 
-hipError_t launch_relayout(const MarchDev& m, float* bricks, int* ctr, hipStream_t s) {
+hipError_t launch_relayout(const MarchDev& m, float* bricks, hipStream_t s) {
   const int nbx = bricks_along(m.nx), nby = bricks_along(m.ny), nbz = bricks_along(m.nz);
   hipLaunchKernelGGL(relayout_bricks, dim3((nbx + kRelayBricks - 1) / kRelayBricks, nby, nbz), dim3(256), 0, s, m.rho,
-                     m.nx, m.ny, m.nz, nbx, nby, bricks, ctr);
+                     m.nx, m.ny, m.nz, nbx, nby, bricks);
   return hipGetLastError();
 }
 
@@ -687,16 +809,17 @@ hipError_t launch_march(const MarchDev& m0, const CamDev& cam, const MarchBuf& b
   m.nbx = buf.nbx;
   m.nby = buf.nby;
   m.nbz = buf.nbz;
-  if (!m.brick) {  // build the bricks in the scratch (this also zeroes the band counters)
-    hipError_t e = launch_relayout(m, buf.brick, buf.ctr, s);
-    if (e != hipSuccess) return e;
-    m.brick = buf.brick;
-  } else {
-    hipLaunchKernelGGL(march_clear, dim3(1), dim3(64), 0, s, buf.ctr);
-  }
   const TileMap tm = tile_map(cam);
+  if (!m.brick) {  // build the bricks in the scratch; one extra block balances the bands
+    m.brick = buf.brick;
+    hipLaunchKernelGGL(relayout_balance, dim3((m.nbx + kRelayBricks - 1) / kRelayBricks, m.nby, m.nbz + 1), dim3(256),
+                       0, s, m, cam, tm, buf.ctr, buf.brick, m.nbz);
+  } else {
+    hipLaunchKernelGGL(march_balance, dim3(1), dim3(kBalanceThreads), 0, s, m, cam, tm, buf.ctr);
+  }
   hipLaunchKernelGGL(march_primary, dim3(8 * tm.per_xcd), dim3(256), 0, s, m, cam, tm, buf, guide);
-  // enough workgroups to fill the chip a few times over; each loops over its band
+  // enough workgroups to fill the chip a few times over; each loops over its
+  // eighth of the records
   const int slots = (int)std::min<size_t>((buf.cap + 255) / 256, kLightSlots);
   hipLaunchKernelGGL(march_lights, dim3(8 * slots), dim3(256), 0, s, m, cam, buf, slots);
   hipLaunchKernelGGL(march_accumulate, dim3((buf.P + 255) / 256), dim3(256), 0, s, m, buf, guide);
