@@ -31,28 +31,50 @@ struct Pad {
   static constexpr int w = CK == 16 ? 20 : 4;   // LDS floats per weight row
 };
 
+// Raw loads of one halo entry (four channels at pixel (y, x), both clamped
+// into the image): the pooled mode keeps its four source pixels, the others
+// one value.  They are combined and masked only when written to LDS, so the
+// loads of a chunk are all in flight together and nothing waits on them
+// before the matrix work of the current chunk.
 template <int MODE>
-__device__ __forceinline__ f4 gather4(const ConvArgs& a, int b, int y, int x, int c) {
+struct Halo {
+  f4 v[MODE == G_POOL ? 4 : 1];
+};
+
+template <int MODE>
+__device__ __forceinline__ Halo<MODE> halo_load(const ConvArgs& a, int b, int y, int x, int c) {
   const float* s0 = static_cast<const float*>(a.src0);
+  Halo<MODE> h;
   if constexpr (MODE == G_GUIDE) {
     const float* g = s0 + ((size_t)(b * a.H + y) * a.W + x) * 3;
-    return f4{g[0], g[1], g[2], 0.0f};
+    h.v[0] = f4{g[0], g[1], g[2], 0.0f};
   } else if constexpr (MODE == G_PLAIN) {
-    return *reinterpret_cast<const f4*>(s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c);
+    h.v[0] = *reinterpret_cast<const f4*>(s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c);
   } else if constexpr (MODE == G_POOL) {
-    const int W2 = 2 * a.W;
-    const float* p = s0 + ((size_t)(b * 2 * a.H + 2 * y) * W2 + 2 * x) * a.c0 + c;
-    const f4 v0 = *reinterpret_cast<const f4*>(p);
-    const f4 v1 = *reinterpret_cast<const f4*>(p + a.c0);
-    const f4 v2 = *reinterpret_cast<const f4*>(p + (size_t)W2 * a.c0);
-    const f4 v3 = *reinterpret_cast<const f4*>(p + (size_t)W2 * a.c0 + a.c0);
-    return f4{fmaxf(fmaxf(v0.x, v1.x), fmaxf(v2.x, v3.x)), fmaxf(fmaxf(v0.y, v1.y), fmaxf(v2.y, v3.y)),
-              fmaxf(fmaxf(v0.z, v1.z), fmaxf(v2.z, v3.z)), fmaxf(fmaxf(v0.w, v1.w), fmaxf(v2.w, v3.w))};
+    const size_t W2 = 2 * (size_t)a.W, c0 = (size_t)a.c0;
+    const float* p = s0 + ((size_t)(b * 2 * a.H + 2 * y) * W2 + 2 * x) * c0 + c;
+    h.v[0] = *reinterpret_cast<const f4*>(p);
+    h.v[1] = *reinterpret_cast<const f4*>(p + c0);
+    h.v[2] = *reinterpret_cast<const f4*>(p + W2 * c0);
+    h.v[3] = *reinterpret_cast<const f4*>(p + W2 * c0 + c0);
   } else {  // G_CONCAT_UP: channels [0, c0) from the skip, then the upsampled low-res tensor
-    if (c < a.c0) return *reinterpret_cast<const f4*>(s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c);
     const int Hl = a.H >> 1, Wl = a.W >> 1;
-    return *reinterpret_cast<const f4*>(static_cast<const float*>(a.src1) + ((size_t)(b * Hl + (y >> 1)) * Wl + (x >> 1)) * a.c1 + (c - a.c0));
+    const float* skip = s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c;
+    const float* up = static_cast<const float*>(a.src1) + ((size_t)(b * Hl + (y >> 1)) * Wl + (x >> 1)) * a.c1 +
+                      max(c - a.c0, 0);
+    h.v[0] = *reinterpret_cast<const f4*>(c < a.c0 ? skip : up);
   }
+  return h;
+}
+
+template <int MODE>
+__device__ __forceinline__ f4 halo_value(const Halo<MODE>& h, bool ok) {
+  f4 v = h.v[0];
+  if constexpr (MODE == G_POOL) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = fmaxf(fmaxf(h.v[0][e], h.v[1][e]), fmaxf(h.v[2][e], h.v[3][e]));
+  }
+  return ok ? v : f4{0.f, 0.f, 0.f, 0.f};
 }
 
 template <int CK, int MODE, int TH>
@@ -82,49 +104,52 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a) {
 #pragma unroll
     for (int nf = 0; nf < NF; ++nf) acc[mf][nf] = f4{0.f, 0.f, 0.f, 0.f};
 
-  // per chunk: the (TH+2) x 18 input halo and the weight slab [tap][n][c]
+  // per chunk: the (TH+2) x 18 input halo and the weight slab [tap][n][c];
+  // every load is unconditional (clamped index), masks apply at commit
   constexpr int NQ = (TH + 2) * kHW * (CK / 4), NW = 9 * kBN * CK / 4;
   constexpr int RQ = (NQ + 255) / 256, RW = (NW + 255) / 256;
-  f4 rq[RQ], rw[RW];
-#define LNM_FETCH(CH)                                                                          \
-  do {                                                                                         \
-    _Pragma("unroll") for (int r = 0; r < RQ; ++r) {                                           \
-      const int q = tid + 256 * r;                                                             \
-      f4 v = f4{0.f, 0.f, 0.f, 0.f};                                                           \
-      if (q < NQ) {                                                                            \
-        const int c4 = q % (CK / 4), p = q / (CK / 4);                                         \
-        const int y = y0 + p / kHW - 1, x = x0 + p % kHW - 1;                                  \
-        if (y >= 0 && y < a.H && x >= 0 && x < a.W) v = gather4<MODE>(a, b, y, x, (CH) * CK + 4 * c4); \
-      }                                                                                        \
-      rq[r] = v;                                                                               \
-    }                                                                                          \
-    const float* wsrc = wblk + (size_t)(CH) * 9 * kBN * CK;                                    \
-    _Pragma("unroll") for (int r = 0; r < RW; ++r) {                                           \
-      const int q = tid + 256 * r;                                                             \
-      if (q < NW) rw[r] = *reinterpret_cast<const f4*>(wsrc + 4 * q);                          \
-    }                                                                                          \
-  } while (0)
-#define LNM_COMMIT(BUF)                                                                        \
-  do {                                                                                         \
-    _Pragma("unroll") for (int r = 0; r < RQ; ++r) {                                           \
-      const int q = tid + 256 * r;                                                             \
-      if (q < NQ) *reinterpret_cast<f4*>(&s_in[BUF][(q / (CK / 4)) * PIN + 4 * (q % (CK / 4))]) = rq[r]; \
-    }                                                                                          \
-    _Pragma("unroll") for (int r = 0; r < RW; ++r) {                                           \
-      const int q = tid + 256 * r;                                                             \
-      if (q < NW) *reinterpret_cast<f4*>(&s_w[BUF][(q / (CK / 4)) * PW + 4 * (q % (CK / 4))]) = rw[r]; \
-    }                                                                                          \
-  } while (0)
+  Halo<MODE> rq[RQ];
+  f4 rw[RW];
+  unsigned ok = 0;
+  auto fetch = [&](int ch) {
+    ok = 0;
+#pragma unroll
+    for (int r = 0; r < RQ; ++r) {
+      const int q = min(tid + 256 * r, NQ - 1);
+      const int c4 = q % (CK / 4), p = q / (CK / 4);
+      const int y = y0 + p / kHW - 1, x = x0 + p % kHW - 1;
+      const bool in = tid + 256 * r < NQ && y >= 0 && y < a.H && x >= 0 && x < a.W;
+      ok |= (unsigned)in << r;
+      rq[r] = halo_load<MODE>(a, b, min(max(y, 0), a.H - 1), min(max(x, 0), a.W - 1), ch * CK + 4 * c4);
+    }
+    const float* wsrc = wblk + (size_t)ch * 9 * kBN * CK;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) rw[r] = *reinterpret_cast<const f4*>(wsrc + 4 * min(tid + 256 * r, NW - 1));
+  };
+  auto commit = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < RQ; ++r) {
+      const int q = tid + 256 * r;
+      if (q < NQ)
+        *reinterpret_cast<f4*>(&s_in[buf][(q / (CK / 4)) * PIN + 4 * (q % (CK / 4))]) =
+            halo_value<MODE>(rq[r], (ok >> r) & 1u);
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int q = tid + 256 * r;
+      if (q < NW) *reinterpret_cast<f4*>(&s_w[buf][(q / (CK / 4)) * PW + 4 * (q % (CK / 4))]) = rw[r];
+    }
+  };
 
   if (ch_lo < ch_hi) {
-    LNM_FETCH(ch_lo);
-    LNM_COMMIT(0);
+    fetch(ch_lo);
+    commit(0);
   }
   __syncthreads();
   for (int ch = ch_lo; ch < ch_hi; ++ch) {
     const int cur = (ch - ch_lo) & 1;
     const bool more = ch + 1 < ch_hi;
-    if (more) LNM_FETCH(ch + 1);
+    if (more) fetch(ch + 1);
     const float* si = s_in[cur];
     const float* sw = s_w[cur];
 #pragma unroll
@@ -158,11 +183,9 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a) {
             acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mf], bv[nf], acc[mf][nf], 0, 0, 0);
       }
     }
-    if (more) LNM_COMMIT(cur ^ 1);
+    if (more) commit(cur ^ 1);
     __syncthreads();
   }
-#undef LNM_FETCH
-#undef LNM_COMMIT
 
   // epilogue: lane holds rows (pixels) 4g..4g+3 of each 16x16 block, column li
 #pragma unroll
@@ -335,7 +358,7 @@ __global__ __launch_bounds__(256) void wgrad3x3_f32(WgradArgs a) {
       const int p = q >> 2, c = c0 + 4 * (q & 3);
       const int y = y0 + p / kHW - 1, xx = x0 + p % kHW - 1;
       f4 v = f4{0.f, 0.f, 0.f, 0.f};
-      if (y >= 0 && y < x.H && xx >= 0 && xx < x.W && c < a.ci) v = gather4<MODE>(x, b, y, xx, c);
+      if (y >= 0 && y < x.H && xx >= 0 && xx < x.W && c < a.ci) v = halo_value<MODE>(halo_load<MODE>(x, b, y, xx, c), true);
       s_x[p][4 * (q & 3) + 0] = v.x;
       s_x[p][4 * (q & 3) + 1] = v.y;
       s_x[p][4 * (q & 3) + 2] = v.z;

@@ -42,31 +42,49 @@ __device__ __forceinline__ uint32_t max_bf16x2(uint32_t a, uint32_t b) {
   return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
 }
 
-// Eight consecutive channels [c, c+8) of the (virtual) input at pixel (y, x).
+// Raw loads of eight consecutive channels [c, c+8) of the (virtual) input at
+// pixel (y, x), all three clamped to valid positions: the pooled mode keeps
+// its four source pixels, the others one value.  They are combined and
+// masked only when written to LDS, so a chunk's loads are all in flight
+// together and nothing waits on them before the current chunk's matrix work.
 template <int MODE>
-__device__ __forceinline__ uint4 gather8(const ConvArgs& a, int b, int y, int x, int c) {
+struct Halo {
+  uint4 v[MODE == G_POOL ? 4 : 1];
+};
+
+template <int MODE>
+__device__ __forceinline__ Halo<MODE> halo_load(const ConvArgs& a, int b, int y, int x, int c) {
   const uint16_t* s0 = static_cast<const uint16_t*>(a.src0);
+  Halo<MODE> h;
   if constexpr (MODE == G_PLAIN) {
-    return *reinterpret_cast<const uint4*>(s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c);
+    h.v[0] = *reinterpret_cast<const uint4*>(s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c);
   } else if constexpr (MODE == G_POOL) {
-    const int W2 = 2 * a.W;
-    const uint16_t* p = s0 + ((size_t)(b * 2 * a.H + 2 * y) * W2 + 2 * x) * a.c0 + c;
-    const uint4 v0 = *reinterpret_cast<const uint4*>(p);
-    const uint4 v1 = *reinterpret_cast<const uint4*>(p + a.c0);
-    const uint4 v2 = *reinterpret_cast<const uint4*>(p + (size_t)W2 * a.c0);
-    const uint4 v3 = *reinterpret_cast<const uint4*>(p + (size_t)W2 * a.c0 + a.c0);
-    uint4 r;
-    r.x = max_bf16x2(max_bf16x2(v0.x, v1.x), max_bf16x2(v2.x, v3.x));
-    r.y = max_bf16x2(max_bf16x2(v0.y, v1.y), max_bf16x2(v2.y, v3.y));
-    r.z = max_bf16x2(max_bf16x2(v0.z, v1.z), max_bf16x2(v2.z, v3.z));
-    r.w = max_bf16x2(max_bf16x2(v0.w, v1.w), max_bf16x2(v2.w, v3.w));
-    return r;
-  } else {  // G_CONCAT_UP
-    if (c < a.c0) return *reinterpret_cast<const uint4*>(s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c);
+    const size_t W2 = 2 * (size_t)a.W, c0 = (size_t)a.c0;
+    const uint16_t* p = s0 + ((size_t)(b * 2 * a.H + 2 * y) * W2 + 2 * x) * c0 + c;
+    h.v[0] = *reinterpret_cast<const uint4*>(p);
+    h.v[1] = *reinterpret_cast<const uint4*>(p + c0);
+    h.v[2] = *reinterpret_cast<const uint4*>(p + W2 * c0);
+    h.v[3] = *reinterpret_cast<const uint4*>(p + W2 * c0 + c0);
+  } else {  // G_CONCAT_UP: channels [0, c0) from the skip, then the upsampled low-res tensor
     const int Hl = a.H >> 1, Wl = a.W >> 1;
-    return *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(a.src1) +
-                                           ((size_t)(b * Hl + (y >> 1)) * Wl + (x >> 1)) * a.c1 + (c - a.c0));
+    const uint16_t* skip = s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c;
+    const uint16_t* up = static_cast<const uint16_t*>(a.src1) +
+                         ((size_t)(b * Hl + (y >> 1)) * Wl + (x >> 1)) * a.c1 + max(c - a.c0, 0);
+    h.v[0] = *reinterpret_cast<const uint4*>(c < a.c0 ? skip : up);
   }
+  return h;
+}
+
+template <int MODE>
+__device__ __forceinline__ uint4 halo_value(const Halo<MODE>& h, bool ok) {
+  uint4 r = h.v[0];
+  if constexpr (MODE == G_POOL) {
+    r.x = max_bf16x2(max_bf16x2(h.v[0].x, h.v[1].x), max_bf16x2(h.v[2].x, h.v[3].x));
+    r.y = max_bf16x2(max_bf16x2(h.v[0].y, h.v[1].y), max_bf16x2(h.v[2].y, h.v[3].y));
+    r.z = max_bf16x2(max_bf16x2(h.v[0].z, h.v[1].z), max_bf16x2(h.v[2].z, h.v[3].z));
+    r.w = max_bf16x2(max_bf16x2(h.v[0].w, h.v[1].w), max_bf16x2(h.v[2].w, h.v[3].w));
+  }
+  return ok ? r : make_uint4(0, 0, 0, 0);
 }
 
 template <int TH>
@@ -124,31 +142,30 @@ __global__ __launch_bounds__(256) void conv3x3_bf16(ConvArgs a) {
 
   constexpr int NQ = (TH + 2) * kHW * (kCK / 8), NW = 9 * kBN * kCK / 8;
   constexpr int RQ = (NQ + 255) / 256, RW = (NW + 255) / 256;
-  uint4 rq[RQ], rw[RW];
+  Halo<MODE> rq[RQ];
+  uint4 rw[RW];
+  unsigned ok = 0;
   auto fetch = [&](int ch) {
+    ok = 0;
 #pragma unroll
     for (int r = 0; r < RQ; ++r) {
-      const int q = tid + 256 * r;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (q < NQ) {
-        const int c8 = q & 3, p = q >> 2;
-        const int y = y0 + p / kHW - 1, x = x0 + p % kHW - 1, c = ch * kCK + 8 * c8;
-        if (y >= 0 && y < a.H && x >= 0 && x < a.W && c < ci) v = gather8<MODE>(a, b, y, x, c);
-      }
-      rq[r] = v;
+      const int q = min(tid + 256 * r, NQ - 1);
+      const int c8 = q & 3, p = q >> 2;
+      const int y = y0 + p / kHW - 1, x = x0 + p % kHW - 1, c = ch * kCK + 8 * c8;
+      const bool in = tid + 256 * r < NQ && y >= 0 && y < a.H && x >= 0 && x < a.W && c < ci;
+      ok |= (unsigned)in << r;
+      rq[r] = halo_load<MODE>(a, b, min(max(y, 0), a.H - 1), min(max(x, 0), a.W - 1), c < ci ? c : 0);
     }
     const uint16_t* wsrc = wblk + (size_t)ch * 9 * kBN * kCK;
 #pragma unroll
-    for (int r = 0; r < RW; ++r) {
-      const int q = tid + 256 * r;
-      if (q < NW) rw[r] = *reinterpret_cast<const uint4*>(wsrc + 8 * q);
-    }
+    for (int r = 0; r < RW; ++r) rw[r] = *reinterpret_cast<const uint4*>(wsrc + 8 * min(tid + 256 * r, NW - 1));
   };
   auto commit = [&](int buf) {
 #pragma unroll
     for (int r = 0; r < RQ; ++r) {
       const int q = tid + 256 * r;
-      if (q < NQ) *reinterpret_cast<uint4*>(&s_in[buf][(q >> 2) * kPad + 8 * (q & 3)]) = rq[r];
+      if (q < NQ)
+        *reinterpret_cast<uint4*>(&s_in[buf][(q >> 2) * kPad + 8 * (q & 3)]) = halo_value<MODE>(rq[r], (ok >> r) & 1u);
     }
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
