@@ -365,8 +365,8 @@ LNM_API lnm_status lnm_trainer_infer(lnm_ctx ctx, lnm_trainer tr, int32_t batch,
 typedef enum {
   LNM_K_MARCH = 0,      /* guiding-map march */
   LNM_K_CONV = 1,       /* 3x3 convolution layers */
-  LNM_K_HEAD = 2,       /* 1x1 head + sigmoid */
-  LNM_K_COMPOSITE = 3,  /* six-way shading */
+  LNM_K_HEAD = 2,       /* 1x1 head + sigmoid (in lnm_frame with rgba: + six-way shading, one launch) */
+  LNM_K_COMPOSITE = 3,  /* six-way shading (lnm_composite, lnm_composite_shadowed) */
   LNM_K_REFERENCE = 4,  /* reference lightmaps */
   LNM_K_ADAPTERS = 5,   /* channel adapters */
   LNM_K_COUNT = 6

@@ -342,7 +342,7 @@ Plan plan_workspace(const lnm_net_s* net, int B, int H, int W) {
 }
 
 lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, const float* guide, float* lm,
-                           float* logits, char* ws, hipStream_t s) {
+                    float* logits, char* ws, hipStream_t s, const CompositeArgs* comp) {
   const Plan p = plan_workspace(net, B, H, W);
   const int L = net->levels;
   auto buf = [&](int i) { return static_cast<void*>(ws + p.out_off[i]); };
@@ -426,7 +426,7 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
   h.logits = logits;
   {
     ProfScope ps(ctx, LNM_K_HEAD, s);
-    e = launch_head(h, s);
+    e = launch_head(h, s, comp);
   }
   if (e != hipSuccess) return fail(LNM_ERR_DEVICE, hipGetErrorString(e));
   return LNM_OK;
@@ -947,17 +947,13 @@ lnm_status lnm_frame(lnm_ctx ctx, lnm_net net, const lnm_volume* vol, const lnm_
     ProfScope ps(ctx, LNM_K_MARCH, s);
     LNM_HIP_CHECK(launch_march(m, c, march_buffers(workspace, m, K, c.W, c.H), guide, s));
   }
-  st = run_unet(ctx, net, 1, c.H, c.W, guide, lightmaps, nullptr, static_cast<char*>(workspace), s);
-  if (st) return st;
-  if (rgba) {
-    a.lm = lightmaps;
-    a.guide = guide;
-    a.rgba = rgba;
-    a.P = c.H * c.W;
-    ProfScope ps(ctx, LNM_K_COMPOSITE, s);
-    LNM_HIP_CHECK(launch_composite(a, s));
-  }
-  return LNM_OK;
+  // the head launch also shades the frame when rgba is requested
+  a.lm = lightmaps;
+  a.guide = guide;
+  a.rgba = rgba;
+  a.P = c.H * c.W;
+  return run_unet(ctx, net, 1, c.H, c.W, guide, lightmaps, nullptr, static_cast<char*>(workspace), s,
+                  rgba ? &a : nullptr);
 }
 
 }  // extern "C"

@@ -223,31 +223,84 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 }
 
 // Finish a split-K layer: sum the splits in order, then the layer epilogue.
-__global__ __launch_bounds__(256) void splitk_reduce(ConvArgs a, int out_type, long total) {
-  const long i = (long)blockIdx.x * 256 + threadIdx.x;
-  if (i >= total) return;
-  const int n = i % a.co;
-  float s = 0.0f;
-  for (int k = 0; k < a.splits; ++k) s += a.partial[(size_t)k * total + i];
-  if (out_type == 2) {
-    float v = a.in_scale * a.w_scale[n] * s + a.bias[n];
-    v = v > 0.0f ? v * a.out_inv_scale : 0.0f;
-    v = fminf(v, 448.0f);
-    static_cast<uint8_t*>(a.out)[i] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xff);
-    return;
+// One lane per four consecutive output elements (channels of one pixel: the
+// channel count is a multiple of 16); the S partial loads are issued before
+// the in-order sum.
+template <int S>
+__global__ __launch_bounds__(256) void splitk_reduce(ConvArgs a, int out_type, long total4) {
+  const long i4 = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i4 >= total4) return;
+  const size_t total = (size_t)total4 * 4;
+  f4 v[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) v[k] = *reinterpret_cast<const f4*>(a.partial + k * total + 4 * i4);
+  const int n0 = (int)((4 * i4) % a.co);
+  float y[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < S; ++k) acc += v[k][e];
+    const int n = n0 + e;
+    if (out_type == 2) {
+      float t = a.in_scale * a.w_scale[n] * acc + a.bias[n];
+      t = t > 0.0f ? t * a.out_inv_scale : 0.0f;
+      y[e] = fminf(t, 448.0f);
+    } else {
+      float t = acc + a.bias[n];
+      if (a.relu) t = fmaxf(t, 0.0f);
+      y[e] = t;
+    }
   }
-  float v = s + a.bias[n];
-  if (a.relu) v = fmaxf(v, 0.0f);
-  if (out_type == 1)
-    static_cast<uint16_t*>(a.out)[i] = f32_to_bf16(v);
-  else
-    static_cast<float*>(a.out)[i] = v;
+  if (out_type == 2) {
+    uint32_t packed = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      packed |= ((uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y[e], 0.0f, 0, false) & 0xffu) << (8 * e);
+    static_cast<uint32_t*>(a.out)[i4] = packed;
+  } else if (out_type == 1) {
+    static_cast<uint2*>(a.out)[i4] = make_uint2((uint32_t)f32_to_bf16(y[0]) | ((uint32_t)f32_to_bf16(y[1]) << 16),
+                                                (uint32_t)f32_to_bf16(y[2]) | ((uint32_t)f32_to_bf16(y[3]) << 16));
+  } else {
+    static_cast<f4*>(a.out)[i4] = f4{y[0], y[1], y[2], y[3]};
+  }
 }
 
-// 1x1 head C -> 6 and sigmoid, one lane per pixel; fp32 arithmetic on
-// fp32 (IN = 0) or bf16 (IN = 1) activations.
-template <int IN>
-__global__ __launch_bounds__(256) void head_kernel(HeadArgs a) {
+__device__ __forceinline__ float srgb_decode(float s) {
+  return s <= 0.04045f ? s / 12.92f : powf((s + 0.055f) / 1.055f, 2.4f);
+}
+
+// Six-way shading of one pixel from its six lightmap values:
+// rgb = sum_l c_l sum_p |l_p| lin(L_p^{sign l_p}), alpha = 1 - T.
+__device__ __forceinline__ void shade_pixel(const CompositeArgs& a, int p, const float (&L)[6]) {
+  float lin[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) lin[q] = srgb_decode(L[q]);
+  float r = 0.f, gg = 0.f, bb = 0.f;
+  for (int k = 0; k < a.n_lights; ++k) {
+    float s = 0.f;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const float c = a.l[k][ax];
+      s += fabsf(c) * (c >= 0.0f ? lin[2 * ax] : lin[2 * ax + 1]);
+    }
+    r += a.rgb[k][0] * s;
+    gg += a.rgb[k][1] * s;
+    bb += a.rgb[k][2] * s;
+  }
+  float* o = a.rgba + (size_t)p * 4;
+  o[0] = r;
+  o[1] = gg;
+  o[2] = bb;
+  o[3] = 1.0f - a.guide[(size_t)p * 3 + 1];
+}
+
+// 1x1 head C -> 6 and sigmoid, one lane per pixel; fp32 arithmetic on fp32
+// (IN = 0), bf16 (IN = 1) or e4m3 (IN = 2) activations.  With COMP the
+// pixel is also shaded from the lightmap values it just stored (the frame's
+// head and composite in one launch; same values as the separate kernels).
+template <int IN, bool COMP>
+__global__ __launch_bounds__(256) void head_kernel(HeadArgs a, CompositeArgs comp) {
   __shared__ float sw[6 * 256];
   __shared__ float sb[6];
   for (int q = threadIdx.x; q < 6 * a.C; q += 256) sw[q] = a.w[q];
@@ -277,42 +330,24 @@ __global__ __launch_bounds__(256) void head_kernel(HeadArgs a) {
       z[o] += w[0] * v.x + w[1] * v.y + w[2] * v.z + w[3] * v.w;
     }
   }
+  float L[6];
 #pragma unroll
   for (int o = 0; o < 6; ++o) {
     if (a.logits) a.logits[(size_t)p * 6 + o] = z[o];
-    a.lm[(size_t)p * 6 + o] = 1.0f / (1.0f + expf(-z[o]));
+    L[o] = 1.0f / (1.0f + expf(-z[o]));
+    a.lm[(size_t)p * 6 + o] = L[o];
   }
+  if constexpr (COMP) shade_pixel(comp, p, L);
 }
 
-__device__ __forceinline__ float srgb_decode(float s) {
-  return s <= 0.04045f ? s / 12.92f : powf((s + 0.055f) / 1.055f, 2.4f);
-}
-
-// Six-way shading: rgb = sum_l c_l sum_p |l_p| lin(L_p^{sign l_p}), alpha = 1 - T.
+// Six-way shading of stored lightmaps.
 __global__ __launch_bounds__(256) void composite_kernel(CompositeArgs a) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= a.P) return;
-  const float* L = a.lm + (size_t)p * 6;
-  float lin[6];
+  float L[6];
 #pragma unroll
-  for (int q = 0; q < 6; ++q) lin[q] = srgb_decode(L[q]);
-  float r = 0.f, gg = 0.f, bb = 0.f;
-  for (int k = 0; k < a.n_lights; ++k) {
-    float s = 0.f;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const float c = a.l[k][ax];
-      s += fabsf(c) * (c >= 0.0f ? lin[2 * ax] : lin[2 * ax + 1]);
-    }
-    r += a.rgb[k][0] * s;
-    gg += a.rgb[k][1] * s;
-    bb += a.rgb[k][2] * s;
-  }
-  float* o = a.rgba + (size_t)p * 4;
-  o[0] = r;
-  o[1] = gg;
-  o[2] = bb;
-  o[3] = 1.0f - a.guide[(size_t)p * 3 + 1];
+  for (int q = 0; q < 6; ++q) L[q] = a.lm[(size_t)p * 6 + q];
+  shade_pixel(a, p, L);
 }
 
 // Weight gradient of a 3x3 layer: dW[o][c][tap] = sum_p E[p][o] X[p + tap][c]
@@ -423,8 +458,16 @@ hipError_t launch_conv3x3_f32(int mode, int ck, const ConvArgs& a, hipStream_t s
 }
 
 hipError_t launch_splitk_reduce(const ConvArgs& a, int out_type, hipStream_t s) {
-  const long total = (long)a.B * a.H * a.W * a.co;
-  hipLaunchKernelGGL(splitk_reduce, dim3((total + 255) / 256), dim3(256), 0, s, a, out_type, total);
+  if (a.co % 4) return hipErrorInvalidValue;
+  const long total4 = (long)a.B * a.H * a.W * a.co / 4;
+  const dim3 grid((unsigned)((total4 + 255) / 256));
+  switch (a.splits) {
+    case 2: hipLaunchKernelGGL(splitk_reduce<2>, grid, dim3(256), 0, s, a, out_type, total4); break;
+    case 4: hipLaunchKernelGGL(splitk_reduce<4>, grid, dim3(256), 0, s, a, out_type, total4); break;
+    case 8: hipLaunchKernelGGL(splitk_reduce<8>, grid, dim3(256), 0, s, a, out_type, total4); break;
+    case 16: hipLaunchKernelGGL(splitk_reduce<16>, grid, dim3(256), 0, s, a, out_type, total4); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -459,16 +502,19 @@ hipError_t launch_wgrad_reduce(const float* partial, int n_partials, int co, int
   return hipGetLastError();
 }
 
-hipError_t launch_head(const HeadArgs& a, hipStream_t s) {
-  if (a.C > 256 || (a.C & 3)) return hipErrorInvalidValue;
-  if (a.in_type == 0)
-    hipLaunchKernelGGL(head_kernel<0>, dim3((a.P + 255) / 256), dim3(256), 0, s, a);
-  else if (a.in_type == 1)
-    hipLaunchKernelGGL(head_kernel<1>, dim3((a.P + 255) / 256), dim3(256), 0, s, a);
-  else if (a.in_type == 2)
-    hipLaunchKernelGGL(head_kernel<2>, dim3((a.P + 255) / 256), dim3(256), 0, s, a);
-  else
-    return hipErrorInvalidValue;
+hipError_t launch_head(const HeadArgs& a, hipStream_t s, const CompositeArgs* comp) {
+  if (a.C > 256 || (a.C & 3) || a.in_type < 0 || a.in_type > 2) return hipErrorInvalidValue;
+  const dim3 grid((a.P + 255) / 256);
+  const CompositeArgs c = comp ? *comp : CompositeArgs{};
+  if (comp) {
+    if (a.in_type == 0) hipLaunchKernelGGL((head_kernel<0, true>), grid, dim3(256), 0, s, a, c);
+    if (a.in_type == 1) hipLaunchKernelGGL((head_kernel<1, true>), grid, dim3(256), 0, s, a, c);
+    if (a.in_type == 2) hipLaunchKernelGGL((head_kernel<2, true>), grid, dim3(256), 0, s, a, c);
+  } else {
+    if (a.in_type == 0) hipLaunchKernelGGL((head_kernel<0, false>), grid, dim3(256), 0, s, a, c);
+    if (a.in_type == 1) hipLaunchKernelGGL((head_kernel<1, false>), grid, dim3(256), 0, s, a, c);
+    if (a.in_type == 2) hipLaunchKernelGGL((head_kernel<2, false>), grid, dim3(256), 0, s, a, c);
+  }
   return hipGetLastError();
 }
 

@@ -136,7 +136,9 @@ struct HeadArgs {
   float* lm;        // [P][6] sigmoid output
   float* logits;    // optional [P][6]
 };
-hipError_t launch_head(const HeadArgs& a, hipStream_t s);
+struct CompositeArgs;
+// comp: also shade each pixel (the frame's head and composite in one launch)
+hipError_t launch_head(const HeadArgs& a, hipStream_t s, const CompositeArgs* comp = nullptr);
 
 struct CompositeArgs {
   const float* lm;     // [P][6]
@@ -242,8 +244,9 @@ struct Plan {
   size_t bytes;
 };
 Plan plan_workspace(const lnm_net_s* net, int B, int H, int W);
+// comp (batch 1): shade each pixel in the head launch as well
 lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, const float* guide, float* lm,
-                    float* logits, char* ws, hipStream_t s);
+                    float* logits, char* ws, hipStream_t s, const CompositeArgs* comp = nullptr);
 lnm_status check_infer(const lnm_net_s* net, int B, int H, int W, size_t ws_bytes, const void* ws);
 
 // ---------------------------------------------------------------- training kernels (train.hip)
