@@ -362,16 +362,8 @@ __device__ __forceinline__ int wave_max(int v) {
 // One optical-depth step, the same float operations in both passes.
 __device__ __forceinline__ float depth_step(float L, float sig, float h) { return L + sig * h; }
 
-// Primary march with four lanes per pixel: lane s of the quad takes the s-th
-// quarter of the pixel's samples.  Pass 1 sums each segment's optical depth
-// (in sample order) and counts its records; a prefix over the quad gives
-// each lane the depth before its segment and its first record index.
-// Pass 2 re-gathers the segment (cache hits) and forms, per sample, the
-// depth tau_n = tau_before + (running sum), T_{n-1}, A_n, the depth D and
-// early termination, writing the records.  The depth before segment s + 1
-// is the same float sum as lane s's last tau_n, and the running sums only
-// grow, so a segment starts only if no earlier one terminated.
-// Tile `tile` (band order) of band `band`, whose work list starts at `list`.
+// Primary march of tile `tile` (band order) of band `band`, whose work list
+// starts at `list`, with four lanes per pixel (see below).
 __device__ __forceinline__ void primary_tile(const MarchDev& m, const CamDev& c, const TileMap& tm,
                                              const MarchBuf& buf, float* __restrict__ guide, int tile, int band,
                                              int2* __restrict__ list) {
@@ -396,17 +388,26 @@ __device__ __forceinline__ void primary_tile(const MarchDev& m, const CamDev& c,
       n1 = (int)floorf(t1 / h - u);
     }
   }
-  const int len = max(0, n1 - n0 + 1), seg = (len + 3) >> 2;
-  const int a0 = n0 + s * seg, a1 = min(n1, a0 + seg - 1);
+  // Lane s of the quad takes samples n = n0 + 4g + s of group g, so the four
+  // lanes gather four consecutive samples and a wave's loads stay in a
+  // compact part of the volume.  Four groups' loads are issued together;
+  // then, group by group, the optical depth runs through the quad in sample
+  // order (tau_n = tau_{n-1} + sigma_n h, handed from lane to lane, the same
+  // float sums as one lane walking the ray), each lane forms T_{n-1}, A_n,
+  // its record index (records of the lower lanes counted by a ballot) and
+  // the depth test, and the quad stops after the group in which the depth
+  // first passes tau_max.  A sample is taken only if the depth before it is
+  // still within tau_max.
   const bool riemann = m.quadrature == LNM_QUAD_RIEMANN;
-  // pass 1: the segment's optical depth and record count
-  float L = 0.0f;
-  int nrec = 0;
-  for (int nb = a0; nb <= a1; nb += 4) {
+  const int lane = threadIdx.x & 63, qbase = lane & ~3;
+  float tau = 0.0f;  // depth before the current group (equal in the quad)
+  int k = 0, dn = 0;  // records so far (equal in the quad), this lane's first sample over depth_tau
+  bool term = false;
+  for (int nb = n0; nb <= n1 && !term; nb += 16) {
     float px[4], py[4], pz[4], sg[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const float t = ((float)(nb + q) + u) * h;
+      const float t = ((float)(nb + 4 * q + s) + u) * h;
       px[q] = o.x + t * d.x;
       py[q] = o.y + t * d.y;
       pz[q] = o.z + t * d.z;
@@ -414,79 +415,55 @@ __device__ __forceinline__ void primary_tile(const MarchDev& m, const CamDev& c,
     sample_batch<4>(m, px, py, pz, sg);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (nb + q > a1) break;
-      L = depth_step(L, sg[q], h);
-      const float alpha = riemann ? sg[q] * h : -expm1f(-sg[q] * h);
-      nrec += alpha != 0.0f;
-    }
-  }
-  // prefix over the quad (lanes 4q .. 4q+3 of the wave)
-  const float L0 = __shfl(L, 0, 4), L1 = __shfl(L, 1, 4), L2 = __shfl(L, 2, 4), L3 = __shfl(L, 3, 4);
-  const int c0 = __shfl(nrec, 0, 4), c1 = __shfl(nrec, 1, 4), c2 = __shfl(nrec, 2, 4);
-  float tb = 0.0f;
-  int kb = 0;
-  if (s > 0) { tb = tb + L0; kb += c0; }
-  if (s > 1) { tb = tb + L1; kb += c1; }
-  if (s > 2) { tb = tb + L2; kb += c2; }
-  const float tau_all = ((0.0f + L0) + L1) + L2 + L3;  // depth after the last sample
-  // pass 2: samples, records, depth, termination
-  int k = kb, dn = 0;
-  bool term = false;
-  if (tb <= m.tau_max) {
-    float Lr = 0.0f, Tprev = expf(-tb);
-    for (int nb = a0; nb <= a1 && !term; nb += 4) {
-      float px[4], py[4], pz[4], sg[4];
+      if (term) break;
+      const int n = nb + 4 * q + s;
+      const bool valid = n <= n1;
+      const float sig = valid ? sg[q] : 0.0f;
+      // running depth through the quad: lane s ends with tau_n
+      float x = s == 0 ? depth_step(tau, sig, h) : 0.0f;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float t = ((float)(nb + q) + u) * h;
-        px[q] = o.x + t * d.x;
-        py[q] = o.y + t * d.y;
-        pz[q] = o.z + t * d.z;
+      for (int r = 1; r < 4; ++r) {
+        const float v = __shfl_up(x, 1, 4);
+        if (s == r) x = depth_step(v, sig, h);
       }
-      sample_batch<4>(m, px, py, pz, sg);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int n = nb + q;
-        if (term || n > a1) break;
-        const float sig = sg[q];
-        if (dn == 0 && sig > m.depth_tau) dn = n;
-        Lr = depth_step(Lr, sig, h);
-        const float tau = tb + Lr;
-        const float alpha = riemann ? sig * h : -expm1f(-sig * h);
-        if (alpha != 0.0f && k < buf.K) {
-          const size_t r = (size_t)k * buf.P + pix;
-          buf.t[r] = ((float)n + u) * h;
-          buf.a[r] = Tprev * alpha;
-          buf.tp[r] = Tprev;
-          ++k;
-        }
-        Tprev = expf(-tau);
-        if (tau > m.tau_max) term = true;
+      float before = __shfl_up(x, 1, 4);
+      if (s == 0) before = tau;
+      const bool active = valid && before <= m.tau_max;
+      const float alpha = riemann ? sig * h : -expm1f(-sig * h);
+      const bool rec = active && alpha != 0.0f;
+      const unsigned quad = (unsigned)(__ballot(rec) >> qbase) & 0xfu;
+      const int kr = k + __popc(quad & ((1u << s) - 1u));
+      if (rec && kr < buf.K) {
+        const float Tprev = expf(-before);
+        const size_t r = (size_t)kr * buf.P + pix;
+        buf.t[r] = ((float)n + u) * h;
+        buf.a[r] = Tprev * alpha;
+        buf.tp[r] = Tprev;
       }
+      if (active && dn == 0 && sig > m.depth_tau) dn = n;
+      k = min(k + __popc(quad), buf.K);
+      const unsigned over = (unsigned)(__ballot(active && x > m.tau_max) >> qbase) & 0xfu;
+      tau = __shfl(x, 3, 4);
+      term = over != 0u;
     }
   }
   // quad results: records, depth, transmittance
-  const int w0 = __shfl(k - kb, 0, 4), w1 = __shfl(k - kb, 1, 4), w2 = __shfl(k - kb, 2, 4),
-            w3 = __shfl(k - kb, 3, 4);
-  const int cnt = w0 + w1 + w2 + w3;
+  const int cnt = k;
   const int big = 0x7fffffff;
   int dmin = dn ? dn : big;
   dmin = min(dmin, __shfl_xor(dmin, 1, 4));
   dmin = min(dmin, __shfl_xor(dmin, 2, 4));
-  const int any_term = __shfl_xor((int)term, 1, 4) | __shfl_xor((int)term, 2, 4) | __shfl_xor((int)term, 3, 4) |
-                       (int)term;
   if (inside && s == 0) {
     buf.cnt[pix] = cnt;
     float* g = guide + 3 * (size_t)pix;
-    g[1] = any_term ? 0.0f : expf(-tau_all);
+    g[1] = term ? 0.0f : expf(-tau);
     g[2] = dmin == big ? 0.0f : (float)dmin * h;
   }
   // append this wave's records to the band's list: one atomic per wave, then
-  // k-major order; record k of a pixel is held by the quad lane whose
-  // [kb, k) range contains it
+  // k-major order (pixels in lane order within each k); lane s of a quad
+  // writes the pixel's records k = s (mod 4)
   const int total = wave_sum(s == 0 ? cnt : 0);
   if (total == 0) return;
-  const int lane = threadIdx.x & 63;
   int base = 0;
   if (lane == 0) base = atomicAdd(buf.ctr + band, total);
   base = __shfl(base, 0);
@@ -494,7 +471,7 @@ __device__ __forceinline__ void primary_tile(const MarchDev& m, const CamDev& c,
   const int kmax = wave_max(k);
   int off = base;
   for (int kk = 0; kk < kmax; ++kk) {
-    const bool mine = kk >= kb && kk < k;
+    const bool mine = (kk & 3) == s && kk < cnt;
     const unsigned long long has = __ballot(mine);
     if (mine) list[off + __popcll(has & below)] = make_int2((int)pix, kk);
     off += __popcll(has);
