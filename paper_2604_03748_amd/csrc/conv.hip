@@ -439,12 +439,16 @@ __global__ __launch_bounds__(256) void wgrad_reduce(const float* __restrict__ pa
   grad_w[i] = s;
 }
 
-template <int CK, int MODE>
-hipError_t launch_tile(const ConvArgs& a, hipStream_t s) {
-  constexpr int TH = 8;
+template <int CK, int MODE, int TH>
+hipError_t launch_th(const ConvArgs& a, hipStream_t s) {
   dim3 grid((a.W + kTW - 1) / kTW, ((a.H + TH - 1) / TH) * a.B, a.n_tiles * a.splits);
   hipLaunchKernelGGL((conv3x3_f32<CK, MODE, TH>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
+}
+template <int CK, int MODE>
+hipError_t launch_tile(const ConvArgs& a, hipStream_t s) {
+  if (CK == 16 && a.th == 4) return launch_th<CK, MODE, 4>(a, s);
+  return launch_th<CK, MODE, 8>(a, s);
 }
 
 }  // namespace
