@@ -298,9 +298,15 @@ static void pack_layer(const LayerDesc& d, int precision, const float* w, const 
 // of th x 16 pixels x 32 output channels); the 3-channel input layer is
 // never split.  The split grows until the layer has 256 workgroups (fp32) or
 // 512 (bf16, fp8), the targets measured fastest per precision with the
-// split-K reductions counted.  fp32 layers take 4-row tiles where that needs
-// a smaller split than 8-row tiles (the deep levels): twice the workgroups
-// without partial sums to write, read and reduce.
+// split-K reductions counted.  fp32 layers take 4-row tiles where that
+// needs a smaller split than 8-row tiles (the deep levels: twice the
+// workgroups without partial sums to write, read and reduce) or where 8-row
+// tiles leave one workgroup per CU (nothing else on the CU hides a
+// workgroup's chunk-boundary stalls): 5 us per frame.  fp8 layers, whose
+// LDS footprint lets five 4-row workgroups share a CU, take 4-row tiles
+// throughout: 19 us per frame.  bf16 keeps 8-row tiles: its footprint
+// allows two workgroups per CU either way, and 4-row tiles measured 11 us
+// slower.
 struct LayerTiling {
   int th, splits;
 };
@@ -310,9 +316,10 @@ static LayerTiling layer_tiling(const lnm_net_s* net, int i, int B, int h, int w
   const int target = net->precision == LNM_FP32 ? 256 : 512, nch = d.ci_pad / d.ck;
   auto wgs = [&](int th) { return (long)((w + 15) / 16) * ((h + th - 1) / th) * B * (d.co_pad / kBN); };
   const int s8 = conv_splits(wgs(8), nch, target);
-  if (net->precision == LNM_FP32 && s8 > 1) {
+  const bool fp8 = net->precision == LNM_FP8_E4M3;
+  if (net->precision != LNM_BF16 && (s8 > 1 || wgs(8) <= 256 || fp8)) {
     const int s4 = conv_splits(wgs(4), nch, target);
-    if (s4 < s8) return {4, s4};
+    if (s4 < s8 || wgs(8) <= 256 || fp8) return {4, s4};
   }
   return {8, s8};
 }

@@ -259,15 +259,20 @@ __global__ __launch_bounds__(256) void conv3x3_bf16_guide(ConvArgs a) {
   store_tile<TH>(a, acc, b, y0, x0, wrow, g, li, blockIdx.z, 0);
 }
 
-template <int MODE>
-hipError_t launch_tile(const ConvArgs& a, hipStream_t s) {
-  constexpr int TH = 8;
+template <int MODE, int TH>
+hipError_t launch_th(const ConvArgs& a, hipStream_t s) {
   dim3 grid((a.W + kTW - 1) / kTW, ((a.H + TH - 1) / TH) * a.B, a.n_tiles * a.splits);
   if constexpr (MODE == G_GUIDE)
     hipLaunchKernelGGL((conv3x3_bf16_guide<TH>), grid, dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((conv3x3_bf16<MODE, TH>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
+}
+// 8-row tiles, or 4-row tiles when the layer asks for them (not the input layer)
+template <int MODE>
+hipError_t launch_tile(const ConvArgs& a, hipStream_t s) {
+  if (MODE != G_GUIDE && a.th == 4) return launch_th<MODE == G_GUIDE ? G_PLAIN : MODE, 4>(a, s);
+  return launch_th<MODE, 8>(a, s);
 }
 
 }  // namespace

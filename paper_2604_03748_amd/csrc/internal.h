@@ -113,7 +113,7 @@ struct ConvArgs {
   // launch_splitk_reduce finishes the layer
   int n_tiles, splits;
   float* partial;
-  int th;  // fp32 tile height in rows: 4 or 8 (0 means 8)
+  int th;  // tile height in rows: 4 or 8 (0 means 8; the input layer always 8)
 };
 // Sum the split partials in split order, then bias, (scale,) ReLU and the
 // output conversion of out_type (0 fp32, 1 bf16, 2 fp8).
