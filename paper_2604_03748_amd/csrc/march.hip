@@ -349,17 +349,19 @@ __device__ __forceinline__ int wave_max(int v) {
 // The march runs in three kernels so that its dominant cost, the light
 // marches (two per primary sample), is spread over one lane per recorded
 // sample and light instead of serialised inside one lane per pixel:
+//   0. (relayout_balance: the bricked grid, and the band tile ranges)
 //   1. march_primary: four lanes per pixel walk the primary samples, write
 //      T and D, and record (t_n, A_n, T_{n-1}) of every sample with a
 //      nonzero weight in [k][P] planes; each wavefront then appends
 //      (pixel, k) of its records, k-major, to its XCD band's work list;
-//   2. march_lights: one lane per work-list entry and light marches toward
-//      that light and stores its transmittance at (light, k, pixel);
+//   2. march_lights: one lane per work-list entry and light (the lists cut
+//      into eight equal ranges, one per XCD) marches toward that light and
+//      stores its transmittance at (light, k, pixel);
 //   3. march_accumulate: one lane per pixel sums A_n L_n in sample order.
 // The work lists keep the light-march lanes dense and spatially coherent (a
 // wave takes neighbouring pixels at similar depths) whatever the per-pixel
 // sample counts are; all three kernels read the bricked grid.
-// One optical-depth step, the same float operations in both passes.
+// One optical-depth step (tau_n = tau_{n-1} + sigma_n h).
 __device__ __forceinline__ float depth_step(float L, float sig, float h) { return L + sig * h; }
 
 // Primary march of tile `tile` (band order) of band `band`, whose work list
