@@ -290,19 +290,56 @@ def precision_report(lnm, ctx, wl, params, dens):
     return out, amax
 
 
-# the conv kernels and their split-K choice (conv_splits lives in conv.hip)
+# the conv kernels and their tiling / split-K choice (layer_tiling in api.hip)
 CONV_SOURCES = ("paper_2604_03748_amd/csrc/conv.hip", "paper_2604_03748_amd/csrc/conv_bf16.hip",
-                "paper_2604_03748_amd/csrc/conv_fp8.hip")
+                "paper_2604_03748_amd/csrc/conv_fp8.hip", "paper_2604_03748_amd/csrc/api.hip")
+MARCH_SOURCES = ("paper_2604_03748_amd/csrc/march.hip", "paper_2604_03748_amd/csrc/api.hip")
 
 
-def conv_source_hash() -> str:
+def source_hash(sources=CONV_SOURCES) -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for rel in CONV_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def conv_source_hash() -> str:
+    return source_hash(CONV_SOURCES)
+
+
+def march_traffic():
+    """HBM bytes of one headline march (relayout + march kernels) from the
+    committed rocprofv3 counter summary, or None when there is none or the
+    march sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "march_persp128_256px_traffic.md")
+    if not os.path.exists(path):
+        return None
+    try:
+        blob = json.loads(open(path).read().split("```json", 1)[1].split("```", 1)[0])
+    except (IndexError, ValueError):
+        return None
+    return blob.get("bytes_per_march") if blob.get("source_hash") == source_hash(MARCH_SOURCES) else None
+
+
+def march_roofline(lnm, wl, stage):
+    """The march against HBM: its compulsory bytes (grid read, bricks written
+    and read back, guiding map written) over the measured march time.  The
+    march is bound by its scattered trilinear gathers (L1/L2 lines), not by
+    HBM, so the fraction is small by design; `traffic` is the measured HBM
+    traffic from the counter summary."""
+    n = wl.grid
+    H, W = wl.camera.height, wl.camera.width
+    bricks = int(lnm.lib().lnm_bricks_bytes(n, n, n))
+    compulsory = 4 * n ** 3 + 2 * bricks + 12 * H * W
+    us = stage["march"]["us_per_frame"]
+    t = march_traffic()
+    return {"bound": "gather (L1/L2 lines)", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "compulsory_bytes": compulsory, "achieved": round(compulsory / (us * 1e-6) / 1e9, 1),
+            "frac": round(compulsory / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5), "traffic": t,
+            "traffic_gbs": round(t / (us * 1e-6) / 1e9, 1) if t else None, "us_per_frame": round(us, 2)}
 
 
 def measured_traffic(dtype):
@@ -356,10 +393,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (reference for HBM counters)")
-    ap.add_argument("--source-hash", action="store_true", help="print the conv sources' hash and exit")
+    ap.add_argument("--source-hash", action="store_true", help="print the conv and march sources' hashes and exit")
     args = ap.parse_args()
     if args.source_hash:
-        print(conv_source_hash())
+        print(conv_source_hash(), source_hash(MARCH_SOURCES))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: frames and smoke instances are "
@@ -428,6 +465,7 @@ def main():
                    "camera": "perspective 60deg at 2.5", "step_voxels": wl.step_voxels, "unet_levels": wl.levels,
                    "unet_base": wl.base, "batch": 1, "lights": 1},
         "roofline": main_r["roofline"],
+        "march_roofline": march_roofline(lnm, wl, main_r["stage"]),
         "stages_us_per_frame": {k: round(v["us_per_frame"], 2) for k, v in main_r["stage"].items()},
         "frames_per_s_two_streams": round(main_r["two_streams"]["fps"], 2) if "two_streams" in main_r else None,
         "modes": {dt: {"value": round(r["fps"], 2), "ms_per_step": round(r["ms_per_step"], 5),

@@ -318,7 +318,8 @@ static LayerTiling layer_tiling(const lnm_net_s* net, int i, int B, int h, int w
   const int s8 = conv_splits(wgs(8), nch, target);
   const bool fp8 = net->precision == LNM_FP8_E4M3;
   if (net->precision != LNM_BF16 && (s8 > 1 || wgs(8) <= 256 || fp8)) {
-    const int s4 = conv_splits(wgs(4), nch, target);
+    // the longest fp32 layers (16+ chunks) split on to two workgroups per CU
+    const int s4 = conv_splits(wgs(4), nch, net->precision == LNM_FP32 && nch >= 16 ? 512 : target);
     if (s4 < s8 || wgs(8) <= 256 || fp8) return {4, s4};
   }
   return {8, s8};
