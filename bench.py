@@ -183,8 +183,10 @@ def dynamic_scene(lnm, ctx, frames, warmup=3):
     """256^3 grid of 32 moving blobs + noise with a sphere obstacle (r 0.15),
     camera orbiting 1.5 deg/frame, light rotating 0.5 deg/frame, 1024^2 view,
     step 4 voxels, 4-level base-48 bf16 network.  Method time (march + U-Net +
-    shading) is measured with HIP events on the stream; regenerating the
-    density each frame is timed separately and not counted."""
+    shading) is measured with HIP events on the stream, and the obstacle
+    shadowing of the same frame (sphere depth map + shadowed shading) beside
+    it; regenerating the density each frame is timed separately and not
+    counted."""
     import torch
 
     from synth.scene import dynamic, light_direction, make_volume_torch, orbit_camera, rotate_y
@@ -203,25 +205,39 @@ def dynamic_scene(lnm, ctx, frames, warmup=3):
     guide = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     lm = torch.empty((H, W, 6), dtype=torch.float32, device="cuda")
     rgba = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
-    gen_ms, frame_ms = [], []
+    # obstacle shadowing (Section 4.5): the sphere's depth map seen from the
+    # light (1024^2 texels over the cube) and the shading with each pixel's
+    # smoke surface tested against it, after the frame
+    centre, radius = (0.5, 0.5, 0.5), 0.15
+    sf = lnm.make_shadow_frame(centre, 0.9, 1024, 2.0 / 256)
+    dmap = torch.empty((1024, 1024), dtype=torch.float32, device="cuda")
+    rgba_s = torch.empty_like(rgba)
+    gen_ms, frame_ms, shadow_ms = [], [], []
     for f in range(warmup + frames):
-        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
         e0.record(stream)
-        dens = make_volume_torch(256, 32, 0, 0.3, frame=f, obstacle_radius=0.15)
+        dens = make_volume_torch(256, 32, 0, 0.3, frame=f, obstacle_radius=radius)
         e1.record(stream)
         prm.frame = f
+        cam = orbit_camera(f)
         light = (tuple(rotate_y(light0, 0.5 * f)), (1.0, 1.0, 1.0))
-        net.frame(dens, 8.0, orbit_camera(f), prm, lights=[light], guide=guide, lightmaps=lm, rgba=rgba,
+        net.frame(dens, 8.0, cam, prm, lights=[light], guide=guide, lightmaps=lm, rgba=rgba,
                   workspace=ws, stream=stream)
         e2.record(stream)
-        e2.synchronize()
+        ctx.shadow_map_sphere(sf, light[0], centre, radius, out=dmap, stream=stream)
+        ctx.composite_shadowed(cam, [light], sf, [dmap], lm, guide, out=rgba_s, stream=stream)
+        e3.record(stream)
+        e3.synchronize()
         if f >= warmup:
             gen_ms.append(e0.elapsed_time(e1))
             frame_ms.append(e1.elapsed_time(e2))
+            shadow_ms.append(e2.elapsed_time(e3))
     fm = np.array(frame_ms)
     return {"workload": "dynamic256_1024px", "frames": frames, "dtype": "bf16",
             "method_frames_per_s": round(1e3 / fm.mean(), 2), "latency_ms_p50": round(float(np.median(fm)), 4),
             "latency_ms_p99": round(float(np.percentile(fm, 99)), 4),
+            "shadow_ms_mean": round(float(np.mean(shadow_ms)), 4),
+            "with_shadows_frames_per_s": round(1e3 / (fm.mean() + float(np.mean(shadow_ms))), 2),
             "density_regen_ms_mean": round(float(np.mean(gen_ms)), 4)}
 
 
