@@ -114,6 +114,28 @@ def test_frame_end_to_end(ctx, orc, wl_fn):
     check_net(lm, lm_full, what=f"frame {wl.name} (oracle guide)")
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_frame_shading_equals_separate_composite(ctx, prec):
+    """lnm_frame shades in its head launch; the result must be bit-identical
+    to lnm_composite run on the frame's own lightmaps and guide."""
+    from paper_2604_03748_amd import lnm
+
+    wl = small_ortho()
+    vol = to_dev(wl.volume())
+    params = he_normal_params(wl.levels, wl.base, seed=2, bias="uniform")
+    lights = [(tuple(light_direction(1)), (1.0, 0.9, 0.8)), ((-0.3, 1.0, 0.2), (0.2, 0.25, 0.3))]
+    p = lnm.make_params(wl.step_voxels, seed=0)
+    amax = None
+    if prec == "fp8":
+        amax = lnm.Net(ctx, wl.levels, wl.base, params).calibrate_amax(ctx.march(vol, 8.0, wl.camera, p))
+    code = {"fp32": lnm.FP32, "bf16": lnm.BF16, "fp8": lnm.FP8_E4M3}[prec]
+    net = lnm.Net(ctx, wl.levels, wl.base, params, precision=code, act_scales=amax)
+    g, lm, rgba = net.frame(vol, 8.0, wl.camera, p, lights=lights)
+    sep = ctx.composite(wl.camera, lights, lm[None], g[None])[0]
+    log(f"{prec}: frame shading vs separate composite, max abs {np.abs(to_host(rgba) - to_host(sep)).max():.3g}")
+    assert np.array_equal(to_host(rgba), to_host(sep))
+
+
 def test_composite_matches_oracle(ctx, orc):
     wl = small_ortho()
     rng = np.random.default_rng(5)
