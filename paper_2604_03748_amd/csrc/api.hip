@@ -364,7 +364,7 @@ Plan plan_workspace(const lnm_net_s* net, int B, int H, int W) {
 }
 
 lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, const float* guide, float* lm,
-                    float* logits, char* ws, hipStream_t s, const CompositeArgs* comp) {
+                    float* logits, char* ws, hipStream_t s, const CompositeArgs* comp, bool fuse_head) {
   const Plan p = plan_workspace(net, B, H, W);
   const int L = net->levels;
   auto buf = [&](int i) { return static_cast<void*>(ws + p.out_off[i]); };
@@ -372,7 +372,8 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
   int li = 0;
   const bool fp8 = net->precision == LNM_FP8_E4M3;
   // src: conv layer that produced the input (-1: the guide), for fp8 scales
-  auto conv = [&](int lvl, int mode, int src, const void* s0, int c0, const void* s1, int c1) -> hipError_t {
+  auto conv = [&](int lvl, int mode, int src, const void* s0, int c0, const void* s1, int c1,
+                  const HeadFuse* head = nullptr) -> hipError_t {
     const LayerDesc& d = net->layers[li];
     ConvArgs a{};
     a.src0 = s0;
@@ -406,10 +407,22 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
     else if (net->precision == LNM_BF16)
       err = launch_conv3x3_bf16(mode, a, s);
     else
-      err = launch_conv3x3_f32(mode, d.ck, a, s);
+      err = launch_conv3x3_f32(mode, d.ck, a, s, head);
     if (err == hipSuccess && a.splits > 1) err = launch_splitk_reduce(a, fp8 ? 2 : net->precision == LNM_BF16 ? 1 : 0, s);
     return err;
   };
+  // fp32 inference: the last layer's epilogue applies the head (and the
+  // frame's shading) when its one 32-channel tile is unsplit, so the layer's
+  // output is never stored and the head needs no launch of its own
+  const int n_conv = (int)net->layers.size() - 1;
+  const LayerDesc& hd = net->layers[n_conv];
+  HeadFuse hf{};
+  hf.w = reinterpret_cast<const float*>(net->dev + hd.w_off);
+  hf.b = reinterpret_cast<const float*>(net->dev + hd.b_off);
+  hf.lm = lm;
+  if (comp) hf.comp = *comp;
+  const bool fused = fuse_head && lm && !logits && net->precision == LNM_FP32 &&
+                     net->layers[n_conv - 1].co <= kBN && layer_splits(net, n_conv - 1, B, H, W) == 1;
   hipError_t e;
   const void* x = guide;
   int cx = 3;
@@ -431,13 +444,12 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
       return fail(LNM_ERR_DEVICE, hipGetErrorString(e));
     x = buf(li - 1);
     cx = net->layers[li - 1].co;
-    if ((e = conv(l, G_PLAIN, li - 1, x, cx, nullptr, 0)) != hipSuccess)
+    if ((e = conv(l, G_PLAIN, li - 1, x, cx, nullptr, 0, fused && l == 0 ? &hf : nullptr)) != hipSuccess)
       return fail(LNM_ERR_DEVICE, hipGetErrorString(e));
     x = buf(li - 1);
     cx = net->layers[li - 1].co;
   }
-  if (!lm) return LNM_OK;  // convolutions only (calibration)
-  const LayerDesc& hd = net->layers[li];
+  if (!lm || fused) return LNM_OK;  // convolutions only (calibration), or the head ran in the last layer
   HeadArgs h{};
   h.in = x;
   h.in_type = fp8 ? 2 : net->precision == LNM_BF16 ? 1 : 0;
@@ -730,7 +742,7 @@ lnm_status lnm_infer(lnm_ctx ctx, lnm_net net, int32_t batch, int32_t H, int32_t
   lnm_status st = check_infer(net, batch, H, W, ws_bytes, workspace);
   if (st) return st;
   return run_unet(ctx, net, batch, H, W, guide, lightmaps, logits, static_cast<char*>(workspace),
-                  (hipStream_t)stream);
+                  (hipStream_t)stream, nullptr, true);
 }
 
 lnm_status lnm_composite(lnm_ctx ctx, const lnm_camera* cam, const lnm_light* lights, int32_t n_lights,
@@ -977,7 +989,7 @@ lnm_status lnm_frame(lnm_ctx ctx, lnm_net net, const lnm_volume* vol, const lnm_
   a.rgba = rgba;
   a.P = c.H * c.W;
   return run_unet(ctx, net, 1, c.H, c.W, guide, lightmaps, nullptr, static_cast<char*>(workspace), s,
-                  rgba ? &a : nullptr);
+                  rgba ? &a : nullptr, true);
 }
 
 }  // extern "C"

@@ -77,8 +77,37 @@ __device__ __forceinline__ f4 halo_value(const Halo<MODE>& h, bool ok) {
   return ok ? v : f4{0.f, 0.f, 0.f, 0.f};
 }
 
-template <int CK, int MODE, int TH>
-__global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a) {
+__device__ __forceinline__ float srgb_decode(float s) {
+  return s <= 0.04045f ? s / 12.92f : powf((s + 0.055f) / 1.055f, 2.4f);
+}
+
+// Six-way shading of one pixel from its six lightmap values:
+// rgb = sum_l c_l sum_p |l_p| lin(L_p^{sign l_p}), alpha = 1 - T.
+__device__ __forceinline__ void shade_pixel(const CompositeArgs& a, int p, const float (&L)[6]) {
+  float lin[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) lin[q] = srgb_decode(L[q]);
+  float r = 0.f, gg = 0.f, bb = 0.f;
+  for (int k = 0; k < a.n_lights; ++k) {
+    float s = 0.f;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const float c = a.l[k][ax];
+      s += fabsf(c) * (c >= 0.0f ? lin[2 * ax] : lin[2 * ax + 1]);
+    }
+    r += a.rgb[k][0] * s;
+    gg += a.rgb[k][1] * s;
+    bb += a.rgb[k][2] * s;
+  }
+  float* o = a.rgba + (size_t)p * 4;
+  o[0] = r;
+  o[1] = gg;
+  o[2] = bb;
+  o[3] = 1.0f - a.guide[(size_t)p * 3 + 1];
+}
+
+template <int CK, int MODE, int TH, bool HEAD>
+__global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a, HeadFuse hf) {
   constexpr int NF = kBN / 16;
   constexpr int MF = TH / 4;
   constexpr int PIN = Pad<CK>::in, PW = Pad<CK>::w;
@@ -187,6 +216,53 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a) {
     __syncthreads();
   }
 
+  if constexpr (HEAD) {
+    // head epilogue (one 32-channel tile, unsplit, ReLU layer): the tile's
+    // activations (bias + ReLU) and the head weights go to LDS (the weight
+    // buffer is free after the last chunk's barrier), then one thread per
+    // pixel forms the six head sums in channel order, the sigmoid, the
+    // lightmap store and, when asked, the pixel's shading
+    constexpr int PP = kBN + 1;  // padded floats per pixel row
+    static_assert(TH * kTW * PP + 6 * kBN <= 9 * kBN * PW, "head tile must fit the weight buffer");
+    float* sh = s_w[0];
+    float* shw = sh + TH * kTW * PP;
+    for (int q = tid; q < 6 * kBN; q += 256) shw[q] = (q % kBN) < a.co ? hf.w[(q / kBN) * a.co + q % kBN] : 0.0f;
+#pragma unroll
+    for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+      for (int nf = 0; nf < NF; ++nf) {
+        const int n = nf * 16 + li;
+        const float bias = n < a.co ? a.bias[n] : 0.0f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sh[((wrow + mf) * kTW + 4 * g + r) * PP + n] = fmaxf(acc[mf][nf][r] + bias, 0.0f);
+      }
+    __syncthreads();
+    if (tid < TH * kTW) {
+      const int y = y0 + tid / kTW, x = x0 + tid % kTW;
+      if (y < a.H && x < a.W) {
+        const float* v = sh + tid * PP;
+        float z[6];
+#pragma unroll
+        for (int o = 0; o < 6; ++o) z[o] = hf.b[o];
+        for (int c = 0; c < kBN; c += 4) {
+#pragma unroll
+          for (int o = 0; o < 6; ++o) {
+            const float* w = shw + o * kBN + c;
+            z[o] += w[0] * v[c] + w[1] * v[c + 1] + w[2] * v[c + 2] + w[3] * v[c + 3];
+          }
+        }
+        const size_t pix = (size_t)(b * a.H + y) * a.W + x;
+        float L[6];
+#pragma unroll
+        for (int o = 0; o < 6; ++o) {
+          L[o] = 1.0f / (1.0f + expf(-z[o]));
+          hf.lm[pix * 6 + o] = L[o];
+        }
+        if (hf.comp.rgba) shade_pixel(hf.comp, (int)pix, L);
+      }
+    }
+    return;
+  }
   // epilogue: lane holds rows (pixels) 4g..4g+3 of each 16x16 block, column
   // li; the stores are non-temporal (the next layer reads the tensor from
   // another XCD, so keeping it in this XCD's L2 only adds to the write-back
@@ -267,35 +343,6 @@ __global__ __launch_bounds__(256) void splitk_reduce(ConvArgs a, int out_type, l
   } else {
     static_cast<f4*>(a.out)[i4] = f4{y[0], y[1], y[2], y[3]};
   }
-}
-
-__device__ __forceinline__ float srgb_decode(float s) {
-  return s <= 0.04045f ? s / 12.92f : powf((s + 0.055f) / 1.055f, 2.4f);
-}
-
-// Six-way shading of one pixel from its six lightmap values:
-// rgb = sum_l c_l sum_p |l_p| lin(L_p^{sign l_p}), alpha = 1 - T.
-__device__ __forceinline__ void shade_pixel(const CompositeArgs& a, int p, const float (&L)[6]) {
-  float lin[6];
-#pragma unroll
-  for (int q = 0; q < 6; ++q) lin[q] = srgb_decode(L[q]);
-  float r = 0.f, gg = 0.f, bb = 0.f;
-  for (int k = 0; k < a.n_lights; ++k) {
-    float s = 0.f;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const float c = a.l[k][ax];
-      s += fabsf(c) * (c >= 0.0f ? lin[2 * ax] : lin[2 * ax + 1]);
-    }
-    r += a.rgb[k][0] * s;
-    gg += a.rgb[k][1] * s;
-    bb += a.rgb[k][2] * s;
-  }
-  float* o = a.rgba + (size_t)p * 4;
-  o[0] = r;
-  o[1] = gg;
-  o[2] = bb;
-  o[3] = 1.0f - a.guide[(size_t)p * 3 + 1];
 }
 
 // 1x1 head C -> 6 and sigmoid, one lane per pixel; fp32 arithmetic on fp32
@@ -440,26 +487,34 @@ __global__ __launch_bounds__(256) void wgrad_reduce(const float* __restrict__ pa
 }
 
 template <int CK, int MODE, int TH>
-hipError_t launch_th(const ConvArgs& a, hipStream_t s) {
+hipError_t launch_th(const ConvArgs& a, hipStream_t s, const HeadFuse* head) {
   dim3 grid((a.W + kTW - 1) / kTW, ((a.H + TH - 1) / TH) * a.B, a.n_tiles * a.splits);
-  hipLaunchKernelGGL((conv3x3_f32<CK, MODE, TH>), grid, dim3(256), 0, s, a);
+  if constexpr (CK == 16 && MODE == G_PLAIN) {
+    if (head) {
+      hipLaunchKernelGGL((conv3x3_f32<CK, MODE, TH, true>), grid, dim3(256), 0, s, a, *head);
+      return hipGetLastError();
+    }
+  }
+  if (head) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((conv3x3_f32<CK, MODE, TH, false>), grid, dim3(256), 0, s, a, HeadFuse{});
   return hipGetLastError();
 }
 template <int CK, int MODE>
-hipError_t launch_tile(const ConvArgs& a, hipStream_t s) {
-  if (CK == 16 && a.th == 4) return launch_th<CK, MODE, 4>(a, s);
-  return launch_th<CK, MODE, 8>(a, s);
+hipError_t launch_tile(const ConvArgs& a, hipStream_t s, const HeadFuse* head) {
+  if (CK == 16 && a.th == 4) return launch_th<CK, MODE, 4>(a, s, head);
+  return launch_th<CK, MODE, 8>(a, s, head);
 }
 
 }  // namespace
 
-hipError_t launch_conv3x3_f32(int mode, int ck, const ConvArgs& a, hipStream_t s) {
-  if (mode == G_GUIDE && ck == 4) return launch_tile<4, G_GUIDE>(a, s);
+hipError_t launch_conv3x3_f32(int mode, int ck, const ConvArgs& a, hipStream_t s, const HeadFuse* head) {
+  if (head && (a.n_tiles != 1 || a.splits != 1 || a.co > kBN || !a.relu)) return hipErrorInvalidValue;
+  if (mode == G_GUIDE && ck == 4) return launch_tile<4, G_GUIDE>(a, s, head);
   if (ck != 16) return hipErrorInvalidValue;
   switch (mode) {
-    case G_PLAIN: return launch_tile<16, G_PLAIN>(a, s);
-    case G_POOL: return launch_tile<16, G_POOL>(a, s);
-    case G_CONCAT_UP: return launch_tile<16, G_CONCAT_UP>(a, s);
+    case G_PLAIN: return launch_tile<16, G_PLAIN>(a, s, head);
+    case G_POOL: return launch_tile<16, G_POOL>(a, s, head);
+    case G_CONCAT_UP: return launch_tile<16, G_CONCAT_UP>(a, s, head);
     default: return hipErrorInvalidValue;
   }
 }

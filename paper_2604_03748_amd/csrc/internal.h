@@ -120,7 +120,10 @@ struct ConvArgs {
 hipError_t launch_splitk_reduce(const ConvArgs& a, int out_type, hipStream_t s);
 // Splits for a layer launched with `wgs` workgroups over `nchunks` input chunks.
 int conv_splits(long wgs, int nchunks, int target);
-hipError_t launch_conv3x3_f32(int mode, int ck, const ConvArgs& a, hipStream_t s);
+struct HeadFuse;
+// head: the layer's epilogue also applies the 1x1 head (plain-input layers
+// of at most 32 output channels, unsplit), instead of storing the layer
+hipError_t launch_conv3x3_f32(int mode, int ck, const ConvArgs& a, hipStream_t s, const HeadFuse* head = nullptr);
 hipError_t launch_conv3x3_bf16(int mode, const ConvArgs& a, hipStream_t s);
 hipError_t launch_conv3x3_fp8(int mode, const ConvArgs& a, hipStream_t s);
 constexpr int kAmaxBlocks = 256;
@@ -151,6 +154,15 @@ struct CompositeArgs {
   float rgb[16][3];
 };
 hipError_t launch_composite(const CompositeArgs& a, hipStream_t s);
+
+// The 1x1 head (+ sigmoid, + optional shading) applied in the last fp32 conv
+// layer's epilogue: that layer's workgroup holds all its channels.
+struct HeadFuse {
+  const float* w;      // [6][C] head weights (C = the layer's output channels)
+  const float* b;      // [6]
+  float* lm;           // [P][6] lightmaps
+  CompositeArgs comp;  // comp.rgba == nullptr: no shading
+};
 
 // ---------------------------------------------------------------- channel adapters
 struct AdapterArgs {
@@ -245,9 +257,12 @@ struct Plan {
   size_t bytes;
 };
 Plan plan_workspace(const lnm_net_s* net, int B, int H, int W);
-// comp (batch 1): shade each pixel in the head launch as well
+// comp (batch 1): shade each pixel in the head launch as well.  fuse_head:
+// an fp32 network may apply the head in its last conv layer's epilogue (that
+// layer's output is then not stored; callers that read it pass false)
 lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, const float* guide, float* lm,
-                    float* logits, char* ws, hipStream_t s, const CompositeArgs* comp = nullptr);
+                    float* logits, char* ws, hipStream_t s, const CompositeArgs* comp = nullptr,
+                    bool fuse_head = false);
 lnm_status check_infer(const lnm_net_s* net, int B, int H, int W, size_t ws_bytes, const void* ws);
 
 // ---------------------------------------------------------------- training kernels (train.hip)
