@@ -403,17 +403,19 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
     ProfScope ps(ctx, LNM_K_CONV, s);
     hipError_t err;
     if (fp8)
-      err = launch_conv3x3_fp8(mode, a, s);
+      err = launch_conv3x3_fp8(mode, a, s, head);
     else if (net->precision == LNM_BF16)
-      err = launch_conv3x3_bf16(mode, a, s);
+      err = launch_conv3x3_bf16(mode, a, s, head);
     else
       err = launch_conv3x3_f32(mode, d.ck, a, s, head);
     if (err == hipSuccess && a.splits > 1) err = launch_splitk_reduce(a, fp8 ? 2 : net->precision == LNM_BF16 ? 1 : 0, s);
     return err;
   };
-  // fp32 inference: the last layer's epilogue applies the head (and the
-  // frame's shading) when its one 32-channel tile is unsplit, so the layer's
-  // output is never stored and the head needs no launch of its own
+  // inference: the last layer's epilogue applies the head (and the frame's
+  // shading) when its one 32-channel tile is unsplit, so the layer's output
+  // is never stored and the head needs no launch of its own; the head reads
+  // the activations in the precision they would have been stored in, so the
+  // result equals the separate head kernel's
   const int n_conv = (int)net->layers.size() - 1;
   const LayerDesc& hd = net->layers[n_conv];
   HeadFuse hf{};
@@ -421,8 +423,9 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
   hf.b = reinterpret_cast<const float*>(net->dev + hd.b_off);
   hf.lm = lm;
   if (comp) hf.comp = *comp;
-  const bool fused = fuse_head && lm && !logits && net->precision == LNM_FP32 &&
-                     net->layers[n_conv - 1].co <= kBN && layer_splits(net, n_conv - 1, B, H, W) == 1;
+  hf.in_scale = fp8 ? net->act_scale[n_conv - 1] : 1.0f;
+  const bool fused = fuse_head && lm && !logits && net->layers[n_conv - 1].co <= kBN &&
+                     layer_splits(net, n_conv - 1, B, H, W) == 1;
   hipError_t e;
   const void* x = guide;
   int cx = 3;

@@ -16,6 +16,7 @@
 // channel 4g + jj for both operands, so each lane fetches its four channels of
 // A and of B with one 16-byte LDS read.
 #include "internal.h"
+#include "head.h"
 
 namespace lnm {
 namespace {
@@ -75,35 +76,6 @@ __device__ __forceinline__ f4 halo_value(const Halo<MODE>& h, bool ok) {
     for (int e = 0; e < 4; ++e) v[e] = fmaxf(fmaxf(h.v[0][e], h.v[1][e]), fmaxf(h.v[2][e], h.v[3][e]));
   }
   return ok ? v : f4{0.f, 0.f, 0.f, 0.f};
-}
-
-__device__ __forceinline__ float srgb_decode(float s) {
-  return s <= 0.04045f ? s / 12.92f : powf((s + 0.055f) / 1.055f, 2.4f);
-}
-
-// Six-way shading of one pixel from its six lightmap values:
-// rgb = sum_l c_l sum_p |l_p| lin(L_p^{sign l_p}), alpha = 1 - T.
-__device__ __forceinline__ void shade_pixel(const CompositeArgs& a, int p, const float (&L)[6]) {
-  float lin[6];
-#pragma unroll
-  for (int q = 0; q < 6; ++q) lin[q] = srgb_decode(L[q]);
-  float r = 0.f, gg = 0.f, bb = 0.f;
-  for (int k = 0; k < a.n_lights; ++k) {
-    float s = 0.f;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const float c = a.l[k][ax];
-      s += fabsf(c) * (c >= 0.0f ? lin[2 * ax] : lin[2 * ax + 1]);
-    }
-    r += a.rgb[k][0] * s;
-    gg += a.rgb[k][1] * s;
-    bb += a.rgb[k][2] * s;
-  }
-  float* o = a.rgba + (size_t)p * 4;
-  o[0] = r;
-  o[1] = gg;
-  o[2] = bb;
-  o[3] = 1.0f - a.guide[(size_t)p * 3 + 1];
 }
 
 template <int CK, int MODE, int TH, bool HEAD>
@@ -220,13 +192,11 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a, HeadFuse hf) {
     // head epilogue (one 32-channel tile, unsplit, ReLU layer): the tile's
     // activations (bias + ReLU) and the head weights go to LDS (the weight
     // buffer is free after the last chunk's barrier), then one thread per
-    // pixel forms the six head sums in channel order, the sigmoid, the
-    // lightmap store and, when asked, the pixel's shading
-    constexpr int PP = kBN + 1;  // padded floats per pixel row
-    static_assert(TH * kTW * PP + 6 * kBN <= 9 * kBN * PW, "head tile must fit the weight buffer");
+    // pixel finishes the head
+    static_assert(TH * kTW * 33 + 6 * kBN <= 9 * kBN * PW, "head tile must fit the weight buffer");
     float* sh = s_w[0];
-    float* shw = sh + TH * kTW * PP;
-    for (int q = tid; q < 6 * kBN; q += 256) shw[q] = (q % kBN) < a.co ? hf.w[(q / kBN) * a.co + q % kBN] : 0.0f;
+    float* shw = sh + TH * kTW * 33;
+    head_weights(hf, a.co, shw);
 #pragma unroll
     for (int mf = 0; mf < MF; ++mf)
 #pragma unroll
@@ -234,33 +204,10 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a, HeadFuse hf) {
         const int n = nf * 16 + li;
         const float bias = n < a.co ? a.bias[n] : 0.0f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sh[((wrow + mf) * kTW + 4 * g + r) * PP + n] = fmaxf(acc[mf][nf][r] + bias, 0.0f);
+        for (int r = 0; r < 4; ++r) sh[((wrow + mf) * kTW + 4 * g + r) * 33 + n] = fmaxf(acc[mf][nf][r] + bias, 0.0f);
       }
     __syncthreads();
-    if (tid < TH * kTW) {
-      const int y = y0 + tid / kTW, x = x0 + tid % kTW;
-      if (y < a.H && x < a.W) {
-        const float* v = sh + tid * PP;
-        float z[6];
-#pragma unroll
-        for (int o = 0; o < 6; ++o) z[o] = hf.b[o];
-        for (int c = 0; c < kBN; c += 4) {
-#pragma unroll
-          for (int o = 0; o < 6; ++o) {
-            const float* w = shw + o * kBN + c;
-            z[o] += w[0] * v[c] + w[1] * v[c + 1] + w[2] * v[c + 2] + w[3] * v[c + 3];
-          }
-        }
-        const size_t pix = (size_t)(b * a.H + y) * a.W + x;
-        float L[6];
-#pragma unroll
-        for (int o = 0; o < 6; ++o) {
-          L[o] = 1.0f / (1.0f + expf(-z[o]));
-          hf.lm[pix * 6 + o] = L[o];
-        }
-        if (hf.comp.rgba) shade_pixel(hf.comp, (int)pix, L);
-      }
-    }
+    head_finish<TH>(hf, sh, shw, b, a.H, a.W, y0, x0);
     return;
   }
   // epilogue: lane holds rows (pixels) 4g..4g+3 of each 16x16 block, column

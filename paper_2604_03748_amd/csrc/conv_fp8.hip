@@ -13,6 +13,7 @@
 // 3-channel input layer runs in bf16 (27 taps x channels in one K step) and
 // writes fp8.
 #include "internal.h"
+#include "head.h"
 
 namespace lnm {
 namespace {
@@ -125,8 +126,8 @@ __device__ __forceinline__ void store_fp8(const ConvArgs& a, const f4 (&acc)[TH 
   }
 }
 
-template <int MODE, int TH>
-__global__ __launch_bounds__(256) void conv3x3_fp8(ConvArgs a) {
+template <int MODE, int TH, bool HEAD>
+__global__ __launch_bounds__(256) void conv3x3_fp8(ConvArgs a, HeadFuse hf) {
   constexpr int MF = TH / 4;
   // two LDS buffers: the next chunk is fetched into registers while the
   // matrix cores work on the current one
@@ -214,6 +215,32 @@ __global__ __launch_bounds__(256) void conv3x3_fp8(ConvArgs a) {
     if (more) commit(cur ^ 1);
     __syncthreads();
   }
+  if constexpr (HEAD) {
+    // head epilogue: the activations as they would be stored (e4m3 of the
+    // scaled bias + ReLU, read back with the tensor's scale) and the head
+    // weights in LDS (both weight buffers are free after the last chunk's
+    // barrier), then one thread per pixel
+    static_assert((TH * kTW * 33 + 6 * kBN) * 4 <= 2 * 9 * kBN * kRow, "head tile must fit the weight buffers");
+    float* sh = reinterpret_cast<float*>(&s_w[0][0]);
+    float* shw = sh + TH * kTW * 33;
+    head_weights(hf, a.co, shw);
+#pragma unroll
+    for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+      for (int nf = 0; nf < 2; ++nf) {
+        const int n = nf * 16 + li;
+        const float bias = n < a.co ? a.bias[n] : 0.0f, sc = n < a.co ? a.in_scale * a.w_scale[n] : 0.0f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float v = sc * acc[mf][nf][r] + bias;
+          v = v > 0.0f ? v * a.out_inv_scale : 0.0f;
+          sh[((wrow + mf) * kTW + 4 * g + r) * 33 + n] = __builtin_amdgcn_cvt_f32_fp8((int)f2fp8(v), 0) * hf.in_scale;
+        }
+      }
+    __syncthreads();
+    head_finish<TH>(hf, sh, shw, b, a.H, a.W, y0, x0);
+    return;
+  }
   store_fp8<TH>(a, acc, b, y0, x0, wrow, g, li, true, nt, ks);
 }
 
@@ -298,29 +325,38 @@ __global__ __launch_bounds__(256) void amax_finish(const float* __restrict__ par
 }
 
 template <int MODE, int TH>
-hipError_t launch_th(const ConvArgs& a, hipStream_t s) {
+hipError_t launch_th(const ConvArgs& a, hipStream_t s, const HeadFuse* head) {
   dim3 grid((a.W + kTW - 1) / kTW, ((a.H + TH - 1) / TH) * a.B, a.n_tiles * a.splits);
-  if constexpr (MODE == G_GUIDE)
+  if constexpr (MODE == G_GUIDE) {
+    if (head) return hipErrorInvalidValue;
     hipLaunchKernelGGL((conv3x3_guide_to_fp8<TH>), grid, dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((conv3x3_fp8<MODE, TH>), grid, dim3(256), 0, s, a);
+  } else if constexpr (MODE == G_PLAIN) {
+    if (head)
+      hipLaunchKernelGGL((conv3x3_fp8<MODE, TH, true>), grid, dim3(256), 0, s, a, *head);
+    else
+      hipLaunchKernelGGL((conv3x3_fp8<MODE, TH, false>), grid, dim3(256), 0, s, a, HeadFuse{});
+  } else {
+    if (head) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((conv3x3_fp8<MODE, TH, false>), grid, dim3(256), 0, s, a, HeadFuse{});
+  }
   return hipGetLastError();
 }
 // 8-row tiles, or 4-row tiles when the layer asks for them (not the input layer)
 template <int MODE>
-hipError_t launch_tile(const ConvArgs& a, hipStream_t s) {
-  if (MODE != G_GUIDE && a.th == 4) return launch_th<MODE == G_GUIDE ? G_PLAIN : MODE, 4>(a, s);
-  return launch_th<MODE, 8>(a, s);
+hipError_t launch_tile(const ConvArgs& a, hipStream_t s, const HeadFuse* head) {
+  if (MODE != G_GUIDE && a.th == 4) return launch_th<MODE == G_GUIDE ? G_PLAIN : MODE, 4>(a, s, head);
+  return launch_th<MODE, 8>(a, s, head);
 }
 
 }  // namespace
 
-hipError_t launch_conv3x3_fp8(int mode, const ConvArgs& a, hipStream_t s) {
+hipError_t launch_conv3x3_fp8(int mode, const ConvArgs& a, hipStream_t s, const HeadFuse* head) {
+  if (head && (a.n_tiles != 1 || a.splits != 1 || a.co > kBN || !a.w_scale)) return hipErrorInvalidValue;
   switch (mode) {
-    case G_GUIDE: return launch_tile<G_GUIDE>(a, s);
-    case G_PLAIN: return launch_tile<G_PLAIN>(a, s);
-    case G_POOL: return launch_tile<G_POOL>(a, s);
-    case G_CONCAT_UP: return launch_tile<G_CONCAT_UP>(a, s);
+    case G_GUIDE: return launch_tile<G_GUIDE>(a, s, head);
+    case G_PLAIN: return launch_tile<G_PLAIN>(a, s, head);
+    case G_POOL: return launch_tile<G_POOL>(a, s, head);
+    case G_CONCAT_UP: return launch_tile<G_CONCAT_UP>(a, s, head);
     default: return hipErrorInvalidValue;
   }
 }

@@ -124,8 +124,8 @@ struct HeadFuse;
 // head: the layer's epilogue also applies the 1x1 head (plain-input layers
 // of at most 32 output channels, unsplit), instead of storing the layer
 hipError_t launch_conv3x3_f32(int mode, int ck, const ConvArgs& a, hipStream_t s, const HeadFuse* head = nullptr);
-hipError_t launch_conv3x3_bf16(int mode, const ConvArgs& a, hipStream_t s);
-hipError_t launch_conv3x3_fp8(int mode, const ConvArgs& a, hipStream_t s);
+hipError_t launch_conv3x3_bf16(int mode, const ConvArgs& a, hipStream_t s, const HeadFuse* head = nullptr);
+hipError_t launch_conv3x3_fp8(int mode, const ConvArgs& a, hipStream_t s, const HeadFuse* head = nullptr);
 constexpr int kAmaxBlocks = 256;
 // max |x| over n floats into *out (partial: kAmaxBlocks floats of scratch)
 hipError_t launch_amax(const float* x, long n, float* partial, float* out, hipStream_t s);
@@ -162,6 +162,7 @@ struct HeadFuse {
   const float* b;      // [6]
   float* lm;           // [P][6] lightmaps
   CompositeArgs comp;  // comp.rgba == nullptr: no shading
+  float in_scale;      // e4m3 layers: the scale of the layer's stored activations
 };
 
 // ---------------------------------------------------------------- channel adapters

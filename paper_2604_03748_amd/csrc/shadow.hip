@@ -13,15 +13,12 @@
 // few MB).
 #include <cmath>
 
+#include "head.h"
 #include "internal.h"
 #include "ray.h"
 
 namespace lnm {
 namespace {
-
-__device__ __forceinline__ float srgb_decode_f(float s) {
-  return s <= 0.04045f ? s / 12.92f : powf((s + 0.055f) / 1.055f, 2.4f);
-}
 
 __global__ __launch_bounds__(256) void shadow_map_sphere_kernel(int S, float E, float cu, float cv, float cz, float r2,
                                                                 float* __restrict__ depth) {
@@ -43,7 +40,7 @@ __global__ __launch_bounds__(256) void composite_shadowed_kernel(ShadowArgs a) {
   const float* L = a.c.lm + (size_t)p * 6;
   float lin[6];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) lin[k] = srgb_decode_f(L[k]);
+  for (int k = 0; k < 6; ++k) lin[k] = srgb_decode(L[k]);
   const float D = a.c.guide[(size_t)p * 3 + 2];
   V3 rel = v3(0.0f, 0.0f, 0.0f);
   if (D > 0.0f) {
