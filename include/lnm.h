@@ -227,7 +227,10 @@ LNM_API size_t lnm_workspace_bytes(lnm_net net, int32_t batch, int32_t H, int32_
 
 /* Lightmaps L[B][H][W][6] = sigmoid(U-Net(G)) from guide G[B][H][W][3]
  * (Section 4.3).  logits (optional, may be NULL): the pre-sigmoid head output,
- * same layout.  H and W must be divisible by 2^(levels-1). */
+ * same layout.  H and W must be divisible by 2^(levels-1).  The workspace is
+ * scratch: its contents after the call are unspecified (without logits the
+ * head runs in the last conv layer's epilogue and that layer's activations
+ * are never stored). */
 LNM_API lnm_status lnm_infer(lnm_ctx ctx, lnm_net net, int32_t batch, int32_t H, int32_t W, const float* guide,
                      float* lightmaps, float* logits, void* workspace, size_t ws_bytes, void* stream);
 
