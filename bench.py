@@ -13,9 +13,11 @@ with HBM traffic from the committed rocprofv3 counter summary when it
 matches the current conv sources.
 
 Further sections (each can be skipped): per-channel error of the three
-precisions against the fp64 oracle; the channel-adapter network; the dynamic
-256^3 / 1024^2 bf16 scene; the continuous-batching server (64 instances,
-Poisson arrivals, HBM budget); the oracle's CPU frame rate (`cpu_baseline`).
+precisions against the fp64 oracle on the 512x512 guiding map of the same
+volume and camera (the precision configuration); the channel-adapter network;
+the dynamic 256^3 / 1024^2 bf16 scene with its obstacle shadowing; the
+continuous-batching server (64 instances, Poisson arrivals, HBM budget); the
+oracle's CPU frame rate (`cpu_baseline`).
 Prints one JSON line.
 
 Usage: python bench.py [--steps K] [--warmup W] [--dtype fp32|bf16|fp8] [--only]
@@ -280,7 +282,7 @@ def adapters_mode(lnm, ctx, wl, params, dens, steps, warmup):
 
 def precision_report(lnm, ctx, wl, params, dens):
     """Max / mean abs error per lightmap channel of fp32, bf16 and fp8
-    against the fp64 oracle, on one frame's guiding map."""
+    against the fp64 oracle, on one frame's guiding map of workload wl."""
     import numpy as np
     import torch
 
@@ -303,6 +305,7 @@ def precision_report(lnm, ctx, wl, params, dens):
         out[k] = {"max_abs": [round(float(x), 6) for x in d.max(axis=0)],
                   "mean_abs": [round(float(x), 7) for x in d.mean(axis=0)]}
     out["weights"] = "He-normal seed 0 (untrained)"
+    out["workload"] = wl.name
     return out, amax
 
 
@@ -491,7 +494,9 @@ def main():
                   for dt, r in res.items() if dt != args.dtype},
     }
     if not args.no_precision:
-        out["precision_error_vs_fp64_oracle"], _ = precision_report(lnm, ctx, wl, params, dens)
+        # the precision configuration: the same volume and camera, 512x512
+        out["precision_error_vs_fp64_oracle"], _ = precision_report(lnm, ctx, headline(res=512), params, dens)
+        log(f"precision: {out['precision_error_vs_fp64_oracle']}")
     if not args.no_adapters:
         out["adapters"] = adapters_mode(lnm, ctx, wl, params, dens, max(20, args.steps // 4), 5)
         log(f"adapters: {out['adapters']}")
