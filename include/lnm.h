@@ -174,6 +174,18 @@ LNM_API size_t lnm_march_workspace_bytes(const lnm_volume* vol, const lnm_camera
 LNM_API lnm_status lnm_march(lnm_ctx ctx, const lnm_volume* vol, const lnm_camera* cam, const lnm_march_params* prm,
                      float* guide, void* workspace, size_t ws_bytes, void* stream);
 
+/* n guiding maps in one call (ragged: each march i has its own grid, camera,
+ * parameters and guides[i], of 3 W_i H_i floats), e.g. one per request of a
+ * serving batch (Algorithm 1 per map, as lnm_march).  The marches run in
+ * order on `stream` and share the one workspace, which must hold the largest
+ * of them: at least lnm_march_batch_workspace_bytes.  Every argument is
+ * checked before anything is enqueued; n in [1, 4096]. */
+LNM_API size_t lnm_march_batch_workspace_bytes(int32_t n, const lnm_volume* vols, const lnm_camera* cams,
+                                               const lnm_march_params* prms);
+LNM_API lnm_status lnm_march_batch(lnm_ctx ctx, int32_t n, const lnm_volume* vols, const lnm_camera* cams,
+                                   const lnm_march_params* prms, float* const* guides, void* workspace,
+                                   size_t ws_bytes, void* stream);
+
 /* Fine-step six-way reference lightmaps lm[H][W][6] used as training targets
  * (they replace the offline path-traced references of Section 5): order
  * (+X, -X, +Y, -Y, +Z, -Z) of the camera frame (X = right, Y = up, Z = toward

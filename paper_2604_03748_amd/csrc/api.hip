@@ -595,6 +595,44 @@ lnm_status lnm_march(lnm_ctx ctx, const lnm_volume* vol, const lnm_camera* cam, 
   return LNM_OK;
 }
 
+size_t lnm_march_batch_workspace_bytes(int32_t n, const lnm_volume* vols, const lnm_camera* cams,
+                                       const lnm_march_params* prms) {
+  if (n < 1 || n > 4096 || !vols || !cams || !prms) return 0;
+  size_t need = 0;
+  for (int i = 0; i < n; ++i) {
+    const size_t b = lnm_march_workspace_bytes(vols + i, cams + i, prms + i);
+    if (!b) return 0;
+    need = std::max(need, b);
+  }
+  return need;
+}
+
+lnm_status lnm_march_batch(lnm_ctx ctx, int32_t n, const lnm_volume* vols, const lnm_camera* cams,
+                           const lnm_march_params* prms, float* const* guides, void* workspace, size_t ws_bytes,
+                           void* stream) {
+  if (!ctx) return fail(LNM_ERR_ARG, "ctx is NULL");
+  if (n < 1 || n > 4096) return fail(LNM_ERR_ARG, "n must be in [1, 4096]");
+  if (!vols || !cams || !prms || !guides) return fail(LNM_ERR_ARG, "vols, cams, prms or guides is NULL");
+  std::vector<MarchDev> ms(n);
+  std::vector<CamDev> cs(n);
+  size_t need = 0;
+  for (int i = 0; i < n; ++i) {  // everything is checked before the first launch
+    if (!guides[i]) return fail(LNM_ERR_ARG, "guides[" + std::to_string(i) + "] is NULL");
+    const lnm_status st = march_setup(vols + i, cams + i, prms + i, &ms[i], &cs[i]);
+    if (st) return fail(st, "march " + std::to_string(i) + ": " + g_err);
+    need = std::max(need, march_scratch_bytes(ms[i], march_capacity(ms[i]), cs[i].W, cs[i].H));
+  }
+  if (!workspace || ws_bytes < need)
+    return fail(LNM_ERR_SHAPE, "march workspace too small: need " + std::to_string(need) + " bytes");
+  hipStream_t s = (hipStream_t)stream;
+  ProfScope ps(ctx, LNM_K_MARCH, s);
+  for (int i = 0; i < n; ++i) {
+    const int K = march_capacity(ms[i]);
+    LNM_HIP_CHECK(launch_march(ms[i], cs[i], march_buffers(workspace, ms[i], K, cs[i].W, cs[i].H), guides[i], s));
+  }
+  return LNM_OK;
+}
+
 size_t lnm_frame_workspace_bytes(lnm_net net, const lnm_volume* vol, const lnm_camera* cam,
                                  const lnm_march_params* prm) {
   MarchDev m;

@@ -22,7 +22,8 @@ LIGHTS_TOP_BOTTOM, LIGHTS_LEFT_RIGHT = 0, 1
 
 EXPORTS = [
     "lnm_abi_struct_size", "lnm_version", "lnm_ctx_create", "lnm_ctx_destroy", "lnm_last_error",
-    "lnm_march_workspace_bytes", "lnm_march", "lnm_reference_lightmaps", "lnm_net_param_count",
+    "lnm_march_workspace_bytes", "lnm_march", "lnm_march_batch_workspace_bytes", "lnm_march_batch",
+    "lnm_reference_lightmaps", "lnm_net_param_count",
     "lnm_net_device_bytes", "lnm_net_create", "lnm_net_destroy", "lnm_workspace_bytes", "lnm_infer", "lnm_frame",
     "lnm_composite", "lnm_profile_enable", "lnm_profile_read", "lnm_trainer_state_bytes", "lnm_frame_workspace_bytes",
     "lnm_train_workspace_bytes", "lnm_trainer_create", "lnm_trainer_destroy", "lnm_train_grad", "lnm_train_step",
@@ -101,6 +102,12 @@ def lib():
         L.lnm_frame_workspace_bytes.argtypes = [vp, C.POINTER(Volume), C.POINTER(Camera), C.POINTER(MarchParams)]
         L.lnm_march.restype = i32
         L.lnm_march.argtypes = [vp, C.POINTER(Volume), C.POINTER(Camera), C.POINTER(MarchParams), vp, vp, sz, vp]
+        L.lnm_march_batch_workspace_bytes.restype = sz
+        L.lnm_march_batch_workspace_bytes.argtypes = [i32, C.POINTER(Volume), C.POINTER(Camera),
+                                                      C.POINTER(MarchParams)]
+        L.lnm_march_batch.restype = i32
+        L.lnm_march_batch.argtypes = [vp, i32, C.POINTER(Volume), C.POINTER(Camera), C.POINTER(MarchParams),
+                                      C.POINTER(vp), vp, sz, vp]
         L.lnm_reference_lightmaps.restype = i32
         L.lnm_reference_lightmaps.argtypes = [vp, C.POINTER(Volume), C.POINTER(Camera), C.c_float, C.c_float, i32,
                                               vp, vp]
@@ -291,6 +298,33 @@ class Context:
         check(lib().lnm_march(self.handle, C.byref(vol), C.byref(c), C.byref(params), _ptr(out), _ptr(workspace),
                               workspace.numel(), _stream(stream)))
         return out
+
+    def march_batch(self, densities, sigma_scales, cams, params, outs=None, workspace=None, stream=None,
+                    bricks=None):
+        """n guiding maps in one call (lnm_march_batch): lists of grids,
+        extinction scales, cameras, march parameters (and optional bricks),
+        each march with its own sizes; returns the list of guides."""
+        import torch
+
+        n = len(densities)
+        if not (len(sigma_scales) == len(cams) == len(params) == n) or n == 0:
+            raise ValueError("densities, sigma_scales, cams and params must be non-empty lists of one length")
+        bricks = bricks if bricks is not None else [None] * n
+        vols = (Volume * n)(*[make_volume(d, ss, b) for d, ss, b in zip(densities, sigma_scales, bricks)])
+        camv = (Camera * n)(*[make_camera(c) for c in cams])
+        prmv = (MarchParams * n)(*params)
+        if outs is None:
+            outs = [torch.empty((c.height, c.width, 3), dtype=torch.float32, device=d.device)
+                    for c, d in zip(camv, densities)]
+        for o, c in zip(outs, camv):
+            _need(o, (c.height, c.width, 3), "guide")
+        if workspace is None:
+            nb = int(lib().lnm_march_batch_workspace_bytes(n, vols, camv, prmv))
+            workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=densities[0].device)
+        ptrs = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        check(lib().lnm_march_batch(self.handle, n, vols, camv, prmv, ptrs, _ptr(workspace), workspace.numel(),
+                                    _stream(stream)))
+        return outs
 
     def reference_lightmaps(self, density, sigma_scale, cam, step_voxels=0.25, ert_eps=1e-6, srgb=False, out=None,
                             stream=None):

@@ -114,11 +114,13 @@ class Backend:
             rgba = torch.empty((B, res, res, 4), dtype=torch.float32, device="cuda")
             ws = self.net.workspace(B, res, res)
             mws = torch.empty(self.batch_bytes(reqs, instances), dtype=torch.uint8, device="cuda")
-            for b, r in enumerate(reqs):
-                inst = instances[r.instance]
-                prm = lnm.make_params(inst.step_voxels, seed=inst.seed, frame=r.frame)
-                self.ctx.march(inst.density, inst.sigma_scale, inst.camera(r.frame), prm, out=guide[b],
-                               workspace=mws, stream=st, bricks=inst.bricks)
+            insts = [instances[r.instance] for r in reqs]
+            # the batch's marches in one call (ragged grids, one camera and seed each)
+            self.ctx.march_batch([i.density for i in insts], [i.sigma_scale for i in insts],
+                                 [i.camera(r.frame) for i, r in zip(insts, reqs)],
+                                 [lnm.make_params(i.step_voxels, seed=i.seed, frame=r.frame) for i, r in zip(insts, reqs)],
+                                 outs=[guide[b] for b in range(B)], workspace=mws, stream=st,
+                                 bricks=[i.bricks for i in insts])
             self.net.infer(guide, out=lm, workspace=ws, stream=st)
             for b, r in enumerate(reqs):
                 inst = instances[r.instance]

@@ -154,3 +154,35 @@ def test_prebuilt_bricks(ctx, orc):
         b = to_host(ctx.march(dens, 6.0, cam, p, bricks=br))
         assert np.array_equal(a, b)
         assert ctx.march_workspace_bytes(dens, 6.0, cam, p, bricks=br) < ctx.march_workspace_bytes(dens, 6.0, cam, p)
+
+
+def test_march_batch_equals_single_marches(ctx):
+    """lnm_march_batch (ragged: own grid, camera, step and seed per map)
+    gives each map bit for bit what lnm_march gives it alone; a bad entry
+    anywhere fails the call before anything is enqueued."""
+    import torch
+
+    from paper_2604_03748_amd import lnm
+
+    vols = [make_volume((20, 28, 36), 5, 17, noise_amp=0.3), make_volume(64, 8, 3, noise_amp=0.3),
+            make_volume((5, 3, 9), 2, 4)]
+    cams = [Camera(PERSPECTIVE, (-1.3, 2.1, 1.7), target=(0.55, 0.45, 0.5), up=(0.2, 0.1, 1.0), width=45, height=37),
+            headline().camera.resized(96, 64),
+            Camera(ORTHOGRAPHIC, (0.4, -2.0, 0.7), up=(0.0, 0.0, 1.0), ortho_half_extent=0.8, width=33, height=50)]
+    prms = [lnm.make_params(1.5, seed=5, frame=3), lnm.make_params(4.0, seed=0), lnm.make_params(0.75, seed=9)]
+    dens = [to_dev(v) for v in vols]
+    log("march batch of 3 ragged maps")
+    got = ctx.march_batch(dens, [6.0, 8.0, 3.0], cams, prms)
+    for i, (d, ss, c, p) in enumerate(zip(dens, [6.0, 8.0, 3.0], cams, prms)):
+        assert np.array_equal(to_host(got[i]), to_host(ctx.march(d, ss, c, p))), i
+    # a zero field of view in the last-but-one entry: error, and the first
+    # guide untouched
+    from dataclasses import replace
+
+    outs = [torch.full((c.height, c.width, 3), float("nan"), device="cuda") for c in cams]
+    bad = [cams[0], replace(cams[1], fov_y_deg=0.0), cams[2]]
+    with pytest.raises(lnm.LnmError):
+        ctx.march_batch(dens, [6.0, 8.0, 3.0], bad, prms, outs=outs,
+                        workspace=torch.empty(64 << 20, dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    assert np.isnan(to_host(outs[0])).all()
