@@ -309,10 +309,11 @@ def precision_report(lnm, ctx, wl, params, dens):
     return out, amax
 
 
-# the conv kernels and their tiling / split-K choice (layer_tiling in api.hip)
+# the conv kernels, their tiling / split-K choice (conv_layer_tiling in
+# conv.hip) and the head epilogue; the march kernels
 CONV_SOURCES = ("paper_2604_03748_amd/csrc/conv.hip", "paper_2604_03748_amd/csrc/conv_bf16.hip",
-                "paper_2604_03748_amd/csrc/conv_fp8.hip", "paper_2604_03748_amd/csrc/api.hip")
-MARCH_SOURCES = ("paper_2604_03748_amd/csrc/march.hip", "paper_2604_03748_amd/csrc/api.hip")
+                "paper_2604_03748_amd/csrc/conv_fp8.hip", "paper_2604_03748_amd/csrc/head.h")
+MARCH_SOURCES = ("paper_2604_03748_amd/csrc/march.hip", "paper_2604_03748_amd/csrc/ray.h")
 
 
 def source_hash(sources=CONV_SOURCES) -> str:

@@ -294,38 +294,8 @@ static void pack_layer(const LayerDesc& d, int precision, const float* w, const 
           for (int cc = 0; cc < d.ck; ++cc) *o++ = host_f2bf(W(t * kBN + n, ch * d.ck + cc, tap));
 }
 
-// Tile height and split-K factor of conv layer i at level size h x w (tiles
-// of th x 16 pixels x 32 output channels); the 3-channel input layer is
-// never split.  The split grows until the layer has 256 workgroups (fp32) or
-// 512 (bf16, fp8), the targets measured fastest per precision with the
-// split-K reductions counted.  fp32 layers take 4-row tiles where that
-// needs a smaller split than 8-row tiles (the deep levels: twice the
-// workgroups without partial sums to write, read and reduce) or where 8-row
-// tiles leave one workgroup per CU (nothing else on the CU hides a
-// workgroup's chunk-boundary stalls): 5 us per frame.  fp8 layers, whose
-// LDS footprint lets five 4-row workgroups share a CU, take 4-row tiles
-// throughout: 19 us per frame.  bf16 keeps 8-row tiles: its footprint
-// allows two workgroups per CU either way, and 4-row tiles measured 11 us
-// slower.
-struct LayerTiling {
-  int th, splits;
-};
-static LayerTiling layer_tiling(const lnm_net_s* net, int i, int B, int h, int w) {
-  const LayerDesc& d = net->layers[i];
-  if (d.ci == 3) return {8, 1};
-  const int target = net->precision == LNM_FP32 ? 256 : 512, nch = d.ci_pad / d.ck;
-  auto wgs = [&](int th) { return (long)((w + 15) / 16) * ((h + th - 1) / th) * B * (d.co_pad / kBN); };
-  const int s8 = conv_splits(wgs(8), nch, target);
-  const bool fp8 = net->precision == LNM_FP8_E4M3;
-  if (net->precision != LNM_BF16 && (s8 > 1 || wgs(8) <= 256 || fp8)) {
-    // the longest fp32 layers (16+ chunks) split on to two workgroups per CU
-    const int s4 = conv_splits(wgs(4), nch, net->precision == LNM_FP32 && nch >= 16 ? 512 : target);
-    if (s4 < s8 || wgs(8) <= 256 || fp8) return {4, s4};
-  }
-  return {8, s8};
-}
 static int layer_splits(const lnm_net_s* net, int i, int B, int h, int w) {
-  return layer_tiling(net, i, B, h, w).splits;
+  return conv_layer_tiling(net, i, B, h, w).splits;
 }
 
 static int layer_level(int L, int i) { return i < 2 * L ? i / 2 : L - 2 - (i - 2 * L) / 2; }
@@ -395,7 +365,7 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
       a.out_inv_scale = 1.0f / net->act_scale[li];
     }
     a.n_tiles = d.co_pad / kBN;
-    const LayerTiling tl = layer_tiling(net, li, B, a.H, a.W);
+    const LayerTiling tl = conv_layer_tiling(net, li, B, a.H, a.W);
     a.th = tl.th;
     a.splits = tl.splits;
     a.partial = reinterpret_cast<float*>(ws + p.partial_off);

@@ -10,7 +10,11 @@
 // from there.  The gather that fills the halo fuses the zero padding, the
 // 2x2 max-pool of the encoder (pooled input mode) and the decoder's nearest
 // 2x upsample + skip concatenation (two-source mode), so none of those
-// tensors is materialised.  The epilogue adds the bias and applies ReLU.
+// tensors is materialised.  The epilogue adds the bias and applies ReLU; in
+// the network's last layer it can instead apply the 1x1 head (and the
+// frame's shading) without storing the layer.  Layers with few tiles are
+// split over K and finished by splitk_reduce; conv_layer_tiling picks each
+// layer's tile height and split.
 //
 // K-slot permutation: MFMA step jj pairs lane group g (= lane / 16) with input
 // channel 4g + jj for both operands, so each lane fetches its four channels of
@@ -486,6 +490,34 @@ int conv_splits(long wgs, int nchunks, int target) {
   int s = 1;
   while (wgs * s < target && 2 * (s * 2) <= nchunks && s < 16) s *= 2;
   return s;
+}
+
+// Tile height and split-K factor of conv layer i at level size h x w (tiles
+// of th x 16 pixels x 32 output channels); the 3-channel input layer is
+// never split.  The split grows until the layer has 256 workgroups (fp32) or
+// 512 (bf16, fp8), the targets measured fastest per precision with the
+// split-K reductions counted.  fp32 layers take 4-row tiles where that
+// needs a smaller split than 8-row tiles (the deep levels: twice the
+// workgroups without partial sums to write, read and reduce) or where 8-row
+// tiles leave one workgroup per CU (nothing else on the CU hides a
+// workgroup's chunk-boundary stalls): 5 us per frame.  fp8 layers, whose
+// LDS footprint lets five 4-row workgroups share a CU, take 4-row tiles
+// throughout: 19 us per frame.  bf16 keeps 8-row tiles: its footprint
+// allows two workgroups per CU either way, and 4-row tiles measured 11 us
+// slower.
+LayerTiling conv_layer_tiling(const lnm_net_s* net, int i, int B, int h, int w) {
+  const LayerDesc& d = net->layers[i];
+  if (d.ci == 3) return {8, 1};
+  const int target = net->precision == LNM_FP32 ? 256 : 512, nch = d.ci_pad / d.ck;
+  auto wgs = [&](int th) { return (long)((w + 15) / 16) * ((h + th - 1) / th) * B * (d.co_pad / kBN); };
+  const int s8 = conv_splits(wgs(8), nch, target);
+  const bool fp8 = net->precision == LNM_FP8_E4M3;
+  if (net->precision != LNM_BF16 && (s8 > 1 || wgs(8) <= 256 || fp8)) {
+    // the longest fp32 layers (16+ chunks) split on to two workgroups per CU
+    const int s4 = conv_splits(wgs(4), nch, net->precision == LNM_FP32 && nch >= 16 ? 512 : target);
+    if (s4 < s8 || wgs(8) <= 256 || fp8) return {4, s4};
+  }
+  return {8, s8};
 }
 
 hipError_t launch_wgrad3x3(int mode, const WgradArgs& a, int* n_partials, hipStream_t s) {

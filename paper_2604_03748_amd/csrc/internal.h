@@ -120,6 +120,12 @@ struct ConvArgs {
 hipError_t launch_splitk_reduce(const ConvArgs& a, int out_type, hipStream_t s);
 // Splits for a layer launched with `wgs` workgroups over `nchunks` input chunks.
 int conv_splits(long wgs, int nchunks, int target);
+// Tile height (4 or 8 rows) and split-K factor of conv layer i of `net` at
+// level size h x w and batch B.
+struct LayerTiling {
+  int th, splits;
+};
+LayerTiling conv_layer_tiling(const lnm_net_s* net, int i, int B, int h, int w);
 struct HeadFuse;
 // head: the layer's epilogue also applies the 1x1 head (plain-input layers
 // of at most 32 output channels, unsplit), instead of storing the layer

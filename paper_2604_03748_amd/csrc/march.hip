@@ -2,11 +2,12 @@
 // reference lightmaps, fp32.
 //
 // The march first copies the density grid into 4^3-cell bricks (so the 8
-// corners of a trilinear sample are one short span of one 512-byte slot) and
-// then runs three kernels (see march_primary).  Pixels are handed out in
-// 16x16 tiles, an 8x8 sub-tile per wavefront, so the 64 rays of a wave are
-// spatially coherent and their gathers share cache lines; tiles are ordered
-// so that each XCD takes one band of the screen.
+// corners of a trilinear sample are one short span of one 512-byte slot),
+// cutting the screen's 8x8 tiles into eight bands of equal estimated work on
+// the way, then runs three kernels (see march_primary): the primary march
+// (four lanes per pixel, one band per XCD), the light marches (one lane per
+// recorded sample and light, an eighth of the records per XCD) and the
+// accumulation.  The fine-step reference kernel reads the linear grid.
 #include <cmath>
 
 #include "internal.h"
