@@ -38,7 +38,7 @@ typedef enum {
   LNM_ERR_SHAPE = 2,       /* inconsistent or unsupported sizes; workspace too small */
   LNM_ERR_OOM = 3,         /* a host allocation failed */
   LNM_ERR_DEVICE = 4,      /* a HIP runtime call failed */
-  LNM_ERR_UNSUPPORTED = 5  /* valid request this build does not implement */
+  LNM_ERR_UNSUPPORTED = 5  /* valid request the library does not implement */
 } lnm_status;
 
 typedef enum { LNM_FP32 = 0, LNM_BF16 = 1, LNM_FP8_E4M3 = 2 } lnm_precision;
