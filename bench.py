@@ -188,7 +188,7 @@ def dynamic_scene(lnm, ctx, frames, warmup=3):
     shading) is measured with HIP events on the stream, and the obstacle
     shadowing of the same frame (sphere depth map + shadowed shading) beside
     it; regenerating the density each frame is timed separately and not
-    counted."""
+    counted.  A few more frames with per-launch events give the stage split."""
     import torch
 
     from synth.scene import dynamic, light_direction, make_volume_torch, orbit_camera, rotate_y
@@ -234,8 +234,20 @@ def dynamic_scene(lnm, ctx, frames, warmup=3):
             gen_ms.append(e0.elapsed_time(e1))
             frame_ms.append(e1.elapsed_time(e2))
             shadow_ms.append(e2.elapsed_time(e3))
+    # stage split of the same frames: HIP events the library records around each launch
+    nprof = 5
+    ctx.profile(True)
+    for f in range(nprof):
+        prm.frame = f
+        net.frame(dens, 8.0, orbit_camera(f), prm, lights=[(tuple(rotate_y(light0, 0.5 * f)), (1.0, 1.0, 1.0))],
+                  guide=guide, lightmaps=lm, rgba=rgba, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    stages = {}
+    for name, k in (("march", lnm.K_MARCH), ("conv3x3", lnm.K_CONV), ("head_composite", lnm.K_HEAD)):
+        stages[name] = round(ctx.profile_read(k)[1] / nprof, 4)
+    ctx.profile(False)
     fm = np.array(frame_ms)
-    return {"workload": "dynamic256_1024px", "frames": frames, "dtype": "bf16",
+    return {"workload": "dynamic256_1024px", "frames": frames, "dtype": "bf16", "stages_ms_per_frame": stages,
             "method_frames_per_s": round(1e3 / fm.mean(), 2), "latency_ms_p50": round(float(np.median(fm)), 4),
             "latency_ms_p99": round(float(np.percentile(fm, 99)), 4),
             "shadow_ms_mean": round(float(np.mean(shadow_ms)), 4),

@@ -74,7 +74,6 @@ int march_capacity(const MarchDev& m);
 size_t march_scratch_bytes(const MarchDev& m, int K, int W, int H);
 MarchBuf march_buffers(void* ws, const MarchDev& m, int K, int W, int H);
 size_t bricks_bytes(int nx, int ny, int nz);
-// ctr (optional): band counters zeroed by the same launch.
 hipError_t launch_relayout(const MarchDev& m, float* bricks, hipStream_t s);
 hipError_t launch_march(const MarchDev& m, const CamDev& cam, const MarchBuf& buf, float* guide, hipStream_t s);
 hipError_t launch_reference(const MarchDev& m, const CamDev& cam, int srgb, float* lm, hipStream_t s);
