@@ -48,6 +48,13 @@ typedef enum { LNM_ORTHOGRAPHIC = 0, LNM_PERSPECTIVE = 1 } lnm_projection;
 typedef enum { LNM_QUAD_ALPHA = 0, LNM_QUAD_RIEMANN = 1 } lnm_quadrature;
 /* Side lights of the guiding map (see lnm_march_params). */
 typedef enum { LNM_LIGHTS_TOP_BOTTOM = 0, LNM_LIGHTS_LEFT_RIGHT = 1 } lnm_light_set;
+/* Order in which the march hands its light marches to the GPU's XCDs (see
+ * lnm_march_params); the guiding map is the same, bit for bit, in every
+ * order.  LNM_ORDER_BANDS: screen bands (best when the bricked grid fits the
+ * XCDs' L2 caches); LNM_ORDER_Z: the samples sorted by brick layer first
+ * (best for large grids, one more kernel and a larger workspace);
+ * LNM_ORDER_AUTO: z order when the bricked grid exceeds 32 MiB. */
+typedef enum { LNM_ORDER_AUTO = 0, LNM_ORDER_BANDS = 1, LNM_ORDER_Z = 2 } lnm_work_order;
 
 typedef struct lnm_ctx_s* lnm_ctx; /* per-device state: properties, error text */
 typedef struct lnm_net_s* lnm_net; /* host descriptor of a packed network */
@@ -107,7 +114,8 @@ typedef struct {
   int32_t quadrature; /* lnm_quadrature */
   float light_w[3];   /* front, first side, second side */
   int32_t light_set;  /* lnm_light_set */
-} lnm_march_params;   /* 48 bytes */
+  int32_t work_order; /* lnm_work_order; 0 (auto) for a zeroed struct */
+} lnm_march_params;   /* 56 bytes */
 
 /* A directional light for six-way shading: dir points toward the light (need
  * not be unit length; its camera-frame components weight the lightmaps). */

@@ -102,6 +102,8 @@ static lnm_status march_setup(const lnm_volume* vol, const lnm_camera* cam, cons
   if (!finite3(prm->light_w)) return fail(LNM_ERR_ARG, "params.light_w must be finite");
   if (prm->light_set != LNM_LIGHTS_TOP_BOTTOM && prm->light_set != LNM_LIGHTS_LEFT_RIGHT)
     return fail(LNM_ERR_ARG, "params.light_set");
+  if (prm->work_order != LNM_ORDER_AUTO && prm->work_order != LNM_ORDER_BANDS && prm->work_order != LNM_ORDER_Z)
+    return fail(LNM_ERR_ARG, "params.work_order");
   const int nmax = std::max(vol->nx, std::max(vol->ny, vol->nz));
   m->rho = vol->density;
   m->nx = vol->nx;
@@ -119,6 +121,7 @@ static lnm_status march_setup(const lnm_volume* vol, const lnm_camera* cam, cons
   m->wt = prm->light_w[1];
   m->wb = prm->light_w[2];
   m->light_set = prm->light_set;
+  m->zorder = march_use_zorder(prm->work_order, vol->nx, vol->ny, vol->nz) ? 1 : 0;
   m->brick = vol->bricks;  // NULL: launch_march builds them in its scratch
   m->nbx = m->nby = m->nbz = 0;
   return LNM_OK;

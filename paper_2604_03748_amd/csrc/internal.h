@@ -45,6 +45,7 @@ struct MarchDev {
   int quadrature;
   float wf, wt, wb;  // front and side light intensities
   int light_set;     // lnm_light_set
+  int zorder;        // light marches in z order (march_use_zorder), else band order
   const float* brick;  // bricked copy of rho (4^3 cells + apron per 128-float slot); caller's or scratch
   int nbx, nby, nbz;   // bricks per axis
 };
@@ -55,9 +56,12 @@ struct MarchBuf {
   float* tp;   // [K][P] transmittance before the sample, T_{n-1}
   float* tl;   // [2][K][P] transmittance toward the top / bottom (first / second side) light
   int* cnt;    // [P] recorded samples per pixel
-  int* ctr;    // [8] entries in each band's work list, then start[0..9) of the bands' tile ranges
-  int2* rec;   // work lists of the light marches, (pixel, k); band e's from entry start[e] * 64 * K
+  int* ctr;    // counter block: entries in each band's work list, the z-order unit counters, start[0..9)
+               // of the bands' tile ranges, the records per z bucket and the z-order scatter cursors
+  int2* rec;   // work lists of the primary march, (pixel, k); band e's from entry start[e] * 64 * K
   size_t cap;  // entries per band at equal bands (the lists hold 8 * cap)
+  uint8_t* zb;  // z order: [K][P] z bucket (brick layer) of each record's sample, else NULL
+  int2* srt;    // z order: [P * K] the records of all bands in z-bucket order, else NULL
   float* brick;
   int nbx, nby, nbz;
   int K, P;  // capacity per pixel, pixels
@@ -70,6 +74,9 @@ struct TileMap {
 };
 // Capacity per pixel: the most primary samples a ray can take in the support box.
 int march_capacity(const MarchDev& m);
+// Whether a march takes the z order (lnm_work_order; AUTO: grids whose
+// bricks exceed the XCDs' L2s together).
+bool march_use_zorder(int work_order, int nx, int ny, int nz);
 // Scratch of one march; the bricked grid is part of it unless m.brick is set.
 size_t march_scratch_bytes(const MarchDev& m, int K, int W, int H);
 MarchBuf march_buffers(void* ws, const MarchDev& m, int K, int W, int H);

@@ -6,8 +6,9 @@
 // cutting the screen's 8x8 tiles into eight bands of equal estimated work on
 // the way, then runs three kernels (see march_primary): the primary march
 // (four lanes per pixel, one band per XCD), the light marches (one lane per
-// recorded sample and light, an eighth of the records per XCD) and the
-// accumulation.  The fine-step reference kernel reads the linear grid.
+// recorded sample and light, an eighth of the records per XCD; on large
+// grids after a scatter of the records into z order) and the accumulation.
+// The fine-step reference kernel reads the linear grid.
 #include <cmath>
 
 #include "internal.h"
@@ -300,9 +301,24 @@ __device__ __forceinline__ void tile_pixel(int* i, int* j) {
 // lanes covers one tile with four lanes per pixel; each wavefront an 8x2
 // block.
 constexpr int kTile = 8;
-// start[0..8] of the band tile ranges, after the 8 band counters in the
-// march's 256-byte counter block
-constexpr int kBandStart = 16;
+// The march's counter block (ints): the 8 band counters, the light marches'
+// per-XCD next-unit counters from kUnitNext (z order), start[0..8] of the
+// band tile ranges from kBandStart, the record count of each z bucket from
+// kZHist and the z-order scatter cursors from kZCursor.
+constexpr int kUnitNext = 8, kBandStart = 16;
+constexpr int kZBuckets = 256;
+constexpr int kZHist = 32, kZCursor = kZHist + kZBuckets;
+constexpr size_t kCounterBytes = 4 * (kZCursor + kZBuckets);
+
+// z bucket of a sample point: the brick layer of its trilinear cell (the
+// bricks hold cells k' = floor(gz) + 1 in layer k' / 4), capped at the last
+// bucket.  A side light has no z component, so a light march stays in its
+// sample's bucket (the fallback lights of a ray along z and the left/right
+// set do not; the order then only loses locality).
+__device__ __forceinline__ int z_bucket(const MarchDev& m, float pz) {
+  const float gz = fminf(fmaxf(pz * (float)m.nz - 0.5f, -1.0f), (float)m.nz);
+  return min(((int)floorf(gz) + 1) >> 2, kZBuckets - 1);
+}
 __device__ __forceinline__ void tile_origin(const TileMap& tm, int L, int* tx, int* ty) {
   if (tm.band_rows) {
     *ty = L / tm.tiles_x;
@@ -353,12 +369,17 @@ __device__ __forceinline__ int wave_max(int v) {
 //   0. (relayout_balance: the bricked grid, and the band tile ranges)
 //   1. march_primary: four lanes per pixel walk the primary samples, write
 //      T and D, and record (t_n, A_n, T_{n-1}) of every sample with a
-//      nonzero weight in [k][P] planes; each wavefront then appends
+//      nonzero weight in [k][P] planes (in z order also the sample's z
+//      bucket, counting the records per bucket); each wavefront then appends
 //      (pixel, k) of its records, k-major, to its XCD band's work list;
-//   2. march_lights: one lane per work-list entry and light (the lists cut
-//      into eight equal ranges, one per XCD) marches toward that light and
+//   2. (z order: zsort_records scatters the band lists' entries into z-bucket
+//      order;)
+//   3. march_lights: one lane per record and light (the records cut into
+//      eight equal ranges, one per XCD) marches toward that light and
 //      stores its transmittance at (light, k, pixel);
-//   3. march_accumulate: one lane per pixel sums A_n L_n in sample order.
+//   4. march_accumulate: one lane per pixel sums A_n L_n in sample order.
+// Band order suits grids whose bricks fit the XCDs' L2s (each XCD's screen
+// band sees a slab of them); larger grids take z order (march_use_zorder).
 // The work lists keep the light-march lanes dense and spatially coherent (a
 // wave takes neighbouring pixels at similar depths) whatever the per-pixel
 // sample counts are; all three kernels read the bricked grid.
@@ -369,7 +390,7 @@ __device__ __forceinline__ float depth_step(float L, float sig, float h) { retur
 // starts at `list`, with four lanes per pixel (see below).
 __device__ __forceinline__ void primary_tile(const MarchDev& m, const CamDev& c, const TileMap& tm,
                                              const MarchBuf& buf, float* __restrict__ guide, int tile, int band,
-                                             int2* __restrict__ list) {
+                                             int2* __restrict__ list, int* zh) {
   int i, j;
   quad_pixel(tm, tile, &i, &j);
   const int s = threadIdx.x & 3;
@@ -442,6 +463,11 @@ __device__ __forceinline__ void primary_tile(const MarchDev& m, const CamDev& c,
         buf.t[r] = ((float)n + u) * h;
         buf.a[r] = Tprev * alpha;
         buf.tp[r] = Tprev;
+        if (m.zorder) {
+          const int zk = z_bucket(m, pz[q]);
+          buf.zb[r] = (uint8_t)zk;
+          atomicAdd(&zh[zk], 1);
+        }
       }
       if (active && dn == 0 && sig > m.depth_tau) dn = n;
       k = min(k + __popc(quad), buf.K);
@@ -486,13 +512,26 @@ __device__ __forceinline__ void primary_tile(const MarchDev& m, const CamDev& c,
 // march_balance so that the bands carry equal estimated work; its work list
 // starts at entry start[e] * 64 * K, room for K records of every pixel it
 // owns.  The band's blocks take its tiles in turn.
+// In z order the block also counts its records per z bucket in LDS and adds
+// them to the global counts at the end.
 __global__ __launch_bounds__(256) void march_primary(MarchDev m, CamDev c, TileMap tm, MarchBuf buf,
                                                      float* __restrict__ guide) {
+  __shared__ int zh[kZBuckets];
+  if (m.zorder) {
+    for (int q = threadIdx.x; q < kZBuckets; q += 256) zh[q] = 0;
+    __syncthreads();
+  }
   const int band = blockIdx.x & 7, slots = gridDim.x >> 3;
   const int* start = buf.ctr + kBandStart;
   const int lo = start[band], hi = start[band + 1];
   int2* list = buf.rec + (size_t)lo * (kTile * kTile) * (size_t)buf.K;
-  for (int L = lo + (int)(blockIdx.x >> 3); L < hi; L += slots) primary_tile(m, c, tm, buf, guide, L, band, list);
+  for (int L = lo + (int)(blockIdx.x >> 3); L < hi; L += slots)
+    primary_tile(m, c, tm, buf, guide, L, band, list, zh);
+  if (m.zorder) {
+    __syncthreads();
+    for (int q = threadIdx.x; q < kZBuckets; q += 256)
+      if (zh[q]) atomicAdd(buf.ctr + kZHist + q, zh[q]);
+  }
 }
 
 // Estimated cost of tile L: the primary samples of its centre ray (every
@@ -529,8 +568,10 @@ __device__ void balance_tiles(const MarchDev& m, const CamDev& c, const TileMap&
   const int a = min(ntiles, tid * per), b = min(ntiles, a + per);
   if (tid < 8) {
     ctr[tid] = 0;
+    ctr[kUnitNext + tid] = 0;
     sh.first[tid] = ntiles;
   }
+  for (int q = tid; q < 2 * kZBuckets; q += kBalanceThreads) ctr[kZHist + q] = 0;
   long long sum = 0;
   for (int L = a; L < b; ++L) {
     const int cst = tile_cost(m, c, tm, L);
@@ -585,17 +626,86 @@ __global__ __launch_bounds__(256) void relayout_balance(MarchDev m, CamDev c, Ti
   relayout_block(m.rho, m.nx, m.ny, m.nz, m.nbx, m.nby, brick, sh.rows, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
-// One lane per (work-list entry, light).  The band lists, concatenated in
-// band order, are one spatially ordered sequence of N records; it is cut
-// into 8 equal contiguous ranges, one per XCD (block b serves range b % 8,
-// the XCD that runs it under round-robin placement), so every XCD and its
-// L2 take an eighth of the light marches even when the smoke covers only a
-// few screen bands, and each range is still a compact slab of the volume.
-// A range is cut into 256-entry chunks and each chunk into two units, one
-// per light, so a workgroup marches one light direction; block b takes
-// units b / 8, b / 8 + slots, ...  Result: T toward the top (or first side)
-// light in tl[0][k][pixel], toward the bottom (second side) light in
-// tl[1][k][pixel].
+// Entry r of the band lists concatenated in band order.
+__device__ __forceinline__ int2 band_entry(const MarchBuf& buf, const int (&count)[8], int r) {
+  int band = 0, off = r;
+#pragma unroll
+  for (int e = 0; e < 7; ++e) {
+    if (band == e && off >= count[e]) {
+      off -= count[e];
+      band = e + 1;
+    }
+  }
+  return buf.rec[(size_t)buf.ctr[kBandStart + band] * (kTile * kTile) * (size_t)buf.K + off];
+}
+
+// Scatter the records of the band lists into z-bucket order (srt).  Bucket
+// b's records take entries [B_b, B_b + n_b), B the exclusive prefix sum of
+// the counts n the primary march took.  Per 256-entry chunk a block counts
+// its records per bucket in LDS, reserves each bucket's share with one
+// global atomic, and writes its entries there; within a bucket the chunks
+// keep their band order, so neighbouring entries stay neighbouring pixels.
+// Every write is bounded by its bucket's range.
+__global__ __launch_bounds__(256) void zsort_records(MarchBuf buf) {
+  __shared__ int scan[2][kZBuckets];
+  __shared__ int bstart[kZBuckets], bend[kZBuckets], lcount[kZBuckets], lbase[kZBuckets];
+  static_assert(kZBuckets == 256, "one lane per bucket");
+  const int tid = threadIdx.x;
+  const int n = buf.ctr[kZHist + tid];
+  scan[0][tid] = n;
+  __syncthreads();
+  int cur = 0;
+  for (int o = 1; o < kZBuckets; o <<= 1) {  // inclusive scan (Hillis-Steele)
+    scan[cur ^ 1][tid] = scan[cur][tid] + (tid >= o ? scan[cur][tid - o] : 0);
+    cur ^= 1;
+    __syncthreads();
+  }
+  bstart[tid] = scan[cur][tid] - n;
+  bend[tid] = scan[cur][tid];
+  int count[8], total = 0;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    count[e] = buf.ctr[e];
+    total += count[e];
+  }
+  for (long c0 = (long)blockIdx.x * 256; c0 < total; c0 += (long)gridDim.x * 256) {
+    lcount[tid] = 0;
+    __syncthreads();
+    const long r = c0 + tid;
+    int2 en = make_int2(0, 0);
+    int b = -1, rank = 0;
+    if (r < total) {
+      en = band_entry(buf, count, (int)r);
+      b = buf.zb[(size_t)en.y * buf.P + en.x];
+      rank = atomicAdd(&lcount[b], 1);
+    }
+    __syncthreads();
+    if (lcount[tid]) lbase[tid] = atomicAdd(buf.ctr + kZCursor + tid, lcount[tid]);
+    __syncthreads();
+    if (b >= 0) {
+      const long pos = (long)bstart[b] + lbase[b] + rank;
+      if (pos < bend[b]) buf.srt[pos] = en;
+    }
+    __syncthreads();
+  }
+}
+
+// One lane per (record, light).  The records, in band order (the band
+// lists concatenated: a spatially ordered sequence) or in z order (srt),
+// are cut into 8 equal contiguous ranges, one per XCD (block b serves range
+// b % 8, the XCD that runs it under round-robin placement), so every XCD
+// and its L2 take an eighth of the light marches even when the smoke covers
+// only a few screen bands.  A range is cut into 256-entry chunks and each
+// chunk into two units, one per light, so a workgroup marches one light
+// direction.  Band order: block b takes units b / 8, b / 8 + slots, ...  Z
+// order: the grid is the blocks resident at once; block b takes unit b / 8,
+// then units R, R + 1, ... in turn from its XCD's counter (R blocks per
+// XCD), so the units in flight stay adjacent and sweep the XCD's slab of
+// brick layers once, layer by layer (a side light keeps its sample's z, so
+// the bricks in use at a time are about one layer).  Result: T toward the
+// top (or first side) light in tl[0][k][pixel], toward the bottom (second
+// side) light in tl[1][k][pixel].
+template <bool Z>
 __global__ __launch_bounds__(256) void march_lights(MarchDev m, CamDev c, MarchBuf buf, int slots) {
   int count[8], total = 0;
 #pragma unroll
@@ -606,30 +716,37 @@ __global__ __launch_bounds__(256) void march_lights(MarchDev m, CamDev c, MarchB
   const int part = blockIdx.x & 7;
   const int lo = (int)((long)total * part / 8), hi = (int)((long)total * (part + 1) / 8);
   const int units = 2 * ((hi - lo + 255) / 256);
-  for (int unit = blockIdx.x >> 3; unit < units; unit += slots) {
-    const int light = unit & 1;
-    if ((light ? m.wb : m.wt) == 0.0f) continue;
-    const int r = lo + (unit >> 1) * 256 + threadIdx.x;
-    if (r >= hi) continue;
-    // band and position of record r in the concatenated lists
-    int band = 0, off = r;
-#pragma unroll
-    for (int e = 0; e < 7; ++e) {
-      if (band == e && off >= count[e]) {
-        off -= count[e];
-        band = e + 1;
-      }
+  const int R = gridDim.x >> 3;
+  __shared__ int s_unit;
+  for (int unit = blockIdx.x >> 3; unit < units;) {
+    do {  // one unit; `continue` leaves it
+      const int light = unit & 1;
+      if ((light ? m.wb : m.wt) == 0.0f) continue;
+      const int r = lo + (unit >> 1) * 256 + threadIdx.x;
+      if (r >= hi) continue;
+      const int2 en = Z ? buf.srt[r] : band_entry(buf, count, r);
+      // every entry of [0, total) is written by the primary march (and the
+      // scatter); the check keeps a lane that would see anything else in bounds
+      if ((unsigned)en.x >= (unsigned)buf.P || (unsigned)en.y >= (unsigned)buf.K) continue;
+      const int pix = en.x, k = en.y;
+      const size_t q = (size_t)k * buf.P + pix;
+      V3 o, d;
+      camera_ray(c, pix % c.W, pix / c.W, &o, &d);
+      const float t = buf.t[q];
+      V3 l = side_light(d, m.light_set);
+      if (light) l = v3(-l.x, -l.y, -l.z);
+      buf.tl[(size_t)light * buf.K * buf.P + q] =
+          light_transmittance_batched(m, v3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z), l);
+    } while (0);
+    if constexpr (Z) {
+      if (R >= units) break;
+      __syncthreads();
+      if (threadIdx.x == 0) s_unit = R + atomicAdd(buf.ctr + kUnitNext + part, 1);
+      __syncthreads();
+      unit = s_unit;
+    } else {
+      unit += slots;
     }
-    const int2 en = buf.rec[(size_t)buf.ctr[kBandStart + band] * (kTile * kTile) * (size_t)buf.K + off];
-    const int pix = en.x, k = en.y;
-    const size_t q = (size_t)k * buf.P + pix;
-    V3 o, d;
-    camera_ray(c, pix % c.W, pix / c.W, &o, &d);
-    const float t = buf.t[q];
-    V3 l = side_light(d, m.light_set);
-    if (light) l = v3(-l.x, -l.y, -l.z);
-    buf.tl[(size_t)light * buf.K * buf.P + q] =
-        light_transmittance_batched(m, v3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z), l);
   }
 }
 
@@ -719,17 +836,29 @@ size_t bricks_bytes(int nx, int ny, int nz) {
   return sizeof(float) * kBrickSlot * (size_t)bricks_along(nx) * bricks_along(ny) * bricks_along(nz);
 }
 
-constexpr size_t kLightSlots = 512;  // workgroups per band in march_lights
+constexpr size_t kLightSlots = 512;  // workgroups per band in march_lights (band order)
+// Bricked grids above this size (the eight XCDs' L2s together) take the z
+// order: measured at 256^3 / 1024^2, march 4.30 -> 2.73 ms; at 128^3 /
+// 256^2 the scatter's launch costs more than the order saves.
+constexpr size_t kZOrderBytes = (size_t)32 << 20;
 static int tiles_per_band(int W, int H) { return (((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) + 7) / 8; }
 
-// Scratch: [K][P] planes t, A, T_{n-1}, T_top, T_bottom; per-pixel counts; 8 band
-// counters; 8 band work lists of (pixel, k) with room for every sample of
-// the band's pixels; the bricked grid unless the caller supplies it.
+// Scratch: [K][P] planes t, A, T_{n-1}, T_top, T_bottom; per-pixel counts; the
+// counter block; 8 band work lists of (pixel, k) with room for every sample
+// of the band's pixels; in z order the [K][P] z-bucket plane and the
+// z-ordered list (room for every sample); the bricked grid unless the
+// caller supplies it.
 size_t march_scratch_bytes(const MarchDev& m, int K, int W, int H) {
   const size_t P = (size_t)W * H, plane = a256(sizeof(float) * (size_t)K * P);
   const size_t cap = (size_t)tiles_per_band(W, H) * kTile * kTile * K;
-  return 5 * plane + a256(sizeof(int) * P) + 256 + a256(8 * cap * sizeof(int2)) +
+  return 5 * plane + a256(sizeof(int) * P) + a256(kCounterBytes) + a256(8 * cap * sizeof(int2)) +
+         (m.zorder ? a256((size_t)K * P) + a256(sizeof(int2) * (size_t)K * P) : 0) +
          (m.brick ? 0 : a256(bricks_bytes(m.nx, m.ny, m.nz)));
+}
+
+bool march_use_zorder(int work_order, int nx, int ny, int nz) {
+  if (work_order != LNM_ORDER_AUTO) return work_order == LNM_ORDER_Z;
+  return bricks_bytes(nx, ny, nz) > kZOrderBytes;
 }
 
 MarchBuf march_buffers(void* ws, const MarchDev& m, int K, int W, int H) {
@@ -744,10 +873,18 @@ MarchBuf march_buffers(void* ws, const MarchDev& m, int K, int W, int H) {
   b.cnt = reinterpret_cast<int*>(p);
   p += a256(sizeof(int) * P);
   b.ctr = reinterpret_cast<int*>(p);
-  p += 256;
+  p += a256(kCounterBytes);
   b.cap = (size_t)tiles_per_band(W, H) * kTile * kTile * K;
   b.rec = reinterpret_cast<int2*>(p);
   p += a256(8 * b.cap * sizeof(int2));
+  b.zb = nullptr;
+  b.srt = nullptr;
+  if (m.zorder) {
+    b.zb = reinterpret_cast<uint8_t*>(p);
+    p += a256((size_t)K * P);
+    b.srt = reinterpret_cast<int2*>(p);
+    p += a256(sizeof(int2) * (size_t)K * P);
+  }
   b.brick = m.brick ? nullptr : reinterpret_cast<float*>(p);
   b.nbx = bricks_along(m.nx);
   b.nby = bricks_along(m.ny);
@@ -784,6 +921,22 @@ static TileMap tile_map(const CamDev& c) {
   return tm;
 }
 
+// Light-march blocks per XCD in z order: as many as are resident at once
+// (the occupancy of march_lights on one XCD's CUs), at least one.
+static int light_blocks_per_xcd() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, march_lights<true>, 256, 0) == hipSuccess)
+      n = std::max(1, per_cu * cus / 8);
+    else
+      n = (int)kLightSlots;
+  }
+  return n;
+}
+
 hipError_t launch_march(const MarchDev& m0, const CamDev& cam, const MarchBuf& buf, float* guide, hipStream_t s) {
   MarchDev m = m0;
   m.nbx = buf.nbx;
@@ -798,10 +951,17 @@ hipError_t launch_march(const MarchDev& m0, const CamDev& cam, const MarchBuf& b
     hipLaunchKernelGGL(march_balance, dim3(1), dim3(kBalanceThreads), 0, s, m, cam, tm, buf.ctr);
   }
   hipLaunchKernelGGL(march_primary, dim3(8 * tm.per_xcd), dim3(256), 0, s, m, cam, tm, buf, guide);
-  // enough workgroups to fill the chip a few times over; each loops over its
-  // eighth of the records
-  const int slots = (int)std::min<size_t>((buf.cap + 255) / 256, kLightSlots);
-  hipLaunchKernelGGL(march_lights, dim3(8 * slots), dim3(256), 0, s, m, cam, buf, slots);
+  if (m.zorder) {
+    // the blocks resident at once; each loops over units of its XCD's range
+    const int slots = (int)std::min<size_t>((buf.cap + 255) / 256, (size_t)light_blocks_per_xcd());
+    hipLaunchKernelGGL(zsort_records, dim3(8 * slots), dim3(256), 0, s, buf);
+    hipLaunchKernelGGL(march_lights<true>, dim3(8 * slots), dim3(256), 0, s, m, cam, buf, slots);
+  } else {
+    // enough workgroups to fill the chip a few times over; each loops over
+    // its eighth of the records
+    const int slots = (int)std::min<size_t>((buf.cap + 255) / 256, kLightSlots);
+    hipLaunchKernelGGL(march_lights<false>, dim3(8 * slots), dim3(256), 0, s, m, cam, buf, slots);
+  }
   hipLaunchKernelGGL(march_accumulate, dim3((buf.P + 255) / 256), dim3(256), 0, s, m, buf, guide);
   return hipGetLastError();
 }

@@ -19,6 +19,7 @@ FP32, BF16, FP8_E4M3 = 0, 1, 2
 ORTHOGRAPHIC, PERSPECTIVE = 0, 1
 QUAD_ALPHA, QUAD_RIEMANN = 0, 1
 LIGHTS_TOP_BOTTOM, LIGHTS_LEFT_RIGHT = 0, 1
+ORDER_AUTO, ORDER_BANDS, ORDER_Z = 0, 1, 2
 
 EXPORTS = [
     "lnm_abi_struct_size", "lnm_version", "lnm_ctx_create", "lnm_ctx_destroy", "lnm_last_error",
@@ -55,7 +56,8 @@ class Camera(C.Structure):
 class MarchParams(C.Structure):
     _fields_ = [("step_voxels", C.c_float), ("depth_tau", C.c_float), ("ert_eps", C.c_float),
                 ("jitter_on", C.c_int32), ("jitter_seed", C.c_uint64), ("frame", C.c_uint32),
-                ("quadrature", C.c_int32), ("light_w", C.c_float * 3), ("light_set", C.c_int32)]
+                ("quadrature", C.c_int32), ("light_w", C.c_float * 3), ("light_set", C.c_int32),
+                ("work_order", C.c_int32)]
 
 
 class Light(C.Structure):
@@ -199,7 +201,7 @@ def make_camera(cam) -> Camera:
 
 
 def make_params(step_voxels, depth_tau=0.1, ert_eps=1e-6, jitter=True, seed=0, frame=0, quadrature=QUAD_ALPHA,
-                light_w=(1.0, 1.0, 1.0), light_set=0) -> MarchParams:
+                light_w=(1.0, 1.0, 1.0), light_set=0, work_order=0) -> MarchParams:
     p = MarchParams()
     p.step_voxels = step_voxels
     p.depth_tau = depth_tau
@@ -210,6 +212,7 @@ def make_params(step_voxels, depth_tau=0.1, ert_eps=1e-6, jitter=True, seed=0, f
     p.quadrature = int(quadrature)
     p.light_w[:] = [float(v) for v in light_w]
     p.light_set = int(light_set)
+    p.work_order = int(work_order)
     return p
 
 

@@ -23,7 +23,7 @@ def _run(ctx, vol, ss, cam, step, **kw):
     p = lnm.make_params(step, depth_tau=kw.get("depth_tau", 0.1), ert_eps=kw.get("ert_eps", 1e-6),
                         jitter=kw.get("jitter", True), seed=kw.get("seed", 0), frame=kw.get("frame", 0),
                         quadrature=kw.get("quadrature", 0), light_w=kw.get("light_w", (1.0, 1.0, 1.0)),
-                        light_set=kw.get("light_set", 0))
+                        light_set=kw.get("light_set", 0), work_order=kw.get("work_order", 0))
     g = ctx.march(to_dev(vol), ss, cam, p)
     return to_host(g)
 
@@ -120,6 +120,12 @@ def test_dynamic_scene_full_size_sampled(ctx, orc):
 
     cam = orbit_camera(37)
     _both(ctx, orc, vol, 8.0, cam, wl.step_voxels, "dynamic256_1024px_stride16", stride=16, frame=37)
+    # this grid takes the z order by default; the band order gives the same map at every pixel
+    from paper_2604_03748_amd import lnm
+
+    a = _run(ctx, vol, 8.0, cam, wl.step_voxels, frame=37)
+    b = _run(ctx, vol, 8.0, cam, wl.step_voxels, frame=37, work_order=lnm.ORDER_BANDS)
+    assert np.array_equal(a, b)
 
 
 def _bricks_numpy(vol):
@@ -154,6 +160,40 @@ def test_prebuilt_bricks(ctx, orc):
         b = to_host(ctx.march(dens, 6.0, cam, p, bricks=br))
         assert np.array_equal(a, b)
         assert ctx.march_workspace_bytes(dens, 6.0, cam, p, bricks=br) < ctx.march_workspace_bytes(dens, 6.0, cam, p)
+
+
+def test_work_orders_agree(ctx, orc):
+    """The light marches' work order (screen bands, or records sorted by
+    brick layer and taken by each XCD in turn) changes nothing in the
+    guiding map: bit for bit equal, on cameras whose side lights stay in z
+    planes and on ones whose lights do not (view along z, left/right set)."""
+    from paper_2604_03748_amd import lnm
+
+    wl = headline()
+    ragged = make_volume((20, 28, 36), 5, 17, noise_amp=0.3)
+    cases = [
+        ("headline", wl.volume(), 8.0, wl.camera, wl.step_voxels, {}),
+        ("ragged", ragged, 6.0, Camera(PERSPECTIVE, (-1.3, 2.1, 1.7), target=(0.55, 0.45, 0.5), up=(0.2, 0.1, 1.0),
+                                        fov_y_deg=48.0, width=45, height=37), 1.5, {"seed": 5, "frame": 3}),
+        ("view_along_z", make_volume(24, 5, 2), 8.0,
+         Camera(ORTHOGRAPHIC, (0.5, 0.5, 3.0), target=(0.5, 0.5, 0.5), up=(0.0, 1.0, 0.0), width=24, height=24),
+         1.0, {"light_w": (0.0, 1.0, 0.5)}),
+        ("left_right", ragged, 6.0, Camera(ORTHOGRAPHIC, (0.4, -2.0, 0.7), up=(0.0, 0.0, 1.0), ortho_half_extent=0.8,
+                                           width=33, height=50), 0.75, {"light_set": 1, "seed": 9}),
+        ("dense_riemann", small_ortho().volume() * 6.0, 8.0, small_ortho().camera, 1.0, {"quadrature": 1}),
+    ]
+    for what, vol, ss, cam, step, kw in cases:
+        log(f"work orders: {what}")
+        a = _run(ctx, vol, ss, cam, step, work_order=lnm.ORDER_BANDS, **kw)
+        b = _run(ctx, vol, ss, cam, step, work_order=lnm.ORDER_Z, **kw)
+        assert np.array_equal(a, b), what
+        assert np.array_equal(a, _run(ctx, vol, ss, cam, step, **kw)), what  # auto: bands on these grids
+    dens = to_dev(ragged)
+    cam = cases[1][3]
+    pb, pz = lnm.make_params(1.5, work_order=lnm.ORDER_BANDS), lnm.make_params(1.5, work_order=lnm.ORDER_Z)
+    assert ctx.march_workspace_bytes(dens, 6.0, cam, pz) > ctx.march_workspace_bytes(dens, 6.0, cam, pb)
+    with pytest.raises(lnm.LnmError):
+        ctx.march(dens, 6.0, cam, lnm.make_params(1.5, work_order=3))
 
 
 def test_march_batch_equals_single_marches(ctx):
