@@ -641,11 +641,12 @@ __device__ __forceinline__ int2 band_entry(const MarchBuf& buf, const int (&coun
 
 // Scatter the records of the band lists into z-bucket order (srt).  Bucket
 // b's records take entries [B_b, B_b + n_b), B the exclusive prefix sum of
-// the counts n the primary march took.  Per 256-entry chunk a block counts
-// its records per bucket in LDS, reserves each bucket's share with one
-// global atomic, and writes its entries there; within a bucket the chunks
-// keep their band order, so neighbouring entries stay neighbouring pixels.
-// Every write is bounded by its bucket's range.
+// the counts n the primary march took.  Each block takes one contiguous
+// share of the band-order records: it counts them per bucket in LDS,
+// reserves each bucket's share with one global atomic, and writes its
+// entries there on a second pass, so within a bucket the entries come in
+// runs of neighbouring pixels.  Every write is bounded by its bucket's
+// range.
 __global__ __launch_bounds__(256) void zsort_records(MarchBuf buf) {
   __shared__ int scan[2][kZBuckets];
   __shared__ int bstart[kZBuckets], bend[kZBuckets], lcount[kZBuckets], lbase[kZBuckets];
@@ -653,6 +654,7 @@ __global__ __launch_bounds__(256) void zsort_records(MarchBuf buf) {
   const int tid = threadIdx.x;
   const int n = buf.ctr[kZHist + tid];
   scan[0][tid] = n;
+  lcount[tid] = 0;
   __syncthreads();
   int cur = 0;
   for (int o = 1; o < kZBuckets; o <<= 1) {  // inclusive scan (Hillis-Steele)
@@ -668,25 +670,22 @@ __global__ __launch_bounds__(256) void zsort_records(MarchBuf buf) {
     count[e] = buf.ctr[e];
     total += count[e];
   }
-  for (long c0 = (long)blockIdx.x * 256; c0 < total; c0 += (long)gridDim.x * 256) {
-    lcount[tid] = 0;
-    __syncthreads();
-    const long r = c0 + tid;
-    int2 en = make_int2(0, 0);
-    int b = -1, rank = 0;
-    if (r < total) {
-      en = band_entry(buf, count, (int)r);
-      b = buf.zb[(size_t)en.y * buf.P + en.x];
-      rank = atomicAdd(&lcount[b], 1);
-    }
-    __syncthreads();
-    if (lcount[tid]) lbase[tid] = atomicAdd(buf.ctr + kZCursor + tid, lcount[tid]);
-    __syncthreads();
-    if (b >= 0) {
-      const long pos = (long)bstart[b] + lbase[b] + rank;
-      if (pos < bend[b]) buf.srt[pos] = en;
-    }
-    __syncthreads();
+  const long per = ((long)total + gridDim.x - 1) / gridDim.x;
+  const int r0 = (int)min((long)total, (long)blockIdx.x * per), r1 = (int)min((long)total, (long)r0 + per);
+  for (int r = r0 + tid; r < r1; r += 256) {
+    const int2 en = band_entry(buf, count, r);
+    atomicAdd(&lcount[buf.zb[(size_t)en.y * buf.P + en.x]], 1);
+  }
+  __syncthreads();
+  const int mine = lcount[tid];
+  if (mine) lbase[tid] = atomicAdd(buf.ctr + kZCursor + tid, mine);
+  lcount[tid] = 0;  // now the block's cursor per bucket
+  __syncthreads();
+  for (int r = r0 + tid; r < r1; r += 256) {
+    const int2 en = band_entry(buf, count, r);
+    const int b = buf.zb[(size_t)en.y * buf.P + en.x];
+    const long pos = (long)bstart[b] + lbase[b] + atomicAdd(&lcount[b], 1);
+    if (pos < bend[b]) buf.srt[pos] = en;
   }
 }
 
