@@ -139,6 +139,57 @@ __device__ __forceinline__ void sample_batch(const MarchDev& m, const float (&px
   for (int q = 0; q < N; ++q) out[q] = brick_lerp(m, t[q], c[q]);
 }
 
+// The z part of brick_tap for points that share one z (a light march whose
+// direction has no z component): computed once per march, selected per
+// sample (an outside point takes the origin's values, as in brick_tap), so
+// the taps are the same, bit for bit.
+struct FlatZ {
+  bool in;        // gz inside (-1, nz)
+  uint32_t zrow;  // (k >> 2) * nby for the point's cell index k
+  uint32_t zoff;  // (k & 3) * 25
+  float fz;
+};
+__device__ __forceinline__ FlatZ flat_z(const MarchDev& m, float pz) {
+  const float gz = pz * (float)m.nz - 0.5f;
+  FlatZ z;
+  z.in = gz > -1.0f && gz < (float)m.nz;
+  const float cz = z.in ? gz : 0.0f, fz0 = floorf(cz);
+  const uint32_t k = (uint32_t)((int)fz0 + 1);
+  z.zrow = (k >> 2) * (uint32_t)m.nby;
+  z.zoff = (k & 3u) * 25u;
+  z.fz = cz - fz0;
+  return z;
+}
+__device__ __forceinline__ BrickTap brick_tap_flat(const MarchDev& m, float px, float py, const FlatZ& z) {
+  const float gx = px * (float)m.nx - 0.5f, gy = py * (float)m.ny - 0.5f;
+  const bool inside = z.in && gx > -1.0f && gy > -1.0f && gx < (float)m.nx && gy < (float)m.ny;
+  const float cx = inside ? gx : 0.0f, cy = inside ? gy : 0.0f;
+  const float fx0 = floorf(cx), fy0 = floorf(cy);
+  const uint32_t i = (uint32_t)((int)fx0 + 1), j = (uint32_t)((int)fy0 + 1);
+  // the origin's cell index is k = 1: row 0, offset 25
+  const uint32_t brick = ((inside ? z.zrow : 0u) + (j >> 2)) * (uint32_t)m.nbx + (i >> 2);
+  BrickTap t;
+  t.r = m.brick + (brick * (uint32_t)kBrickSlot + ((inside ? z.zoff : 25u) + (j & 3u) * 5u + (i & 3u)));
+  t.fx = cx - fx0;
+  t.fy = cy - fy0;
+  t.fz = inside ? z.fz : 0.0f;
+  t.mask = inside ? 1.0f : 0.0f;
+  return t;
+}
+template <int N>
+__device__ __forceinline__ void sample_batch_flat(const MarchDev& m, const float (&px)[N], const float (&py)[N],
+                                                  const FlatZ& z, float (&out)[N]) {
+  BrickTap t[N];
+  BrickVals c[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) t[q] = brick_tap_flat(m, px[q], py[q], z);
+#pragma unroll
+  for (int q = 0; q < N; ++q) c[q] = brick_load(t[q]);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int q = 0; q < N; ++q) out[q] = brick_lerp(m, t[q], c[q]);
+}
+
 // Fill the bricked grid from the caller's linear grid (HBM-bound copy; once
 // per march, or once per grid with lnm_make_bricks).  Workgroup = 31
 // consecutive bricks along x at one (by, bz): it stages the 25 source rows
@@ -265,9 +316,13 @@ __device__ __forceinline__ float light_transmittance(const MarchDev& m, V3 x, V3
 // march are gathered four at a time (all loads issued before any is used)
 // and summed in order; the march stops at the termination limit.  Same
 // result as light_transmittance<true>.
+// FLAT: l has no z component, so every sample has the z of x (x.z + t * 0
+// is x.z exactly) and the z part of the taps is computed once.
+template <bool FLAT>
 __device__ __forceinline__ float light_transmittance_batched(const MarchDev& m, V3 x, V3 l) {
   const float h = m.h, lim = m.tau_max / h;
   const int kmax = light_steps(m, x, l, h);
+  const FlatZ fz = flat_z(m, FLAT ? x.z : 0.0f);
   float acc = 0.0f;
   for (int k = 1; k <= kmax; k += 4) {
     float px[4], py[4], pz[4], sv[4];
@@ -278,7 +333,10 @@ __device__ __forceinline__ float light_transmittance_batched(const MarchDev& m, 
       py[q] = x.y + t * l.y;
       pz[q] = x.z + t * l.z;
     }
-    sample_batch<4>(m, px, py, pz, sv);
+    if constexpr (FLAT)
+      sample_batch_flat<4>(m, px, py, fz, sv);
+    else
+      sample_batch<4>(m, px, py, pz, sv);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       acc += k + q <= kmax ? sv[q] : 0.0f;
@@ -734,8 +792,9 @@ __global__ __launch_bounds__(256) void march_lights(MarchDev m, CamDev c, MarchB
       const float t = buf.t[q];
       V3 l = side_light(d, m.light_set);
       if (light) l = v3(-l.x, -l.y, -l.z);
+      const V3 x = v3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
       buf.tl[(size_t)light * buf.K * buf.P + q] =
-          light_transmittance_batched(m, v3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z), l);
+          l.z == 0.0f ? light_transmittance_batched<true>(m, x, l) : light_transmittance_batched<false>(m, x, l);
     } while (0);
     if constexpr (Z) {
       if (R >= units) break;
