@@ -511,6 +511,14 @@ LayerTiling conv_layer_tiling(const lnm_net_s* net, int i, int B, int h, int w) 
   const int target = net->precision == LNM_FP32 ? 256 : 512, nch = d.ci_pad / d.ck;
   auto wgs = [&](int th) { return (long)((w + 15) / 16) * ((h + th - 1) / th) * B * (d.co_pad / kBN); };
   const int s8 = conv_splits(wgs(8), nch, target);
+  if (net->precision == LNM_BF16 && s8 == 1) {
+    // large bf16 layers: the 64-channel tile, when it still gives two
+    // workgroups per CU
+    const int nt = d.co_pad / kBN;
+    const long large =
+        (long)((w + 15) / 16) * ((h + kBf16LargeRows - 1) / kBf16LargeRows) * B * ((nt + 1) / 2);
+    if (nt >= 2 && large >= 512) return {kBf16Large, 1};
+  }
   const bool fp8 = net->precision == LNM_FP8_E4M3;
   if (net->precision != LNM_BF16 && (s8 > 1 || wgs(8) <= 256 || fp8)) {
     // the longest fp32 layers (16+ chunks) split on to two workgroups per CU

@@ -21,6 +21,10 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+// 16 bytes as a native vector: arrays of these stay in registers (arrays of
+// the u32x4 struct are copied member-wise through memory and were kept in
+// scratch)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTW = 16;
 constexpr int kHW = kTW + 2;
@@ -50,7 +54,7 @@ __device__ __forceinline__ uint32_t max_bf16x2(uint32_t a, uint32_t b) {
 // together and nothing waits on them before the current chunk's matrix work.
 template <int MODE>
 struct Halo {
-  uint4 v[MODE == G_POOL ? 4 : 1];
+  u32x4 v[MODE == G_POOL ? 4 : 1];
 };
 
 template <int MODE>
@@ -58,38 +62,38 @@ __device__ __forceinline__ Halo<MODE> halo_load(const ConvArgs& a, int b, int y,
   const uint16_t* s0 = static_cast<const uint16_t*>(a.src0);
   Halo<MODE> h;
   if constexpr (MODE == G_PLAIN) {
-    h.v[0] = *reinterpret_cast<const uint4*>(s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c);
+    h.v[0] = *reinterpret_cast<const u32x4*>(s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c);
   } else if constexpr (MODE == G_POOL) {
     const size_t W2 = 2 * (size_t)a.W, c0 = (size_t)a.c0;
     const uint16_t* p = s0 + ((size_t)(b * 2 * a.H + 2 * y) * W2 + 2 * x) * c0 + c;
-    h.v[0] = *reinterpret_cast<const uint4*>(p);
-    h.v[1] = *reinterpret_cast<const uint4*>(p + c0);
-    h.v[2] = *reinterpret_cast<const uint4*>(p + W2 * c0);
-    h.v[3] = *reinterpret_cast<const uint4*>(p + W2 * c0 + c0);
+    h.v[0] = *reinterpret_cast<const u32x4*>(p);
+    h.v[1] = *reinterpret_cast<const u32x4*>(p + c0);
+    h.v[2] = *reinterpret_cast<const u32x4*>(p + W2 * c0);
+    h.v[3] = *reinterpret_cast<const u32x4*>(p + W2 * c0 + c0);
   } else {  // G_CONCAT_UP: channels [0, c0) from the skip, then the upsampled low-res tensor
     const int Hl = a.H >> 1, Wl = a.W >> 1;
     const uint16_t* skip = s0 + ((size_t)(b * a.H + y) * a.W + x) * a.c0 + c;
     const uint16_t* up = static_cast<const uint16_t*>(a.src1) +
                          ((size_t)(b * Hl + (y >> 1)) * Wl + (x >> 1)) * a.c1 + max(c - a.c0, 0);
-    h.v[0] = *reinterpret_cast<const uint4*>(c < a.c0 ? skip : up);
+    h.v[0] = *reinterpret_cast<const u32x4*>(c < a.c0 ? skip : up);
   }
   return h;
 }
 
 template <int MODE>
-__device__ __forceinline__ uint4 halo_value(const Halo<MODE>& h, bool ok) {
-  uint4 r = h.v[0];
+__device__ __forceinline__ u32x4 halo_value(const Halo<MODE>& h, bool ok) {
+  u32x4 r = h.v[0];
   if constexpr (MODE == G_POOL) {
     r.x = max_bf16x2(max_bf16x2(h.v[0].x, h.v[1].x), max_bf16x2(h.v[2].x, h.v[3].x));
     r.y = max_bf16x2(max_bf16x2(h.v[0].y, h.v[1].y), max_bf16x2(h.v[2].y, h.v[3].y));
     r.z = max_bf16x2(max_bf16x2(h.v[0].z, h.v[1].z), max_bf16x2(h.v[2].z, h.v[3].z));
     r.w = max_bf16x2(max_bf16x2(h.v[0].w, h.v[1].w), max_bf16x2(h.v[2].w, h.v[3].w));
   }
-  return ok ? r : make_uint4(0, 0, 0, 0);
+  return ok ? r : u32x4{0u, 0u, 0u, 0u};
 }
 
-template <int TH>
-__device__ __forceinline__ void store_tile(const ConvArgs& a, const f4 (&acc)[TH / 4][2], int b, int y0, int x0,
+template <int TH, int NF = 2>
+__device__ __forceinline__ void store_tile(const ConvArgs& a, const f4 (&acc)[TH / 4][NF], int b, int y0, int x0,
                                            int wrow, int g, int li, int nt, int ks) {
   uint16_t* out = static_cast<uint16_t*>(a.out);
 #pragma unroll
@@ -97,7 +101,7 @@ __device__ __forceinline__ void store_tile(const ConvArgs& a, const f4 (&acc)[TH
     const int y = y0 + wrow + mf;
     if (y >= a.H) continue;
 #pragma unroll
-    for (int nf = 0; nf < 2; ++nf) {
+    for (int nf = 0; nf < NF; ++nf) {
       const int n = nt * kBN + nf * 16 + li;
       if (n >= a.co) continue;
       const float bias = a.bias[n];
@@ -118,33 +122,42 @@ __device__ __forceinline__ void store_tile(const ConvArgs& a, const f4 (&acc)[TH
   }
 }
 
-template <int MODE, int TH, bool HEAD>
+// NB output-channel tiles of 32 per workgroup (NF = 2 NB 16-column MFMA
+// blocks per wave) and NBUF LDS buffers: the default is one tile, double
+// buffered; the large-layer form (8 rows x 64 channels, 2 x 4 blocks per
+// wave: a quarter fewer LDS reads per MFMA, and the halo read once for 64
+// channels) is single buffered, its next chunk prefetched into registers,
+// so two workgroups share a CU.  (16 rows x 64 channels, 4 x 4 blocks, needs
+// more than 256 registers per lane: one wave per SIMD, and slower.)
+template <int MODE, int TH, bool HEAD, int NB = 1, int NBUF = 2>
 __global__ __launch_bounds__(256) void conv3x3_bf16(ConvArgs a, HeadFuse hf) {
-  constexpr int MF = TH / 4;
-  // two LDS buffers: the next chunk is fetched into registers while the
-  // matrix cores work on the current one
-  __shared__ __attribute__((aligned(16))) uint16_t s_in[2][(TH + 2) * kHW * kPad];
-  __shared__ __attribute__((aligned(16))) uint16_t s_w[2][9 * kBN * kPad];
+  constexpr int MF = TH / 4, NF = 2 * NB, BN = kBN * NB;
+  __shared__ __attribute__((aligned(16))) uint16_t s_in[NBUF][(TH + 2) * kHW * kPad];
+  __shared__ __attribute__((aligned(16))) uint16_t s_w[NBUF][9 * BN * kPad];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tiles_y = (a.H + TH - 1) / TH;
   const int b = blockIdx.y / tiles_y;
   const int y0 = (blockIdx.y - b * tiles_y) * TH, x0 = blockIdx.x * kTW;
   const int g = lane >> 4, li = lane & 15, wrow = wave * MF;
-  const int nt = blockIdx.z % a.n_tiles, ks = blockIdx.z / a.n_tiles;
+  const int groups = (a.n_tiles + NB - 1) / NB;
+  const int nt = (blockIdx.z % groups) * NB, ks = blockIdx.z / groups;
   const int nchunks = a.ci_pad / kCK;
   const int ch_lo = ks * nchunks / a.splits, ch_hi = (ks + 1) * nchunks / a.splits;
   const int ci = a.c0 + a.c1;  // real input channels (the rest of ci_pad is zero padding)
-  const uint16_t* wblk = static_cast<const uint16_t*>(a.w) + (size_t)nt * nchunks * 9 * kBN * kCK;
+  const size_t tile_elems = (size_t)nchunks * 9 * kBN * kCK;  // one n-tile's packed weights
+  const uint16_t* wblk = static_cast<const uint16_t*>(a.w) + (size_t)nt * tile_elems;
 
-  f4 acc[MF][2];
+  f4 acc[MF][NF];
 #pragma unroll
-  for (int mf = 0; mf < MF; ++mf) acc[mf][0] = acc[mf][1] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int mf = 0; mf < MF; ++mf)
+#pragma unroll
+    for (int nf = 0; nf < NF; ++nf) acc[mf][nf] = f4{0.f, 0.f, 0.f, 0.f};
 
-  constexpr int NQ = (TH + 2) * kHW * (kCK / 8), NW = 9 * kBN * kCK / 8;
+  constexpr int NQ = (TH + 2) * kHW * (kCK / 8), NW = 9 * BN * kCK / 8;
   constexpr int RQ = (NQ + 255) / 256, RW = (NW + 255) / 256;
   Halo<MODE> rq[RQ];
-  uint4 rw[RW];
+  u32x4 rw[RW];
   unsigned ok = 0;
   auto fetch = [&](int ch) {
     ok = 0;
@@ -159,19 +172,28 @@ __global__ __launch_bounds__(256) void conv3x3_bf16(ConvArgs a, HeadFuse hf) {
     }
     const uint16_t* wsrc = wblk + (size_t)ch * 9 * kBN * kCK;
 #pragma unroll
-    for (int r = 0; r < RW; ++r) rw[r] = *reinterpret_cast<const uint4*>(wsrc + 8 * min(tid + 256 * r, NW - 1));
+    for (int r = 0; r < RW; ++r) {
+      // LDS row (tap, n of BN) <- n-tile nt + n / 32's slab [tap][n % 32][c]
+      // (past the last tile of an odd count: the last tile again, its
+      // outputs are not stored)
+      const int q = min(tid + 256 * r, NW - 1);
+      const int row = q >> 2, tap = row / BN, n = row - tap * BN;
+      const int tsel = min(nt + n / kBN, a.n_tiles - 1) - nt;
+      rw[r] = *reinterpret_cast<const u32x4*>(wsrc + (size_t)tsel * tile_elems +
+                                              ((tap * kBN + n % kBN) * kCK + 8 * (q & 3)));
+    }
   };
   auto commit = [&](int buf) {
 #pragma unroll
     for (int r = 0; r < RQ; ++r) {
       const int q = tid + 256 * r;
       if (q < NQ)
-        *reinterpret_cast<uint4*>(&s_in[buf][(q >> 2) * kPad + 8 * (q & 3)]) = halo_value<MODE>(rq[r], (ok >> r) & 1u);
+        *reinterpret_cast<u32x4*>(&s_in[buf][(q >> 2) * kPad + 8 * (q & 3)]) = halo_value<MODE>(rq[r], (ok >> r) & 1u);
     }
 #pragma unroll
     for (int r = 0; r < RW; ++r) {
       const int q = tid + 256 * r;
-      if (q < NW) *reinterpret_cast<uint4*>(&s_w[buf][(q >> 2) * kPad + 8 * (q & 3)]) = rw[r];
+      if (q < NW) *reinterpret_cast<u32x4*>(&s_w[buf][(q >> 2) * kPad + 8 * (q & 3)]) = rw[r];
     }
   };
 
@@ -181,7 +203,7 @@ __global__ __launch_bounds__(256) void conv3x3_bf16(ConvArgs a, HeadFuse hf) {
   }
   __syncthreads();
   for (int ch = ch_lo; ch < ch_hi; ++ch) {
-    const int cur = (ch - ch_lo) & 1;
+    const int cur = NBUF == 2 ? (ch - ch_lo) & 1 : 0;
     const bool more = ch + 1 < ch_hi;
     if (more) fetch(ch + 1);
     const uint16_t* si = s_in[cur];
@@ -189,21 +211,29 @@ __global__ __launch_bounds__(256) void conv3x3_bf16(ConvArgs a, HeadFuse hf) {
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3, dx = tap - 3 * (tap / 3);
-      bf16x8 av[MF], bv[2];
+      bf16x8 av[MF], bv[NF];
 #pragma unroll
       for (int mf = 0; mf < MF; ++mf)
         av[mf] = *reinterpret_cast<const bf16x8*>(&si[((wrow + mf + dy) * kHW + li + dx) * kPad + 8 * g]);
 #pragma unroll
-      for (int nf = 0; nf < 2; ++nf)
-        bv[nf] = *reinterpret_cast<const bf16x8*>(&sw[(tap * kBN + nf * 16 + li) * kPad + 8 * g]);
+      for (int nf = 0; nf < NF; ++nf)
+        bv[nf] = *reinterpret_cast<const bf16x8*>(&sw[(tap * BN + nf * 16 + li) * kPad + 8 * g]);
 #pragma unroll
       for (int mf = 0; mf < MF; ++mf)
 #pragma unroll
-        for (int nf = 0; nf < 2; ++nf)
+        for (int nf = 0; nf < NF; ++nf)
           acc[mf][nf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mf], bv[nf], acc[mf][nf], 0, 0, 0);
     }
-    if (more) commit(cur ^ 1);
-    __syncthreads();
+    if constexpr (NBUF == 2) {
+      if (more) commit(cur ^ 1);
+      __syncthreads();
+    } else {  // one buffer: every wave is done reading it before it is refilled
+      __syncthreads();
+      if (more) {
+        commit(0);
+        __syncthreads();
+      }
+    }
   }
   if constexpr (HEAD) {
     // head epilogue: the activations as they would be stored (bf16 of
@@ -227,7 +257,7 @@ __global__ __launch_bounds__(256) void conv3x3_bf16(ConvArgs a, HeadFuse hf) {
     head_finish<TH>(hf, sh, shw, b, a.H, a.W, y0, x0);
     return;
   }
-  store_tile<TH>(a, acc, b, y0, x0, wrow, g, li, nt, ks);
+  store_tile<TH, NF>(a, acc, b, y0, x0, wrow, g, li, nt, ks);
 }
 
 // First layer: 3 fp32 input channels; K slot k = 3 tap + c for k < 27.
@@ -255,7 +285,7 @@ __global__ __launch_bounds__(256) void conv3x3_bf16_guide(ConvArgs a) {
   const uint16_t* wsrc = static_cast<const uint16_t*>(a.w) + (size_t)blockIdx.z * kBN * kCK;
   for (int q = tid; q < kBN * kCK / 8; q += 256) {
     const int c8 = q & 3, row = q >> 2;
-    *reinterpret_cast<uint4*>(&s_w[row * kPad + 8 * c8]) = *reinterpret_cast<const uint4*>(wsrc + 8 * q);
+    *reinterpret_cast<u32x4*>(&s_w[row * kPad + 8 * c8]) = *reinterpret_cast<const u32x4*>(wsrc + 8 * q);
   }
   __syncthreads();
   f4 acc[MF][2];
@@ -299,10 +329,24 @@ hipError_t launch_th(const ConvArgs& a, hipStream_t s, const HeadFuse* head) {
   }
   return hipGetLastError();
 }
-// 8-row tiles, or 4-row tiles when the layer asks for them (not the input layer)
+// Large-layer form: kBf16LargeRows x 16 pixels x 64 channels per workgroup,
+// one LDS buffer.
+template <int MODE>
+hipError_t launch_large(const ConvArgs& a, hipStream_t s, const HeadFuse* head) {
+  if (head || a.n_tiles < 2) return hipErrorInvalidValue;
+  constexpr int R = kBf16LargeRows;
+  dim3 grid((a.W + kTW - 1) / kTW, ((a.H + R - 1) / R) * a.B, ((a.n_tiles + 1) / 2) * a.splits);
+  hipLaunchKernelGGL((conv3x3_bf16<MODE, R, false, 2, 1>), grid, dim3(256), 0, s, a, HeadFuse{});
+  return hipGetLastError();
+}
+// 8-row tiles, 4-row tiles or the large-layer form when the layer asks for
+// them (not the input layer)
 template <int MODE>
 hipError_t launch_tile(const ConvArgs& a, hipStream_t s, const HeadFuse* head) {
-  if (MODE != G_GUIDE && a.th == 4) return launch_th<MODE == G_GUIDE ? G_PLAIN : MODE, 4>(a, s, head);
+  if constexpr (MODE != G_GUIDE) {
+    if (a.th == 4) return launch_th<MODE, 4>(a, s, head);
+    if (a.th == kBf16Large) return launch_large<MODE>(a, s, head);
+  }
   return launch_th<MODE, 8>(a, s, head);
 }
 

@@ -119,7 +119,9 @@ struct ConvArgs {
   // launch_splitk_reduce finishes the layer
   int n_tiles, splits;
   float* partial;
-  int th;  // tile height in rows: 4 or 8 (0 means 8; the input layer always 8)
+  int th;  // tile height in rows: 4 or 8 (0 means 8; the input layer always 8); kBf16Large: the
+           // bf16 large-layer form (kBf16LargeRows rows x 64 channels per workgroup; n_tiles >= 2,
+           // no head)
 };
 // Sum the split partials in split order, then bias, (scale,) ReLU and the
 // output conversion of out_type (0 fp32, 1 bf16, 2 fp8).
@@ -131,6 +133,8 @@ int conv_splits(long wgs, int nchunks, int target);
 struct LayerTiling {
   int th, splits;
 };
+// The bf16 large-layer tile (ConvArgs::th code and its height in rows).
+constexpr int kBf16Large = 16, kBf16LargeRows = 8;
 LayerTiling conv_layer_tiling(const lnm_net_s* net, int i, int B, int h, int w);
 struct HeadFuse;
 // head: the layer's epilogue also applies the 1x1 head (plain-input layers
