@@ -496,15 +496,15 @@ int conv_splits(long wgs, int nchunks, int target) {
 // of th x 16 pixels x 32 output channels); the 3-channel input layer is
 // never split.  The split grows until the layer has 256 workgroups (fp32) or
 // 512 (bf16, fp8), the targets measured fastest per precision with the
-// split-K reductions counted.  fp32 layers take 4-row tiles where that
-// needs a smaller split than 8-row tiles (the deep levels: twice the
+// split-K reductions counted.  fp32 and bf16 layers take 4-row tiles where
+// that needs a smaller split than 8-row tiles (the deep levels: twice the
 // workgroups without partial sums to write, read and reduce) or where 8-row
 // tiles leave one workgroup per CU (nothing else on the CU hides a
-// workgroup's chunk-boundary stalls): 5 us per frame.  fp8 layers, whose
-// LDS footprint lets five 4-row workgroups share a CU, take 4-row tiles
-// throughout: 19 us per frame.  bf16 keeps 8-row tiles: its footprint
-// allows two workgroups per CU either way, and 4-row tiles measured 11 us
-// slower.
+// workgroup's chunk-boundary stalls): 5 us per fp32 frame, 9 us per bf16
+// frame.  fp8 layers, whose LDS footprint lets five 4-row workgroups share
+// a CU, take 4-row tiles throughout: 19 us per frame.  Large bf16 layers
+// take the 8-row x 64-channel form when it still gives two workgroups per
+// CU.
 LayerTiling conv_layer_tiling(const lnm_net_s* net, int i, int B, int h, int w) {
   const LayerDesc& d = net->layers[i];
   if (d.ci == 3) return {8, 1};
@@ -520,7 +520,7 @@ LayerTiling conv_layer_tiling(const lnm_net_s* net, int i, int B, int h, int w) 
     if (nt >= 2 && large >= 512) return {kBf16Large, 1};
   }
   const bool fp8 = net->precision == LNM_FP8_E4M3;
-  if (net->precision != LNM_BF16 && (s8 > 1 || wgs(8) <= 256 || fp8)) {
+  if (s8 > 1 || wgs(8) <= 256 || fp8) {
     // the longest fp32 layers (16+ chunks) split on to two workgroups per CU
     const int s4 = conv_splits(wgs(4), nch, net->precision == LNM_FP32 && nch >= 16 ? 512 : target);
     if (s4 < s8 || wgs(8) <= 256 || fp8) return {4, s4};
