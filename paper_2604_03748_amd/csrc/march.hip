@@ -669,19 +669,21 @@ __global__ __launch_bounds__(256) void march_balance(MarchDev m, CamDev c, TileM
   balance_tiles(m, c, tm, ctr, sh);
 }
 
-// The march's relayout: the same blocks plus one z slice whose first block
-// cuts the screen tiles into the balanced band ranges (the others exit).
+// The march's relayout: the same blocks behind one z slice whose first
+// block cuts the screen tiles into the balanced band ranges (the others
+// exit); that slice is dispatched first, so the balance runs beside the
+// copy instead of after it.
 __global__ __launch_bounds__(256) void relayout_balance(MarchDev m, CamDev c, TileMap tm, int* __restrict__ ctr,
-                                                        float* __restrict__ brick, int nbz) {
+                                                        float* __restrict__ brick) {
   __shared__ union {
     float rows[25][kRelayRow];
     BalanceLds bal;
   } sh;
-  if ((int)blockIdx.z == nbz) {
+  if (blockIdx.z == 0) {
     if (blockIdx.x == 0 && blockIdx.y == 0) balance_tiles(m, c, tm, ctr, sh.bal);
     return;
   }
-  relayout_block(m.rho, m.nx, m.ny, m.nz, m.nbx, m.nby, brick, sh.rows, blockIdx.x, blockIdx.y, blockIdx.z);
+  relayout_block(m.rho, m.nx, m.ny, m.nz, m.nbx, m.nby, brick, sh.rows, blockIdx.x, blockIdx.y, blockIdx.z - 1);
 }
 
 // Entry r of the band lists concatenated in band order.
@@ -1004,7 +1006,7 @@ hipError_t launch_march(const MarchDev& m0, const CamDev& cam, const MarchBuf& b
   if (!m.brick) {  // build the bricks in the scratch; one extra block balances the bands
     m.brick = buf.brick;
     hipLaunchKernelGGL(relayout_balance, dim3((m.nbx + kRelayBricks - 1) / kRelayBricks, m.nby, m.nbz + 1), dim3(256),
-                       0, s, m, cam, tm, buf.ctr, buf.brick, m.nbz);
+                       0, s, m, cam, tm, buf.ctr, buf.brick);
   } else {
     hipLaunchKernelGGL(march_balance, dim3(1), dim3(kBalanceThreads), 0, s, m, cam, tm, buf.ctr);
   }
