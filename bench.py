@@ -329,12 +329,19 @@ MARCH_SOURCES = ("paper_2604_03748_amd/csrc/march.hip", "paper_2604_03748_amd/cs
 
 
 def source_hash(sources=CONV_SOURCES) -> str:
+    """sha256[:16] of the sources' code: comments and blank space removed, so
+    that an edit of the documentation alone keeps a profile of the same
+    kernels valid."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for rel in sources:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

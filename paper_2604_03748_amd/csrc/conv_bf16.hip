@@ -7,7 +7,9 @@
 // TH x 16 pixel tile x 32 output channels; per 32-channel input chunk the
 // (TH+2) x 18 halo and the 9 x 32 x 32 weight slab are staged in LDS and read
 // by all nine taps; the halo gather fuses zero padding, 2x2 max-pooling and the
-// decoder's upsample + skip concatenation.
+// decoder's upsample + skip concatenation.  Large layers take an 8-row x
+// 64-channel form (two n-tiles per workgroup, one LDS buffer), which sums
+// every output in the same order and so gives the same values.
 //
 // K-slot permutation: lane group g (= lane / 16) supplies input channels
 // 8g .. 8g+7 of the chunk to both MFMA operands, one 16-byte LDS read each.
