@@ -169,8 +169,9 @@ LNM_API lnm_status lnm_make_bricks(lnm_ctx ctx, const lnm_volume* vol, float* br
 
 /* Device workspace (bytes) the march needs for this volume, camera and step:
  * per pixel, records of up to K primary samples (K bounded by the support
- * box diagonal over h) and their light terms, plus the bricked grid unless
- * vol->bricks is given; 0 on invalid arguments. */
+ * box diagonal over h) and their light terms, in z order (prm->work_order)
+ * also a z-bucket byte and a sorted-list entry per record, plus the bricked
+ * grid unless vol->bricks is given; 0 on invalid arguments. */
 LNM_API size_t lnm_march_workspace_bytes(const lnm_volume* vol, const lnm_camera* cam,
                                          const lnm_march_params* prm);
 
