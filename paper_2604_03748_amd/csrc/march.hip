@@ -445,10 +445,12 @@ __device__ __forceinline__ int wave_max(int v) {
 __device__ __forceinline__ float depth_step(float L, float sig, float h) { return L + sig * h; }
 
 // Primary march of tile `tile` (band order) of band `band`, whose work list
-// starts at `list`, with four lanes per pixel (see below).
+// starts at `list`, with four lanes per pixel (see below); zh: the block's
+// z-bucket counts, agg: 5 ints of LDS for the block's append.  Every thread
+// of the block calls it (it has block barriers).
 __device__ __forceinline__ void primary_tile(const MarchDev& m, const CamDev& c, const TileMap& tm,
                                              const MarchBuf& buf, float* __restrict__ guide, int tile, int band,
-                                             int2* __restrict__ list, int* zh) {
+                                             int2* __restrict__ list, int* zh, int* agg) {
   int i, j;
   quad_pixel(tm, tile, &i, &j);
   const int s = threadIdx.x & 3;
@@ -546,14 +548,23 @@ __device__ __forceinline__ void primary_tile(const MarchDev& m, const CamDev& c,
     g[1] = term ? 0.0f : expf(-tau);
     g[2] = dmin == big ? 0.0f : (float)dmin * h;
   }
-  // append this wave's records to the band's list: one atomic per wave, then
-  // k-major order (pixels in lane order within each k); lane s of a quad
-  // writes the pixel's records k = s (mod 4)
+  // append the tile's records to the band's list: one atomic per block (the
+  // four waves' totals summed in LDS; a wave's share follows the lower
+  // waves'), then k-major order within each wave (pixels in lane order within
+  // each k); lane s of a quad writes the pixel's records k = s (mod 4)
   const int total = wave_sum(s == 0 ? cnt : 0);
+  const int wave = threadIdx.x >> 6;
+  if (lane == 0) agg[wave] = total;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int all = agg[0] + agg[1] + agg[2] + agg[3];
+    agg[4] = all ? atomicAdd(buf.ctr + band, all) : 0;
+  }
+  __syncthreads();
+  int base = agg[4];
+  for (int w = 0; w < wave; ++w) base += agg[w];
+  __syncthreads();
   if (total == 0) return;
-  int base = 0;
-  if (lane == 0) base = atomicAdd(buf.ctr + band, total);
-  base = __shfl(base, 0);
   const unsigned long long below = (1ull << lane) - 1ull;
   const int kmax = wave_max(k);
   int off = base;
@@ -575,6 +586,7 @@ __device__ __forceinline__ void primary_tile(const MarchDev& m, const CamDev& c,
 __global__ __launch_bounds__(256) void march_primary(MarchDev m, CamDev c, TileMap tm, MarchBuf buf,
                                                      float* __restrict__ guide) {
   __shared__ int zh[kZBuckets];
+  __shared__ int agg[5];
   if (m.zorder) {
     for (int q = threadIdx.x; q < kZBuckets; q += 256) zh[q] = 0;
     __syncthreads();
@@ -584,7 +596,7 @@ __global__ __launch_bounds__(256) void march_primary(MarchDev m, CamDev c, TileM
   const int lo = start[band], hi = start[band + 1];
   int2* list = buf.rec + (size_t)lo * (kTile * kTile) * (size_t)buf.K;
   for (int L = lo + (int)(blockIdx.x >> 3); L < hi; L += slots)
-    primary_tile(m, c, tm, buf, guide, L, band, list, zh);
+    primary_tile(m, c, tm, buf, guide, L, band, list, zh, agg);
   if (m.zorder) {
     __syncthreads();
     for (int q = threadIdx.x; q < kZBuckets; q += 256)
