@@ -55,3 +55,24 @@ def test_param_count_and_device_bytes(L):
     assert L.param_count(1, 16) == 0  # unsupported depth
     assert L.param_count(3, 8) == 0  # width not a multiple of 16
     assert lib.lnm_version().startswith(b"liblnm")
+
+
+def test_work_order_choice_by_grid_size(L):
+    """lnm_march_workspace_bytes is host arithmetic, and the z order adds a
+    bucket byte and a list entry per record: the automatic order is the band
+    order for a 128^3 grid (18 MB of bricks) and the z order for a 256^3 grid
+    (141 MB, above the 32 MiB of the eight L2 caches)."""
+    from synth.scene import headline
+
+    cam = L.make_camera(headline().camera)
+    lib = L.lib()
+    for n, z_expected in ((128, False), (256, True)):
+        vol = L.Volume()
+        vol.density, vol.nx, vol.ny, vol.nz, vol.sigma_scale, vol.bricks = 0x1000, n, n, n, 8.0, None
+        ws = {o: lib.lnm_march_workspace_bytes(C.byref(vol), C.byref(cam),
+                                               C.byref(L.make_params(4.0, work_order=o)))
+              for o in (L.ORDER_AUTO, L.ORDER_BANDS, L.ORDER_Z)}
+        assert ws[L.ORDER_Z] > ws[L.ORDER_BANDS] > 0, n
+        assert ws[L.ORDER_AUTO] == (ws[L.ORDER_Z] if z_expected else ws[L.ORDER_BANDS]), n
+    bad = L.make_params(4.0, work_order=3)
+    assert lib.lnm_march_workspace_bytes(C.byref(vol), C.byref(cam), C.byref(bad)) == 0
