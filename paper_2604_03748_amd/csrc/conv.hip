@@ -505,11 +505,16 @@ int conv_splits(long wgs, int nchunks, int target) {
 // a CU, take 4-row tiles throughout: 19 us per frame.  Large bf16 layers
 // take the 8-row x 64-channel form when it still gives two workgroups per
 // CU.
+//
+// The split and the tile height follow the workgroup count of one image, so
+// an image's sums (whose order the split sets) are the same alone and in any
+// batch; only the bf16 large form, which sums in the same order as the
+// default form, looks at the batch.
 LayerTiling conv_layer_tiling(const lnm_net_s* net, int i, int B, int h, int w) {
   const LayerDesc& d = net->layers[i];
   if (d.ci == 3) return {8, 1};
   const int target = net->precision == LNM_FP32 ? 256 : 512, nch = d.ci_pad / d.ck;
-  auto wgs = [&](int th) { return (long)((w + 15) / 16) * ((h + th - 1) / th) * B * (d.co_pad / kBN); };
+  auto wgs = [&](int th) { return (long)((w + 15) / 16) * ((h + th - 1) / th) * (d.co_pad / kBN); };
   const int s8 = conv_splits(wgs(8), nch, target);
   if (net->precision == LNM_BF16 && s8 == 1) {
     // large bf16 layers: the 64-channel tile, when it still gives two
