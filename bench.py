@@ -529,13 +529,16 @@ def main():
             return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
 
         # the configured load (2000 frames/s offered, 64 GB), then half that
-        # load, and the configured load under a 2 GB budget so admission binds
+        # load, the configured load under a 2 GB budget so admission binds,
+        # and 8000 frames/s offered for 3 s, beyond what the server keeps up
+        # with: its throughput there is the server's capacity
         out["served"] = rounded(served(lnm, ctx, params, args.serve_seconds, warmup_s=1.0))
         log(f"served: {out['served']}")
         other_s = min(args.serve_seconds, 5.0)
         out["served_other_loads"] = [
             rounded(served(lnm, ctx, params, other_s, warmup_s=1.0, rate_hz=1000.0)),
             rounded(served(lnm, ctx, params, other_s, warmup_s=1.0, budget_gb=2.0)),
+            rounded(served(lnm, ctx, params, min(other_s, 3.0), warmup_s=1.0, rate_hz=8000.0)),
         ]
         log(f"served at other loads: {out['served_other_loads']}")
     if not args.no_cpu_baseline:
