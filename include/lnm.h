@@ -224,7 +224,9 @@ LNM_API size_t lnm_net_device_bytes(int32_t levels, int32_t base, int32_t precis
  * one scale per output channel, max|W[o]|/448; activations stored as e4m3
  * with one scale per tensor, amax/448, the two inputs of each decoder
  * concatenation sharing the larger; fp32 accumulation; the 3-channel input
- * layer in bf16).  Other values: LNM_ERR_UNSUPPORTED.
+ * layer and the last 3x3 layer, whose features the head reads, in bf16, the
+ * layer before that storing bf16 for it).  Other values:
+ * LNM_ERR_UNSUPPORTED.
  * act_scales: LNM_FP8_E4M3 only (else NULL): the calibrated maximum |output|
  * of each convolution layer (4 levels - 2 floats, see lnm_calibrate_amax).
  * levels in [2, 6]; base in [1, 256] with base multiple of 16 for levels

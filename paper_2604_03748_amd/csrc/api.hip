@@ -135,7 +135,11 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // Layer table and packed-weight layout of a network at one precision.
 // fp32: chunks of 16 input channels (4 for the 3-channel input);
 // bf16: chunks of 32 (the 3-channel input packs its 27 taps x channels into
-// one 32-wide K step).
+// one 32-wide K step).  The fp8 network keeps its last 3x3 layer, the one
+// the head reads, in bf16: the layer before it stores bf16 activations for
+// it, and the head reads bf16 instead of e4m3 features (e4m3's 3-bit
+// mantissa on the features the head sums is the largest single term of the
+// fp8 form's error).
 bool net_shape(int levels, int base, int precision, std::vector<LayerDesc>* out, size_t* dev_bytes,
                       std::string* why) {
   if (levels < 2 || levels > 6) return *why = "levels must be in [2, 6]", false;
@@ -149,6 +153,8 @@ bool net_shape(int levels, int base, int precision, std::vector<LayerDesc>* out,
     d.ci = ci;
     d.co = co;
     d.k = k;
+    d.prec = precision;
+    d.out_es = elem_bytes(precision);
     if (precision == LNM_FP32) {
       d.ck = ci == 3 ? 4 : 16;
       d.ci_pad = (ci + d.ck - 1) / d.ck * d.ck;
@@ -172,7 +178,13 @@ bool net_shape(int levels, int base, int precision, std::vector<LayerDesc>* out,
     add(base << l, base << l, 3);
   }
   add(base, 6, 1);
-  const size_t es = elem_bytes(precision);
+  if (precision == LNM_FP8_E4M3) {
+    const size_t last = L.size() - 2;  // the last 3x3 layer
+    L[last].prec = LNM_BF16;
+    L[last].out_es = 2;
+    L[last - 1].out_es = 2;
+  }
+  L.back().out_es = 4;
   size_t off = 0;
   for (auto& d : L) {
     off = align256(off);
@@ -182,11 +194,11 @@ bool net_shape(int levels, int base, int precision, std::vector<LayerDesc>* out,
     else if (precision != LNM_FP32 && d.ci == 3)
       off += sizeof(uint16_t) * d.co_pad * 32;  // the 3-channel input layer is bf16 in both reduced forms
     else
-      off += es * d.co_pad * d.ci_pad * 9;
+      off += (size_t)elem_bytes(d.prec) * d.co_pad * d.ci_pad * 9;
     off = align256(off);
     d.b_off = off;
     off += sizeof(float) * (d.k == 3 ? d.co_pad : 6);
-    if (precision == LNM_FP8_E4M3 && d.k == 3 && d.ci != 3) {
+    if (d.prec == LNM_FP8_E4M3 && d.k == 3 && d.ci != 3) {
       off = align256(off);
       d.s_off = off;
       off += sizeof(float) * d.co_pad;
@@ -308,12 +320,11 @@ Plan plan_workspace(const lnm_net_s* net, int B, int H, int W) {
   size_t off = 0;
   const int L = net->levels;
   int li = 0;
-  const size_t es = elem_bytes(net->precision);
   auto add = [&](int lvl) {
     const LayerDesc& d = net->layers[li++];
     off = align256(off);
     p.out_off.push_back(off);
-    off += es * (size_t)B * (H >> lvl) * (W >> lvl) * d.co;
+    off += (size_t)d.out_es * B * (H >> lvl) * (W >> lvl) * d.co;
   };
   for (int l = 0; l < L; ++l) {
     add(l);
@@ -343,7 +354,6 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
   auto buf = [&](int i) { return static_cast<void*>(ws + p.out_off[i]); };
   std::vector<int> skip(L);
   int li = 0;
-  const bool fp8 = net->precision == LNM_FP8_E4M3;
   // src: conv layer that produced the input (-1: the guide), for fp8 scales
   auto conv = [&](int lvl, int mode, int src, const void* s0, int c0, const void* s1, int c1,
                   const HeadFuse* head = nullptr) -> hipError_t {
@@ -362,10 +372,11 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
     a.bias = reinterpret_cast<const float*>(net->dev + d.b_off);
     a.out = buf(li);
     a.relu = 1;
-    if (fp8) {
+    if (d.prec == LNM_FP8_E4M3) {
       a.in_scale = src >= 0 ? net->act_scale[src] : 1.0f;
       a.w_scale = d.s_off ? reinterpret_cast<const float*>(net->dev + d.s_off) : nullptr;
       a.out_inv_scale = 1.0f / net->act_scale[li];
+      a.out_bf16 = d.out_es == 2;
     }
     a.n_tiles = d.co_pad / kBN;
     const LayerTiling tl = conv_layer_tiling(net, li, B, a.H, a.W);
@@ -375,13 +386,17 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
     ++li;
     ProfScope ps(ctx, LNM_K_CONV, s);
     hipError_t err;
-    if (fp8)
+    int out_type = 0;
+    if (d.prec == LNM_FP8_E4M3) {
       err = launch_conv3x3_fp8(mode, a, s, head);
-    else if (net->precision == LNM_BF16)
+      out_type = a.out_bf16 ? 3 : 2;
+    } else if (d.prec == LNM_BF16) {
       err = launch_conv3x3_bf16(mode, a, s, head);
-    else
+      out_type = 1;
+    } else {
       err = launch_conv3x3_f32(mode, d.ck, a, s, head);
-    if (err == hipSuccess && a.splits > 1) err = launch_splitk_reduce(a, fp8 ? 2 : net->precision == LNM_BF16 ? 1 : 0, s);
+    }
+    if (err == hipSuccess && a.splits > 1) err = launch_splitk_reduce(a, out_type, s);
     return err;
   };
   // inference: the last layer's epilogue applies the head (and the frame's
@@ -396,7 +411,8 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
   hf.b = reinterpret_cast<const float*>(net->dev + hd.b_off);
   hf.lm = lm;
   if (comp) hf.comp = *comp;
-  hf.in_scale = fp8 ? net->act_scale[n_conv - 1] : 1.0f;
+  const bool last_e4m3 = net->layers[n_conv - 1].out_es == 1;  // features the head reads
+  hf.in_scale = last_e4m3 ? net->act_scale[n_conv - 1] : 1.0f;
   const bool fused = fuse_head && lm && !logits && net->layers[n_conv - 1].co <= kBN &&
                      layer_splits(net, n_conv - 1, B, H, W) == 1;
   hipError_t e;
@@ -428,8 +444,8 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
   if (!lm || fused) return LNM_OK;  // convolutions only (calibration), or the head ran in the last layer
   HeadArgs h{};
   h.in = x;
-  h.in_type = fp8 ? 2 : net->precision == LNM_BF16 ? 1 : 0;
-  h.in_scale = fp8 ? net->act_scale[li - 1] : 1.0f;
+  h.in_type = net->layers[li - 1].out_es == 4 ? 0 : net->layers[li - 1].out_es == 2 ? 1 : 2;
+  h.in_scale = last_e4m3 ? net->act_scale[li - 1] : 1.0f;
   h.P = B * H * W;
   h.C = cx;
   h.w = reinterpret_cast<const float*>(net->dev + hd.w_off);
@@ -469,6 +485,51 @@ static lnm_status light_setup(const CamDev& c, const lnm_light* lights, int n, C
     for (int q = 0; q < 3; ++q) a->rgb[k][q] = lights[k].rgb[q];
   }
   return LNM_OK;
+}
+
+lnm_status frame_impl(lnm_ctx_s* ctx, const lnm_net_s* net, const lnm_volume* vol, const lnm_camera* cam,
+                      const lnm_march_params* prm, const lnm_light* lights, int n_lights, float* guide,
+                      float* lightmaps, float* rgba, void* workspace, size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(LNM_ERR_ARG, "ctx is NULL");
+  if (!guide || !lightmaps) return fail(LNM_ERR_ARG, "guide or lightmaps is NULL");
+  MarchDev m;
+  CamDev c;
+  lnm_status st = march_setup(vol, cam, prm, &m, &c);
+  if (st) return st;
+  st = check_infer(net, 1, c.H, c.W, ws_bytes, workspace);
+  if (st) return st;
+  const int K = march_capacity(m);
+  const size_t need = march_scratch_bytes(m, K, c.W, c.H);
+  if (ws_bytes < need) return fail(LNM_ERR_SHAPE, "workspace too small for the march: need " + std::to_string(need));
+  CompositeArgs a{};
+  if (rgba) {
+    st = light_setup(c, lights, n_lights, &a);
+    if (st) return st;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  {
+    ProfScope ps(ctx, LNM_K_MARCH, s);
+    LNM_HIP_CHECK(launch_march(m, c, march_buffers(workspace, m, K, c.W, c.H), guide, s));
+  }
+  // the head launch also shades the frame when rgba is requested
+  a.lm = lightmaps;
+  a.guide = guide;
+  a.rgba = rgba;
+  a.P = c.H * c.W;
+  return run_unet(ctx, net, 1, c.H, c.W, guide, lightmaps, nullptr, static_cast<char*>(workspace), s,
+                  rgba ? &a : nullptr, true);
+}
+
+size_t frame_workspace_bytes(const lnm_net_s* net, const lnm_volume* vol, const lnm_camera* cam,
+                             const lnm_march_params* prm) {
+  MarchDev m;
+  CamDev c;
+  if (!net || march_setup(vol, cam, prm, &m, &c)) return 0;
+  const int div = 1 << (net->levels - 1);
+  if (c.H % div || c.W % div) return 0;
+  // the march's records are dead once the guide is written, so the U-Net
+  // activations reuse the same bytes
+  return std::max(march_scratch_bytes(m, march_capacity(m), c.W, c.H), plan_workspace(net, 1, c.H, c.W).bytes);
 }
 
 }  // namespace lnm
@@ -608,14 +669,7 @@ lnm_status lnm_march_batch(lnm_ctx ctx, int32_t n, const lnm_volume* vols, const
 
 size_t lnm_frame_workspace_bytes(lnm_net net, const lnm_volume* vol, const lnm_camera* cam,
                                  const lnm_march_params* prm) {
-  MarchDev m;
-  CamDev c;
-  if (!net || march_setup(vol, cam, prm, &m, &c)) return 0;
-  const int div = 1 << (net->levels - 1);
-  if (c.H % div || c.W % div) return 0;
-  // the march's records are dead once the guide is written, so the U-Net
-  // activations reuse the same bytes
-  return std::max(march_scratch_bytes(m, march_capacity(m), c.W, c.H), plan_workspace(net, 1, c.H, c.W).bytes);
+  return frame_workspace_bytes(net, vol, cam, prm);
 }
 
 lnm_status lnm_reference_lightmaps(lnm_ctx ctx, const lnm_volume* vol, const lnm_camera* cam, float step_voxels,
@@ -694,7 +748,7 @@ lnm_status lnm_net_create(lnm_ctx ctx, int32_t levels, int32_t base, int32_t pre
   size_t off = 0;
   for (auto& d : L) {
     const size_t nw = (size_t)d.co * d.ci * d.k * d.k;
-    pack_layer(d, precision, host_params + off, host_params + off + nw, packed.data());
+    pack_layer(d, d.prec, host_params + off, host_params + off + nw, packed.data());
     off += nw + d.co;
   }
   auto* net = new (std::nothrow) lnm_net_s;
@@ -851,7 +905,8 @@ lnm_status lnm_infer_adapters(lnm_ctx ctx, lnm_adapters ad, int32_t batch, int32
   const int n_conv = (int)net->layers.size() - 1;
   AdapterArgs a{};
   a.feat = ws + plan_workspace(net, batch, H, W).out_off[n_conv - 1];
-  a.feat_scale = net->precision == LNM_FP8_E4M3 ? net->act_scale[n_conv - 1] : 1.0f;
+  const int feat_es = net->layers[n_conv - 1].out_es;  // the decoder features as stored
+  a.feat_scale = feat_es == 1 ? net->act_scale[n_conv - 1] : 1.0f;
   a.prm = ad->dev;
   a.B = batch;
   a.H = H;
@@ -864,7 +919,7 @@ lnm_status lnm_infer_adapters(lnm_ctx ctx, lnm_adapters ad, int32_t batch, int32
   a.sca = reinterpret_cast<float*>(ws + ap.sca_off);
   a.lm = lightmaps;
   a.extra = extra;
-  const int in_type = net->precision == LNM_FP8_E4M3 ? 2 : net->precision == LNM_BF16 ? 1 : 0;
+  const int in_type = feat_es == 4 ? 0 : feat_es == 2 ? 1 : 2;
   ProfScope ps(ctx, LNM_K_ADAPTERS, s);
   LNM_HIP_CHECK(launch_adapters(ad->c, a, in_type, s));
   return LNM_OK;
@@ -976,34 +1031,7 @@ lnm_status lnm_composite_shadowed(lnm_ctx ctx, const lnm_camera* cam, const lnm_
 lnm_status lnm_frame(lnm_ctx ctx, lnm_net net, const lnm_volume* vol, const lnm_camera* cam,
                      const lnm_march_params* prm, const lnm_light* lights, int32_t n_lights, float* guide,
                      float* lightmaps, float* rgba, void* workspace, size_t ws_bytes, void* stream) {
-  if (!ctx) return fail(LNM_ERR_ARG, "ctx is NULL");
-  if (!guide || !lightmaps) return fail(LNM_ERR_ARG, "guide or lightmaps is NULL");
-  MarchDev m;
-  CamDev c;
-  lnm_status st = march_setup(vol, cam, prm, &m, &c);
-  if (st) return st;
-  st = check_infer(net, 1, c.H, c.W, ws_bytes, workspace);
-  if (st) return st;
-  const int K = march_capacity(m);
-  const size_t need = march_scratch_bytes(m, K, c.W, c.H);
-  if (ws_bytes < need) return fail(LNM_ERR_SHAPE, "workspace too small for the march: need " + std::to_string(need));
-  CompositeArgs a{};
-  if (rgba) {
-    st = light_setup(c, lights, n_lights, &a);
-    if (st) return st;
-  }
-  hipStream_t s = (hipStream_t)stream;
-  {
-    ProfScope ps(ctx, LNM_K_MARCH, s);
-    LNM_HIP_CHECK(launch_march(m, c, march_buffers(workspace, m, K, c.W, c.H), guide, s));
-  }
-  // the head launch also shades the frame when rgba is requested
-  a.lm = lightmaps;
-  a.guide = guide;
-  a.rgba = rgba;
-  a.P = c.H * c.W;
-  return run_unet(ctx, net, 1, c.H, c.W, guide, lightmaps, nullptr, static_cast<char*>(workspace), s,
-                  rgba ? &a : nullptr, true);
+  return frame_impl(ctx, net, vol, cam, prm, lights, n_lights, guide, lightmaps, rgba, workspace, ws_bytes, stream);
 }
 
 }  // extern "C"

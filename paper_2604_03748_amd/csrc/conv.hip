@@ -276,6 +276,8 @@ __global__ __launch_bounds__(256) void splitk_reduce(ConvArgs a, int out_type, l
       float t = a.in_scale * a.w_scale[n] * acc + a.bias[n];
       t = t > 0.0f ? t * a.out_inv_scale : 0.0f;
       y[e] = fminf(t, 448.0f);
+    } else if (out_type == 3) {
+      y[e] = fmaxf(a.in_scale * a.w_scale[n] * acc + a.bias[n], 0.0f);
     } else {
       float t = acc + a.bias[n];
       if (a.relu) t = fmaxf(t, 0.0f);
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(256) void splitk_reduce(ConvArgs a, int out_type, l
     for (int e = 0; e < 4; ++e)
       packed |= ((uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y[e], 0.0f, 0, false) & 0xffu) << (8 * e);
     static_cast<uint32_t*>(a.out)[i4] = packed;
-  } else if (out_type == 1) {
+  } else if (out_type == 1 || out_type == 3) {
     static_cast<uint2*>(a.out)[i4] = make_uint2((uint32_t)f32_to_bf16(y[0]) | ((uint32_t)f32_to_bf16(y[1]) << 16),
                                                 (uint32_t)f32_to_bf16(y[2]) | ((uint32_t)f32_to_bf16(y[3]) << 16));
   } else {
@@ -513,10 +515,10 @@ int conv_splits(long wgs, int nchunks, int target) {
 LayerTiling conv_layer_tiling(const lnm_net_s* net, int i, int B, int h, int w) {
   const LayerDesc& d = net->layers[i];
   if (d.ci == 3) return {8, 1};
-  const int target = net->precision == LNM_FP32 ? 256 : 512, nch = d.ci_pad / d.ck;
+  const int target = d.prec == LNM_FP32 ? 256 : 512, nch = d.ci_pad / d.ck;
   auto wgs = [&](int th) { return (long)((w + 15) / 16) * ((h + th - 1) / th) * (d.co_pad / kBN); };
   const int s8 = conv_splits(wgs(8), nch, target);
-  if (net->precision == LNM_BF16 && s8 == 1) {
+  if (d.prec == LNM_BF16 && s8 == 1) {
     // large bf16 layers: the 64-channel tile, when it still gives two
     // workgroups per CU
     const int nt = d.co_pad / kBN;
@@ -524,10 +526,10 @@ LayerTiling conv_layer_tiling(const lnm_net_s* net, int i, int B, int h, int w) 
         (long)((w + 15) / 16) * ((h + kBf16LargeRows - 1) / kBf16LargeRows) * B * ((nt + 1) / 2);
     if (nt >= 2 && large >= 512) return {kBf16Large, 1};
   }
-  const bool fp8 = net->precision == LNM_FP8_E4M3;
+  const bool fp8 = d.prec == LNM_FP8_E4M3;
   if (s8 > 1 || wgs(8) <= 256 || fp8) {
     // the longest fp32 layers (16+ chunks) split on to two workgroups per CU
-    const int s4 = conv_splits(wgs(4), nch, net->precision == LNM_FP32 && nch >= 16 ? 512 : target);
+    const int s4 = conv_splits(wgs(4), nch, d.prec == LNM_FP32 && nch >= 16 ? 512 : target);
     if (s4 < s8 || wgs(8) <= 256 || fp8) return {4, s4};
   }
   return {8, s8};

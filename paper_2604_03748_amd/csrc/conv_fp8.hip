@@ -94,7 +94,8 @@ __device__ __forceinline__ uint2 halo_value(const Halo<MODE>& h, bool ok) {
 }
 
 // y = scale[o] * acc + bias (scale = s_in s_w[o], or 1 for the bf16 layer),
-// ReLU, stored as e4m3 of y * out_inv_scale.
+// ReLU, stored as e4m3 of y * out_inv_scale (bf16 of y when the consumer is
+// the network's bf16 last layer).
 template <int TH>
 __device__ __forceinline__ void store_fp8(const ConvArgs& a, const f4 (&acc)[TH / 4][2], int b, int y0, int x0,
                                           int wrow, int g, int li, bool scaled, int nt, int ks) {
@@ -119,6 +120,10 @@ __device__ __forceinline__ void store_fp8(const ConvArgs& a, const f4 (&acc)[TH 
           continue;
         }
         float v = sc * acc[mf][nf][r] + bias;
+        if (a.out_bf16) {  // for a bf16 consumer: unscaled
+          static_cast<uint16_t*>(a.out)[pix * a.co + n] = f2bf(fmaxf(v, 0.0f));
+          continue;
+        }
         v = v > 0.0f ? v * a.out_inv_scale : 0.0f;
         out[pix * a.co + n] = (uint8_t)f2fp8(v);
       }

@@ -98,6 +98,8 @@ struct LayerDesc {
   size_t w_off;  // byte offset of the packed weights in the device buffer
   size_t b_off;  // byte offset of the fp32 biases (co_pad of them)
   size_t s_off;  // byte offset of fp32 per-output-channel weight scales (fp8)
+  int prec;      // the layer's weights and matrix arithmetic (lnm_precision)
+  int out_es;    // bytes per stored output element: 4 fp32, 2 bf16, 1 e4m3
 };
 
 // Activation element types: fp32 (4 bytes), bf16 (2), fp8 e4m3 (1).
@@ -122,9 +124,11 @@ struct ConvArgs {
   int th;  // tile height in rows: 4 or 8 (0 means 8; the input layer always 8); kBf16Large: the
            // bf16 large-layer form (kBf16LargeRows rows x 64 channels per workgroup; n_tiles >= 2,
            // no head)
+  int out_bf16;  // fp8 layers: store max(y, 0) as bf16 (unscaled) instead of e4m3
 };
 // Sum the split partials in split order, then bias, (scale,) ReLU and the
-// output conversion of out_type (0 fp32, 1 bf16, 2 fp8).
+// output conversion of out_type (0 fp32, 1 bf16, 2 fp8; 3: fp8 partials,
+// scaled like 2, stored as bf16).
 hipError_t launch_splitk_reduce(const ConvArgs& a, int out_type, hipStream_t s);
 // Splits for a layer launched with `wgs` workgroups over `nchunks` input chunks.
 int conv_splits(long wgs, int nchunks, int target);
@@ -281,6 +285,12 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
                     float* logits, char* ws, hipStream_t s, const CompositeArgs* comp = nullptr,
                     bool fuse_head = false);
 lnm_status check_infer(const lnm_net_s* net, int B, int H, int W, size_t ws_bytes, const void* ws);
+// lnm_frame on a caller's (or the library's static) workspace, and its size
+lnm_status frame_impl(lnm_ctx_s* ctx, const lnm_net_s* net, const lnm_volume* vol, const lnm_camera* cam,
+                      const lnm_march_params* prm, const lnm_light* lights, int n_lights, float* guide,
+                      float* lightmaps, float* rgba, void* workspace, size_t ws_bytes, void* stream);
+size_t frame_workspace_bytes(const lnm_net_s* net, const lnm_volume* vol, const lnm_camera* cam,
+                             const lnm_march_params* prm);
 
 // ---------------------------------------------------------------- training kernels (train.hip)
 // Layer geometry shared by the backward kernels.

@@ -72,6 +72,8 @@ bool state_layout(int levels, int base, StateLayout* s, std::string* why) {
     d.ck = 16;
     d.ci_pad = (f.co + 15) / 16 * 16;
     d.co_pad = (f.ci + kBN - 1) / kBN * kBN;
+    d.prec = LNM_FP32;
+    d.out_es = 4;
     s->dg[i] = d;
     s->dgrad_w[i] = take(sizeof(float) * d.co_pad * d.ci_pad * 9);
     s->max_dg_co_pad = std::max(s->max_dg_co_pad, d.co_pad);
