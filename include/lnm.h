@@ -274,6 +274,25 @@ LNM_API lnm_status lnm_frame(lnm_ctx ctx, lnm_net net, const lnm_volume* vol, co
 LNM_API size_t lnm_frame_workspace_bytes(lnm_net net, const lnm_volume* vol, const lnm_camera* cam,
                                          const lnm_march_params* prm);
 
+/* Size of the library's static frame workspace: 128 MiB, held on every
+ * device the library runs on until the process ends. */
+#define LNM_STATIC_SCRATCH_BYTES 134217728u
+/* lnm_frame for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same frame, bit for bit, computed in the library's static workspace
+ * instead of a caller-provided one.  It allocates no device memory and
+ * calls no allocating routine.  The caller still provides guide, lightmaps
+ * and rgba (rgba may be NULL) as for lnm_frame.  A frame whose
+ * lnm_frame_workspace_bytes exceeds LNM_STATIC_SCRATCH_BYTES (the 128^3 grid
+ * at 256 x 256 takes about 120 MiB) returns LNM_ERR_SHAPE with nothing
+ * enqueued.  All calls on one device share its one workspace: calls that
+ * may overlap on a device (other streams, other threads, other contexts)
+ * race and must be serialised by the caller.  Nothing needs clearing between
+ * calls: every byte the frame reads is written earlier in the same call. */
+LNM_API lnm_status lnm_frame_static(lnm_ctx ctx, lnm_net net, const lnm_volume* vol, const lnm_camera* cam,
+                                    const lnm_march_params* prm, const lnm_light* lights, int32_t n_lights,
+                                    float* guide, float* lightmaps, float* rgba, void* stream);
+
 /* Six-way shading alone (the shading step of lnm_frame) for B images that share
  * one camera and light set. */
 LNM_API lnm_status lnm_composite(lnm_ctx ctx, const lnm_camera* cam, const lnm_light* lights, int32_t n_lights,

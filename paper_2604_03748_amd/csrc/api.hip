@@ -567,6 +567,13 @@ lnm_status lnm_ctx_create(int32_t hip_device, lnm_ctx* out) {
   c->device = hip_device;
   c->cu_count = prop.multiProcessorCount;
   c->arch = prop.gcnArchName;
+  // each device holds its own copy of the static workspace: look up this
+  // device's address now, with the device current
+  const hipError_t e = static_scratch_address(&c->static_scratch);
+  if (e != hipSuccess || !c->static_scratch) {
+    delete c;
+    return fail(LNM_ERR_DEVICE, std::string("static workspace address: ") + hipGetErrorString(e));
+  }
   *out = c;
   return LNM_OK;
 }

@@ -234,6 +234,9 @@ struct lnm_ctx_s {
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
+  // device address of the static frame workspace (LNM_STATIC_SCRATCH_BYTES)
+  // on this context's device, looked up once at creation
+  void* static_scratch = nullptr;
 };
 
 namespace lnm {
@@ -291,6 +294,9 @@ lnm_status frame_impl(lnm_ctx_s* ctx, const lnm_net_s* net, const lnm_volume* vo
                       float* lightmaps, float* rgba, void* workspace, size_t ws_bytes, void* stream);
 size_t frame_workspace_bytes(const lnm_net_s* net, const lnm_volume* vol, const lnm_camera* cam,
                              const lnm_march_params* prm);
+// Device address of the library's static frame workspace on the current
+// device (frame_static.hip); call with that device current.
+hipError_t static_scratch_address(void** out);
 
 // ---------------------------------------------------------------- training kernels (train.hip)
 // Layer geometry shared by the backward kernels.

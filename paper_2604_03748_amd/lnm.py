@@ -31,8 +31,9 @@ EXPORTS = [
     "lnm_trainer_read_params", "lnm_trainer_save", "lnm_trainer_load", "lnm_trainer_infer", "lnm_calibrate_amax",
     "lnm_shadow_map_sphere", "lnm_composite_shadowed", "lnm_bricks_bytes", "lnm_make_bricks",
     "lnm_adapters_param_count", "lnm_adapters_device_bytes", "lnm_adapters_create", "lnm_adapters_destroy",
-    "lnm_adapters_workspace_bytes", "lnm_infer_adapters",
+    "lnm_adapters_workspace_bytes", "lnm_infer_adapters", "lnm_frame_static",
 ]
+STATIC_SCRATCH_BYTES = 128 << 20  # LNM_STATIC_SCRATCH_BYTES
 K_MARCH, K_CONV, K_HEAD, K_COMPOSITE, K_REFERENCE, K_ADAPTERS = range(6)
 
 
@@ -127,6 +128,9 @@ def lib():
         L.lnm_frame.restype = i32
         L.lnm_frame.argtypes = [vp, vp, C.POINTER(Volume), C.POINTER(Camera), C.POINTER(MarchParams),
                                 C.POINTER(Light), i32, vp, vp, vp, vp, sz, vp]
+        L.lnm_frame_static.restype = i32
+        L.lnm_frame_static.argtypes = [vp, vp, C.POINTER(Volume), C.POINTER(Camera), C.POINTER(MarchParams),
+                                       C.POINTER(Light), i32, vp, vp, vp, vp]
         L.lnm_composite.restype = i32
         L.lnm_composite.argtypes = [vp, C.POINTER(Camera), C.POINTER(Light), i32, i32, i32, i32, vp, vp, vp, vp]
         L.lnm_shadow_map_sphere.restype = i32
@@ -484,6 +488,21 @@ class Net:
         check(lib().lnm_frame(self.ctx.handle, self.handle, C.byref(vol), C.byref(c), C.byref(params), arr, n,
                               _ptr(guide), _ptr(lightmaps), _ptr(rgba) if shade else None, _ptr(workspace),
                               workspace.numel(), _stream(stream)))
+        return guide, lightmaps, rgba
+
+    def frame_static(self, density, sigma_scale, cam, params: MarchParams, guide, lightmaps, lights=(), rgba=None,
+                     stream=None, bricks=None):
+        """lnm_frame_static: the frame in the library's static workspace.
+        The caller provides the output tensors (nothing is allocated here)."""
+        vol = make_volume(density, sigma_scale, bricks)
+        c = make_camera(cam)
+        _need(guide, (c.height, c.width, 3), "guide")
+        _need(lightmaps, (c.height, c.width, 6), "lightmaps")
+        if rgba is not None:
+            _need(rgba, (c.height, c.width, 4), "rgba")
+        arr, n = make_lights(lights)
+        check(lib().lnm_frame_static(self.ctx.handle, self.handle, C.byref(vol), C.byref(c), C.byref(params), arr, n,
+                                     _ptr(guide), _ptr(lightmaps), _ptr(rgba), _stream(stream)))
         return guide, lightmaps, rgba
 
 
