@@ -145,10 +145,12 @@ def measure_two_streams(lnm, net, dens, wl, light, steps, warmup):
     return {"fps": steps / elapsed, "ms_per_frame_amortised": 1e3 * elapsed / steps}
 
 
-def served(lnm, ctx, params, seconds, warmup_s, rate_hz=2000.0, budget_gb=64.0, n_instances=64, seed=7):
+def served(lnm, ctx, params, seconds, warmup_s, rate_hz=2000.0, budget_gb=64.0, n_instances=64, seed=7,
+           hold_ms=0.0):
     """Continuous-batching server: n_instances smoke instances (grids
     {64,96,128,192,256}^3, views {128,256,512}^2, own seeded blobs + noise and
-    light), Poisson arrivals at rate_hz, bf16 network, HBM budget."""
+    light), Poisson arrivals at rate_hz, bf16 network, HBM budget (resident
+    grids and brick copies included), batches held up to hold_ms."""
     import torch
 
     from paper_2604_03748_amd.serve import Backend, Instance, Scheduler, poisson_requests
@@ -171,10 +173,17 @@ def served(lnm, ctx, params, seconds, warmup_s, rate_hz=2000.0, budget_gb=64.0, 
     be = Backend(ctx, net, n_streams=4)
     budget = int(budget_gb * 2**30)
     if warmup_s > 0:
-        Scheduler(be, insts, budget, max_batch=16).run(poisson_requests(n_instances, rate_hz, warmup_s, seed + 1))
+        Scheduler(be, insts, budget, max_batch=16, hold_s=hold_ms * 1e-3).run(
+            poisson_requests(n_instances, rate_hz, warmup_s, seed + 1))
     reqs = poisson_requests(n_instances, rate_hz, seconds, seed)
-    sch = Scheduler(be, insts, budget, max_batch=16)
+    sch = Scheduler(be, insts, budget, max_batch=16, hold_s=hold_ms * 1e-3)
     st = sch.run(reqs)
+    # the completed frames' network work against the bf16 matrix peak
+    from synth.weights import unet_flops
+
+    fl = sum(unet_flops(4, 32, 1, insts[r.instance].res, insts[r.instance].res) for r in sch.done)
+    st["net_tflops"] = fl / st["wall_s"] / 1e12 if st["wall_s"] > 0 else 0.0
+    st["net_frac_of_bf16_peak"] = st["net_tflops"] / PEAK_TFLOPS["bf16"]
     st.update({"offered_rate_fps": rate_hz, "instances": n_instances, "duration_s": seconds,
                "grids": sorted({v.density.shape[0] for v in insts.values()}), "views": list(views),
                "dtype": "bf16", "budget_gb": budget_gb})
@@ -247,7 +256,16 @@ def dynamic_scene(lnm, ctx, frames, warmup=3):
         stages[name] = round(ctx.profile_read(k)[1] / nprof, 4)
     ctx.profile(False)
     fm = np.array(frame_ms)
+    from synth.weights import unet_flops
+
+    conv_fl = unet_flops(wl.levels, wl.base, 1, H, W) - 2.0 * H * W * 6 * wl.base  # 3x3 layers only
+    conv_tf = conv_fl / (stages["conv3x3"] * 1e-3) / 1e12
+    prim, sec = DYNAMIC_SAMPLES
     return {"workload": "dynamic256_1024px", "frames": frames, "dtype": "bf16", "stages_ms_per_frame": stages,
+            "conv_roofline": {"bound": "mfma", "achieved": round(conv_tf, 2), "peak": PEAK_TFLOPS["bf16"],
+                              "unit": "TFLOP/s", "frac": round(conv_tf / PEAK_TFLOPS["bf16"], 4),
+                              "flops_per_frame": round(conv_fl)},
+            "march_g_samples_per_s": round((prim + sec) / (stages["march"] * 1e-3) / 1e9, 2),
             "method_frames_per_s": round(1e3 / fm.mean(), 2), "latency_ms_p50": round(float(np.median(fm)), 4),
             "latency_ms_p99": round(float(np.percentile(fm, 99)), 4),
             "shadow_ms_mean": round(float(np.mean(shadow_ms)), 4),
@@ -349,36 +367,90 @@ def conv_source_hash() -> str:
     return source_hash(CONV_SOURCES)
 
 
-def march_traffic():
-    """HBM bytes of one headline march (relayout + march kernels) from the
-    committed rocprofv3 counter summary, or None when there is none or the
-    march sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "march_persp128_256px_traffic.md")
+# Samples of one frame's march (primary + light-march samples, the geometric
+# count with early termination as the method takes it), from the oracle's
+# counters for frame 0 of each workload: the per-unit figure of the march's
+# rate.  persp128: 270,662 + 8,304,019 at 256x256, 1,082,304 + 33,217,091
+# at 512x512.
+MARCH_SAMPLES = {"persp128_256px": (270662, 8304019), "persp128_512px": (1082304, 33217091)}
+# dynamic256_1024px, frame 0 (the blobs move, so later frames differ a little)
+DYNAMIC_SAMPLES = (8463809, 521045931)
+# A CU issues at most one wave64 VALU instruction per clock (four SIMDs, each
+# taking four clocks per wave64 instruction): 256 CUs x 2.4 GHz.
+VALU_PEAK_INSTS = 256 * 2.4e9
+
+
+def profile_blob(name, sources):
+    """The json block of a committed profile summary, or None when there is
+    none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     try:
         blob = json.loads(open(path).read().split("```json", 1)[1].split("```", 1)[0])
     except (IndexError, ValueError):
         return None
-    return blob.get("bytes_per_march") if blob.get("source_hash") == source_hash(MARCH_SOURCES) else None
+    return blob if blob.get("source_hash") == source_hash(sources) else None
 
 
-def march_roofline(lnm, wl, stage):
-    """The march against HBM: its compulsory bytes (grid read, bricks written
-    and read back, guiding map written) over the measured march time.  The
-    march is bound by its scattered trilinear gathers (L1/L2 lines), not by
-    HBM, so the fraction is small by design; `traffic` is the measured HBM
-    traffic from the counter summary."""
+def march_traffic():
+    """HBM bytes of one headline march (relayout + march kernels) from the
+    committed rocprofv3 counter summary, or None when there is none or the
+    march sources changed since it was taken."""
+    blob = profile_blob("march_persp128_256px_traffic.md", MARCH_SOURCES)
+    return blob.get("bytes_per_march") if blob else None
+
+
+def march_roofline(lnm, wl, stage, relayout_us=None):
+    """The march against its binding bound, the VALU issue rate: VALU
+    instructions per march (committed rocprofv3 counters, SQ_INSTS_VALU) over
+    the measured march time, against one wave64 instruction per CU per clock.
+    Beside it: samples per second (oracle sample counts of the frame), the
+    algorithmic HBM bytes (grid read once, guiding map written once) and the
+    measured HBM traffic against the 8 TB/s peak, and the brick relayout (a
+    plain copy: grid read, bricks written) against the same peak."""
     n = wl.grid
     H, W = wl.camera.height, wl.camera.width
-    bricks = int(lnm.lib().lnm_bricks_bytes(n, n, n))
-    compulsory = 4 * n ** 3 + 2 * bricks + 12 * H * W
     us = stage["march"]["us_per_frame"]
-    t = march_traffic()
-    return {"bound": "gather (L1/L2 lines)", "unit": "GB/s", "peak": HBM_PEAK_GBS,
-            "compulsory_bytes": compulsory, "achieved": round(compulsory / (us * 1e-6) / 1e9, 1),
-            "frac": round(compulsory / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5), "traffic": t,
-            "traffic_gbs": round(t / (us * 1e-6) / 1e9, 1) if t else None, "us_per_frame": round(us, 2)}
+    prim, sec = MARCH_SAMPLES[wl.name]
+    algorithmic = 4 * n ** 3 + 12 * H * W
+    headline = wl.name == "persp128_256px"  # the workload the committed counters were taken on
+    t = march_traffic() if headline else None
+    blob = profile_blob("march_persp128_256px_counters.md", MARCH_SOURCES) if headline else None
+    insts = blob.get("valu_insts_per_march") if blob else None
+    out = {"bound": "alu", "unit": "G VALU instr/s", "peak": round(VALU_PEAK_INSTS / 1e9, 1),
+           "achieved": round(insts / (us * 1e-6) / 1e9, 2) if insts else None,
+           "frac": round(insts / (us * 1e-6) / VALU_PEAK_INSTS, 4) if insts else None,
+           "valu_insts_per_march": insts, "us_per_frame": round(us, 2),
+           "samples": prim + sec, "g_samples_per_s": round((prim + sec) / (us * 1e-6) / 1e9, 2),
+           "hbm": {"algorithmic_bytes": algorithmic, "achieved_gbs": round(algorithmic / (us * 1e-6) / 1e9, 1),
+                   "peak_gbs": HBM_PEAK_GBS, "frac": round(algorithmic / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 5),
+                   "traffic": t, "traffic_gbs": round(t / (us * 1e-6) / 1e9, 1) if t else None}}
+    if relayout_us:
+        bricks = int(lnm.lib().lnm_bricks_bytes(n, n, n))
+        b = 4 * n ** 3 + bricks
+        out["relayout"] = {"bound": "hbm", "bytes": b, "us": round(relayout_us, 3),
+                           "achieved_gbs": round(b / (relayout_us * 1e-6) / 1e9, 1), "peak_gbs": HBM_PEAK_GBS,
+                           "frac": round(b / (relayout_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def relayout_time(lnm, ctx, dens, reps=50):
+    """Mean duration of the brick relayout of the grid (lnm_make_bricks: grid
+    read, bricks written), HIP events on the stream it runs on."""
+    import torch
+
+    out = ctx.make_bricks(dens)
+    for _ in range(5):
+        ctx.make_bricks(dens, out=out)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        ctx.make_bricks(dens, out=out)
+    e1.record(st)
+    e1.synchronize()
+    return 1e3 * e0.elapsed_time(e1) / reps
 
 
 def measured_traffic(dtype):
@@ -429,6 +501,7 @@ def main():
     ap.add_argument("--no-dynamic", action="store_true", help="skip the dynamic-scene mode")
     ap.add_argument("--no-adapters", action="store_true", help="skip the channel-adapter mode")
     ap.add_argument("--no-two-streams", action="store_true", help="skip the two-stream throughput pass")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 512x512 frame timing")
     ap.add_argument("--dynamic-frames", type=int, default=60)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU time of the oracle sample")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -505,7 +578,7 @@ def main():
                    "camera": "perspective 60deg at 2.5", "step_voxels": wl.step_voxels, "unet_levels": wl.levels,
                    "unet_base": wl.base, "batch": 1, "lights": 1},
         "roofline": main_r["roofline"],
-        "march_roofline": march_roofline(lnm, wl, main_r["stage"]),
+        "march_roofline": march_roofline(lnm, wl, main_r["stage"], relayout_time(lnm, ctx, dens)),
         "stages_us_per_frame": {k: round(v["us_per_frame"], 2) for k, v in main_r["stage"].items()},
         "frames_per_s_two_streams": round(main_r["two_streams"]["fps"], 2) if "two_streams" in main_r else None,
         "modes": {dt: {"value": round(r["fps"], 2), "ms_per_step": round(r["ms_per_step"], 5),
@@ -514,6 +587,24 @@ def main():
                        "stages_us_per_frame": {k: round(v["us_per_frame"], 2) for k, v in r["stage"].items()}}
                   for dt, r in res.items() if dt != args.dtype},
     }
+    if not args.no_c3:
+        # the precision configuration's frame: the same volume and camera at
+        # 512x512, each precision
+        wl3 = headline(res=512)
+        c3 = {}
+        for dt in ("fp32", "bf16", "fp8"):
+            net = lnm.Net(ctx, wl3.levels, wl3.base, params, precision=prec[dt],
+                          act_scales=amax if dt == "fp8" else None)
+            steps3 = max(20, args.steps // 4)
+            r = measure(lnm, ctx, net, dens, wl3, light, steps3, max(5, args.warmup // 4), stream)
+            del net
+            c3[dt] = {"value": round(r["fps"], 2), "ms_per_step": round(r["ms_per_step"], 5),
+                      "roofline": conv_roofline(wl3, r["stage"], dt),
+                      "stages_us_per_frame": {k: round(v["us_per_frame"], 2) for k, v in r["stage"].items()}}
+            if dt == "fp32":
+                c3[dt]["march_roofline"] = march_roofline(lnm, wl3, r["stage"])
+            log(f"512x512 {dt}: {r['ms_per_step']:.4f} ms/frame, {r['fps']:.1f} frames/s")
+        out["persp128_512px"] = c3
     if not args.no_precision:
         # the precision configuration: the same volume and camera, 512x512
         out["precision_error_vs_fp64_oracle"], _ = precision_report(lnm, ctx, headline(res=512), params, dens)
@@ -528,17 +619,20 @@ def main():
         def rounded(st):
             return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
 
-        # the configured load (2000 frames/s offered, 64 GB), then half that
-        # load, the configured load under a 2 GB budget so admission binds,
-        # and 8000 frames/s offered for 3 s, beyond what the server keeps up
+        # the configured load (2000 frames/s offered, 64 GB) with batches held
+        # up to 2 ms while the device is busy; then the same load launched
+        # without holding, half that load, the configured load under a 6 GB
+        # budget (resident grids and bricks included) so admission binds, and
+        # 8000 frames/s offered for 3 s, beyond what the server keeps up
         # with: its throughput there is the server's capacity
-        out["served"] = rounded(served(lnm, ctx, params, args.serve_seconds, warmup_s=1.0))
+        out["served"] = rounded(served(lnm, ctx, params, args.serve_seconds, warmup_s=1.0, hold_ms=2.0))
         log(f"served: {out['served']}")
         other_s = min(args.serve_seconds, 5.0)
         out["served_other_loads"] = [
-            rounded(served(lnm, ctx, params, other_s, warmup_s=1.0, rate_hz=1000.0)),
-            rounded(served(lnm, ctx, params, other_s, warmup_s=1.0, budget_gb=2.0)),
-            rounded(served(lnm, ctx, params, min(other_s, 3.0), warmup_s=1.0, rate_hz=8000.0)),
+            rounded(served(lnm, ctx, params, other_s, warmup_s=1.0, hold_ms=0.0)),
+            rounded(served(lnm, ctx, params, other_s, warmup_s=1.0, rate_hz=1000.0, hold_ms=2.0)),
+            rounded(served(lnm, ctx, params, other_s, warmup_s=1.0, budget_gb=6.0, hold_ms=2.0)),
+            rounded(served(lnm, ctx, params, min(other_s, 3.0), warmup_s=1.0, rate_hz=8000.0, hold_ms=2.0)),
         ]
         log(f"served at other loads: {out['served_other_loads']}")
     if not args.no_cpu_baseline:
