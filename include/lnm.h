@@ -299,6 +299,17 @@ LNM_API lnm_status lnm_composite(lnm_ctx ctx, const lnm_camera* cam, const lnm_l
                          int32_t batch, int32_t H, int32_t W, const float* lightmaps, const float* guide, float* rgba,
                          void* stream);
 
+/* Six-way shading (Section 3, as lnm_composite) of B images of one size in
+ * one launch, each with its own camera and lights, e.g. the frames of a
+ * serving batch: image b is shaded with cams[b] (width W, height H) and the
+ * host lights[light_start[b] .. light_start[b + 1]), exactly as lnm_composite
+ * shades it alone.  lightmaps [B][H][W][6], guides [B][H][W][3], rgba
+ * [B][H][W][4] (device).  batch in [1, 64], light_start[0] = 0, at most 16
+ * lights per image and 64 in all. */
+LNM_API lnm_status lnm_composite_batch(lnm_ctx ctx, int32_t batch, const lnm_camera* cams, const lnm_light* lights,
+                                       const int32_t* light_start, int32_t H, int32_t W, const float* lightmaps,
+                                       const float* guides, float* rgba, void* stream);
+
 /* ----------------------------------------------------------- channel adapters */
 /* Channel adapters (Section 4.3): four NAFBlocks on the decoder output of a
  * network (width c = its base), one per output group, each followed by a 1x1

@@ -840,6 +840,47 @@ lnm_status lnm_composite(lnm_ctx ctx, const lnm_camera* cam, const lnm_light* li
   return LNM_OK;
 }
 
+lnm_status lnm_composite_batch(lnm_ctx ctx, int32_t batch, const lnm_camera* cams, const lnm_light* lights,
+                               const int32_t* light_start, int32_t H, int32_t W, const float* lightmaps,
+                               const float* guides, float* rgba, void* stream) {
+  if (!ctx || !cams || !light_start || !lightmaps || !guides || !rgba) return fail(LNM_ERR_ARG, "NULL argument");
+  if (batch < 1 || batch > kBatchShadeImages) return fail(LNM_ERR_ARG, "batch must be in [1, 64]");
+  if (H < 1 || W < 1 || (double)batch * H * W > 2.0e9) return fail(LNM_ERR_SHAPE, "H and W must be >= 1");
+  if (light_start[0] != 0) return fail(LNM_ERR_ARG, "light_start[0] must be 0");
+  const int n_lights = light_start[batch];
+  if (n_lights < 0 || n_lights > kBatchShadeLights) return fail(LNM_ERR_ARG, "at most 64 lights in all");
+  if (n_lights && !lights) return fail(LNM_ERR_ARG, "lights is NULL");
+  CompositeBatchArgs a{};
+  for (int b = 0; b < batch; ++b) {
+    if (light_start[b + 1] < light_start[b]) return fail(LNM_ERR_ARG, "light_start must not decrease");
+    if (cams[b].width != W || cams[b].height != H)
+      return fail(LNM_ERR_SHAPE, "camera " + std::to_string(b) + " is not W x H");
+    CamDev c;
+    std::string why;
+    if (!make_cam(cams[b], &c, &why)) return fail(LNM_ERR_ARG, "camera " + std::to_string(b) + ": " + why);
+    CompositeArgs one{};
+    const int k0 = light_start[b], nk = light_start[b + 1] - k0;
+    if (nk > 16) return fail(LNM_ERR_ARG, "at most 16 lights per image");
+    lnm_status st = light_setup(c, lights + k0, nk, &one);
+    if (st) return st;
+    for (int k = 0; k < nk; ++k)
+      for (int q = 0; q < 3; ++q) {
+        a.l[k0 + k][q] = one.l[k][q];
+        a.rgb[k0 + k][q] = one.rgb[k][q];
+      }
+    a.light_lo[b] = k0;
+  }
+  a.light_lo[batch] = n_lights;
+  a.lm = lightmaps;
+  a.guide = guides;
+  a.rgba = rgba;
+  a.P = H * W;
+  a.B = batch;
+  ProfScope ps(ctx, LNM_K_COMPOSITE, (hipStream_t)stream);
+  LNM_HIP_CHECK(launch_composite_batch(a, (hipStream_t)stream));
+  return LNM_OK;
+}
+
 // ---------------------------------------------------------------- channel adapters
 static size_t adapters_params(int c) { return c >= 1 ? 4 * (7 * (size_t)c * c + 35 * (size_t)c + 2) : 0; }
 

@@ -353,6 +353,17 @@ __global__ __launch_bounds__(256) void composite_kernel(CompositeArgs a) {
   shade_pixel(a, p, L);
 }
 
+// Six-way shading of a batch of images with per-image lights.
+__global__ __launch_bounds__(256) void composite_batch_kernel(CompositeBatchArgs a) {
+  const long p = (long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= (long)a.P * a.B) return;
+  const int b = (int)(p / a.P);
+  float L[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) L[q] = a.lm[(size_t)p * 6 + q];
+  shade_lights(a.l, a.rgb, a.light_lo[b], a.light_lo[b + 1], a.guide, a.rgba, (size_t)p, L);
+}
+
 // Weight gradient of a 3x3 layer: dW[o][c][tap] = sum_p E[p][o] X[p + tap][c]
 // as an MFMA GEMM with M = output channels, N = input channels, K = pixels.
 // Workgroup: 32 output channels x 16 input channels x 9 taps over a group of
@@ -576,6 +587,12 @@ hipError_t launch_head(const HeadArgs& a, hipStream_t s, const CompositeArgs* co
 
 hipError_t launch_composite(const CompositeArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(composite_kernel, dim3((a.P + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_composite_batch(const CompositeBatchArgs& a, hipStream_t s) {
+  const long n = (long)a.P * a.B;
+  hipLaunchKernelGGL(composite_batch_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

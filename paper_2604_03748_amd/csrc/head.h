@@ -10,29 +10,35 @@ __device__ __forceinline__ float srgb_decode(float s) {
   return s <= 0.04045f ? s / 12.92f : powf((s + 0.055f) / 1.055f, 2.4f);
 }
 
-// Six-way shading of one pixel from its six lightmap values:
+// Six-way shading of one pixel from its six lightmap values with lights
+// [k0, k1) of the tables l (camera frame) and rgb:
 // rgb = sum_l c_l sum_p |l_p| lin(L_p^{sign l_p}), alpha = 1 - T.
-__device__ __forceinline__ void shade_pixel(const CompositeArgs& a, int p, const float (&L)[6]) {
+__device__ __forceinline__ void shade_lights(const float (*l)[3], const float (*rgb)[3], int k0, int k1,
+                                             const float* guide, float* rgba, size_t p, const float (&L)[6]) {
   float lin[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) lin[q] = srgb_decode(L[q]);
   float r = 0.f, gg = 0.f, bb = 0.f;
-  for (int k = 0; k < a.n_lights; ++k) {
+  for (int k = k0; k < k1; ++k) {
     float s = 0.f;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const float c = a.l[k][ax];
+      const float c = l[k][ax];
       s += fabsf(c) * (c >= 0.0f ? lin[2 * ax] : lin[2 * ax + 1]);
     }
-    r += a.rgb[k][0] * s;
-    gg += a.rgb[k][1] * s;
-    bb += a.rgb[k][2] * s;
+    r += rgb[k][0] * s;
+    gg += rgb[k][1] * s;
+    bb += rgb[k][2] * s;
   }
-  float* o = a.rgba + (size_t)p * 4;
+  float* o = rgba + p * 4;
   o[0] = r;
   o[1] = gg;
   o[2] = bb;
-  o[3] = 1.0f - a.guide[(size_t)p * 3 + 1];
+  o[3] = 1.0f - guide[p * 3 + 1];
+}
+
+__device__ __forceinline__ void shade_pixel(const CompositeArgs& a, int p, const float (&L)[6]) {
+  shade_lights(a.l, a.rgb, 0, a.n_lights, a.guide, a.rgba, (size_t)p, L);
 }
 
 // Head epilogue of a conv layer (one 32-channel output tile): the tile's

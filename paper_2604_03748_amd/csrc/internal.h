@@ -175,6 +175,20 @@ struct CompositeArgs {
 };
 hipError_t launch_composite(const CompositeArgs& a, hipStream_t s);
 
+// Shading of a batch of equally sized images, each with its own camera
+// frame and lights: image b takes lights [light_lo[b], light_lo[b + 1]).
+constexpr int kBatchShadeImages = 64, kBatchShadeLights = 64;
+struct CompositeBatchArgs {
+  const float* lm;     // [B][P][6]
+  const float* guide;  // [B][P][3]
+  float* rgba;         // [B][P][4]
+  int P, B;            // pixels per image, images
+  int light_lo[kBatchShadeImages + 1];
+  float l[kBatchShadeLights][3];  // light direction in its image's camera frame
+  float rgb[kBatchShadeLights][3];
+};
+hipError_t launch_composite_batch(const CompositeBatchArgs& a, hipStream_t s);
+
 // The 1x1 head (+ sigmoid, + optional shading) applied in the last fp32 conv
 // layer's epilogue: that layer's workgroup holds all its channels.
 struct HeadFuse {

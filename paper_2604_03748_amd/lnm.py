@@ -7,6 +7,7 @@ library is missing this module raises; there is no fallback.
 from __future__ import annotations
 
 import ctypes as C
+import functools
 import os
 
 import numpy as np
@@ -31,7 +32,7 @@ EXPORTS = [
     "lnm_trainer_read_params", "lnm_trainer_save", "lnm_trainer_load", "lnm_trainer_infer", "lnm_calibrate_amax",
     "lnm_shadow_map_sphere", "lnm_composite_shadowed", "lnm_bricks_bytes", "lnm_make_bricks",
     "lnm_adapters_param_count", "lnm_adapters_device_bytes", "lnm_adapters_create", "lnm_adapters_destroy",
-    "lnm_adapters_workspace_bytes", "lnm_infer_adapters", "lnm_frame_static",
+    "lnm_adapters_workspace_bytes", "lnm_infer_adapters", "lnm_frame_static", "lnm_composite_batch",
 ]
 STATIC_SCRATCH_BYTES = 128 << 20  # LNM_STATIC_SCRATCH_BYTES
 K_MARCH, K_CONV, K_HEAD, K_COMPOSITE, K_REFERENCE, K_ADAPTERS = range(6)
@@ -131,6 +132,9 @@ def lib():
         L.lnm_frame_static.restype = i32
         L.lnm_frame_static.argtypes = [vp, vp, C.POINTER(Volume), C.POINTER(Camera), C.POINTER(MarchParams),
                                        C.POINTER(Light), i32, vp, vp, vp, vp]
+        L.lnm_composite_batch.restype = i32
+        L.lnm_composite_batch.argtypes = [vp, i32, C.POINTER(Camera), C.POINTER(Light), C.POINTER(i32), i32, i32, vp,
+                                          vp, vp, vp]
         L.lnm_composite.restype = i32
         L.lnm_composite.argtypes = [vp, C.POINTER(Camera), C.POINTER(Light), i32, i32, i32, i32, vp, vp, vp, vp]
         L.lnm_shadow_map_sphere.restype = i32
@@ -172,6 +176,24 @@ def check(status: int):
 # ------------------------------------------------------------------ marshalling
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _on_stream(fn):
+    """Run a binding method with `stream` (when given) as torch's current
+    stream, so every tensor the method allocates for the call (outputs,
+    workspaces) belongs to the stream its kernels run on and the caching
+    allocator never hands that memory to other work while they use it."""
+    @functools.wraps(fn)
+    def wrapper(*args, **kw):
+        stream = kw.get("stream")
+        if stream is None:
+            return fn(*args, **kw)
+        import torch
+
+        with torch.cuda.stream(stream):
+            return fn(*args, **kw)
+
+    return wrapper
 
 
 def _stream(stream=None):
@@ -273,6 +295,7 @@ class Context:
         return n.value, ms.value
 
     # -- march
+    @_on_stream
     def make_bricks(self, density, out=None, stream=None):
         """Bricked copy of a density grid for repeated marches (lnm_make_bricks)."""
         import torch
@@ -290,6 +313,7 @@ class Context:
         c = make_camera(cam)
         return int(lib().lnm_march_workspace_bytes(C.byref(vol), C.byref(c), C.byref(params)))
 
+    @_on_stream
     def march(self, density, sigma_scale, cam, params: MarchParams, out=None, workspace=None, stream=None,
               bricks=None):
         import torch
@@ -306,6 +330,7 @@ class Context:
                               workspace.numel(), _stream(stream)))
         return out
 
+    @_on_stream
     def march_batch(self, densities, sigma_scales, cams, params, outs=None, workspace=None, stream=None,
                     bricks=None):
         """n guiding maps in one call (lnm_march_batch): lists of grids,
@@ -333,6 +358,7 @@ class Context:
                                     _stream(stream)))
         return outs
 
+    @_on_stream
     def reference_lightmaps(self, density, sigma_scale, cam, step_voxels=0.25, ert_eps=1e-6, srgb=False, out=None,
                             stream=None):
         import torch
@@ -346,6 +372,7 @@ class Context:
                                             _ptr(out), _stream(stream)))
         return out
 
+    @_on_stream
     def composite(self, cam, lights, lightmaps, guide, out=None, stream=None):
         import torch
 
@@ -359,6 +386,31 @@ class Context:
                                   _stream(stream)))
         return out
 
+    @_on_stream
+    def composite_batch(self, cams, lights, lightmaps, guides, out=None, stream=None):
+        """lnm_composite_batch: image b of lightmaps [B][H][W][6] / guides
+        [B][H][W][3] shaded with cams[b] and its own list lights[b]."""
+        import torch
+
+        B, H, W = lightmaps.shape[0], lightmaps.shape[1], lightmaps.shape[2]
+        _need(lightmaps, (B, H, W, 6), "lightmaps")
+        _need(guides, (B, H, W, 3), "guides")
+        if out is None:
+            out = torch.empty((B, H, W, 4), dtype=torch.float32, device=lightmaps.device)
+        _need(out, (B, H, W, 4), "out")
+        if len(cams) != B or len(lights) != B:
+            raise ValueError("one camera and one light list per image")
+        ca = (Camera * B)(*[make_camera(c) for c in cams])
+        flat = [l for ls in lights for l in ls]
+        arr, _ = make_lights(flat)
+        start = (C.c_int32 * (B + 1))()
+        for b in range(B):
+            start[b + 1] = start[b] + len(lights[b])
+        check(lib().lnm_composite_batch(self.handle, B, ca, arr, start, H, W, _ptr(lightmaps), _ptr(guides), _ptr(out),
+                                        _stream(stream)))
+        return out
+
+    @_on_stream
     def shadow_map_sphere(self, frame: ShadowFrame, light_dir, centre, radius, out=None, stream=None):
         """[size][size] obstacle depths of a sphere seen from a directional light."""
         import torch
@@ -372,6 +424,7 @@ class Context:
                                           f3(*map(float, centre)), float(radius), _ptr(out), _stream(stream)))
         return out
 
+    @_on_stream
     def composite_shadowed(self, cam, lights, frame: ShadowFrame, depth_maps, lightmaps, guide, out=None, vis=None,
                            stream=None):
         """Six-way shading with light k's term masked by the visibility of each
@@ -429,6 +482,7 @@ class Net:
     def workspace_bytes(self, batch, H, W) -> int:
         return int(lib().lnm_workspace_bytes(self.handle, batch, H, W))
 
+    @_on_stream
     def calibrate_amax(self, guide, stream=None) -> np.ndarray:
         """Per-convolution maximum |output| of this (fp32) net on guide [B][H][W][3]."""
         g = guide if guide.dim() == 4 else guide.unsqueeze(0)
@@ -446,6 +500,7 @@ class Net:
 
         return torch.empty(max(1, self.workspace_bytes(batch, H, W)), dtype=torch.uint8, device=self.buf.device)
 
+    @_on_stream
     def infer(self, guide, out=None, logits=None, workspace=None, stream=None):
         import torch
 
@@ -470,6 +525,7 @@ class Net:
             raise LnmError(LNM_ERR_SHAPE, "no frame workspace for these arguments")
         return torch.empty(n, dtype=torch.uint8, device=density.device)
 
+    @_on_stream
     def frame(self, density, sigma_scale, cam, params: MarchParams, lights=(), guide=None, lightmaps=None, rgba=None,
               workspace=None, stream=None, shade=True, bricks=None):
         import torch
@@ -567,6 +623,7 @@ class Trainer:
             self._ws[key] = torch.empty(max(n, 1), dtype=torch.uint8, device=self.state.device)
         return self._ws[key]
 
+    @_on_stream
     def grad(self, guide, target, stream=None):
         """(loss tensor [1], gradient tensor [n_params]) for one batch."""
         import torch
@@ -581,6 +638,7 @@ class Trainer:
                                    _ptr(g), _ptr(ws), ws.numel(), _stream(stream)))
         return loss, g
 
+    @_on_stream
     def step(self, guide, target, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, loss=None, stream=None):
         import torch
 
@@ -615,6 +673,7 @@ class Trainer:
         check(lib().lnm_trainer_load(self.handle, p.ctypes.data_as(C.c_void_p), m.ctypes.data_as(C.c_void_p),
                                      v.ctypes.data_as(C.c_void_p), int(ck["step"]), self.n_params, _stream(stream)))
 
+    @_on_stream
     def infer(self, guide, out=None, stream=None):
         import torch
 
@@ -666,6 +725,7 @@ class Adapters:
             raise LnmError(LNM_ERR_SHAPE, "no adapter workspace for these sizes")
         return torch.empty(n, dtype=torch.uint8, device=self.buf.device)
 
+    @_on_stream
     def infer(self, guide, out=None, extra=None, with_extra=True, workspace=None, stream=None):
         """guide [B][H][W][3] -> (lightmaps [B][H][W][6], extra [B][H][W][2] or None)."""
         import torch

@@ -1,15 +1,22 @@
 """Continuous-batching frame server for many smoke instances.
 
 Each request asks for the next frame of one smoke instance (its density grid,
-and optionally the march's bricked copy of it, stay resident on the device).  The scheduler admits pending requests in
-arrival order as stream slots and HBM budget free up: requests of the same
-view resolution are grouped into a batch, each is marched from its own grid
-and camera, the batch goes through one U-Net call, and each result is shaded
-for its own lights.  Batches are issued on several HIP streams, so work of
-requests that arrive while others run overlaps on the device.  Every kernel
-computes an image from that image's inputs only, in the same order
-regardless of batch composition, so a frame is bit-identical alone and in a
-mix.
+and optionally the march's bricked copy of it, stay resident on the device).
+The HBM budget covers everything the server keeps on the device: the
+resident grids and brick copies are charged when the scheduler starts (grids
+and then brick copies are admitted smallest first; a brick copy that does not
+fit is dropped and that instance's marches rebuild bricks in their per-batch
+scratch; an instance whose grid does not fit is not served), and each batch's images, activations and
+march scratch while it is in flight.  The scheduler admits pending requests
+in arrival order as stream slots and budget free up: requests of the same
+view resolution are grouped into a batch (held up to a stated deadline for
+more of the same size while other batches keep the device busy), each is
+marched from its own grid and camera, the batch goes through one U-Net call
+and one shading launch that gives each image its own camera and light.
+Batches are issued on several HIP streams, so work of requests that arrive
+while others run overlaps on the device.  Every kernel computes an image
+from that image's inputs only, in the same order regardless of batch
+composition, so a frame is bit-identical alone and in a mix.
 
 The device work is the library's (march, U-Net, shading); this module is
 host-side scheduling, memory accounting and timing.
@@ -87,6 +94,14 @@ class Backend:
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
         self.keep = {}
 
+    @staticmethod
+    def resident_bytes(inst) -> int:
+        """Device bytes an instance keeps resident: its grid and brick copy."""
+        n = inst.density.numel() * inst.density.element_size()
+        if inst.bricks is not None:
+            n += inst.bricks.numel() * inst.bricks.element_size()
+        return n
+
     def request_bytes(self, res: int) -> int:
         """Device bytes one request of this view size occupies while in flight
         (its images and its share of the batched U-Net activations)."""
@@ -122,9 +137,9 @@ class Backend:
                                  outs=[guide[b] for b in range(B)], workspace=mws, stream=st,
                                  bricks=[i.bricks for i in insts])
             self.net.infer(guide, out=lm, workspace=ws, stream=st)
-            for b, r in enumerate(reqs):
-                inst = instances[r.instance]
-                self.ctx.composite(inst.camera(r.frame), [inst.light], lm[b], guide[b], out=rgba[b], stream=st)
+            # one shading launch for the batch, each image with its own camera and light
+            self.ctx.composite_batch([i.camera(r.frame) for i, r in zip(insts, reqs)], [[i.light] for i in insts],
+                                     lm, guide, out=rgba, stream=st)
             ev = torch.cuda.Event()
             ev.record(st)
         for b, r in enumerate(reqs):
@@ -138,17 +153,46 @@ class Backend:
 
 
 class Scheduler:
-    """Admission by HBM budget and stream slots, batching by view size."""
+    """Admission by HBM budget and stream slots, batching by view size.
+
+    hold_s: while at least one batch is in flight, a group of equal-size
+    requests smaller than max_batch waits until its oldest request has waited
+    this long (0: launch whatever is pending as soon as a slot is free); an
+    idle device takes pending requests at once."""
 
     def __init__(self, backend, instances, budget_bytes: int, max_batch: int = 16, clock=time.perf_counter,
-                 keep_ids=()):
+                 keep_ids=(), hold_s: float = 0.0):
         self.be, self.inst = backend, instances
         self.budget = int(budget_bytes)
         self.max_batch = max_batch
         self.clock = clock
         self.keep_ids = set(keep_ids)
-        self.in_use = 0
-        self.peak_in_use = 0
+        self.hold_s = float(hold_s)
+        # resident data first: grids, then brick copies while they fit
+        self.unserved = set()
+        self.dropped_bricks = []
+        resident = 0
+        rb = getattr(backend, "resident_bytes", None)
+        if rb is not None:
+            for k in sorted(instances, key=lambda k: self._grid_bytes(instances[k])):
+                g = self._grid_bytes(instances[k])
+                if resident + g > self.budget:
+                    self.unserved.add(k)
+                else:
+                    resident += g
+            for k in sorted(instances, key=lambda k: self._grid_bytes(instances[k])):
+                inst = instances[k]
+                if k in self.unserved or getattr(inst, "bricks", None) is None:
+                    continue
+                extra = rb(inst) - self._grid_bytes(inst)
+                if resident + extra <= self.budget:
+                    resident += extra
+                else:
+                    inst.bricks = None
+                    self.dropped_bricks.append(k)
+        self.resident = resident
+        self.in_use = resident
+        self.peak_in_use = resident
         self.free_slots = list(range(len(getattr(backend, "streams", [0]))))
         self.inflight = []  # (slot, handle, reqs, bytes)
         self.done = []
@@ -156,8 +200,28 @@ class Scheduler:
         self.rejected = []  # requests larger than the whole budget
         self.failed = []  # (request, error) of batches whose launch failed
 
+    @staticmethod
+    def _grid_bytes(inst) -> int:
+        d = getattr(inst, "density", None)
+        return d.numel() * d.element_size() if d is not None else 0
+
+    def _ready(self, pending, now) -> bool:
+        """Whether the oldest pending request's group should launch now."""
+        if self.hold_s <= 0 or not self.inflight:
+            return True
+        first = pending[0]
+        if now - first.t_arrival >= self.hold_s:
+            return True
+        res = self.inst[first.instance].res
+        return sum(1 for r in pending if self.inst[r.instance].res == res) >= self.max_batch
+
     def _admit(self, pending, now):
-        while self.free_slots and pending:
+        while pending and pending[0].instance in self.unserved:
+            self.rejected.append(pending.popleft())
+        while self.free_slots and pending and self._ready(pending, now):
+            if pending[0].instance in self.unserved:
+                self.rejected.append(pending.popleft())
+                continue
             res = self.inst[pending[0].instance].res
             need1 = self.be.request_bytes(res)
             if hasattr(self.be, "batch_bytes"):
@@ -169,7 +233,7 @@ class Scheduler:
             keep = collections.deque()
             while pending and len(batch) < self.max_batch:
                 r = pending.popleft()
-                if self.inst[r.instance].res != res:
+                if self.inst[r.instance].res != res or r.instance in self.unserved:
                     keep.append(r)
                     continue
                 nb = self.be.request_bytes(res)
@@ -251,8 +315,13 @@ class Scheduler:
             "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
             "mean_batch": len(self.done) / max(self.n_batches, 1),
-            "peak_bytes_in_flight": self.peak_in_use,
+            "hold_ms": self.hold_s * 1e3,
+            "resident_bytes": self.resident,
+            "peak_bytes": self.peak_in_use,
+            "peak_bytes_in_flight": self.peak_in_use - self.resident,
             "budget_bytes": self.budget,
+            "instances_unserved": len(self.unserved),
+            "brick_copies_dropped": len(self.dropped_bricks),
         }
 
 
