@@ -79,6 +79,9 @@ def lib():
         L.orc_adapter_param_count.argtypes = [C.c_int]
         L.orc_adapters_forward.restype = C.c_int
         L.orc_adapters_forward.argtypes = [C.c_int, _F, C.c_long, C.c_int, C.c_int, C.c_int, _D, _D, _D]
+        L.orc_adapters_loss_grad.restype = C.c_int
+        L.orc_adapters_loss_grad.argtypes = [C.c_int, C.c_int, _F, C.c_long, _F, C.c_long, C.c_int, C.c_int, C.c_int,
+                                             _D, _D, _D, _D, _D]
         L.orc_adam.restype = None
         L.orc_adam.argtypes = [C.c_long, _D, _D, _D, _D, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
         L.orc_num_threads.restype = C.c_int
@@ -281,6 +284,27 @@ def adapters_forward(params, c, feat):
     if st:
         raise ValueError(f"orc_adapters_forward status {st}")
     return (lm[0], ex[0]) if squeeze else (lm, ex)
+
+
+def adapters_loss_grad(params, levels, base, ad_params, guide, target):
+    """The network with the four adapters in place of its head: (loss,
+    gradient of the trunk's parameters (head entries 0), gradient of the
+    adapters' parameters)."""
+    g = _f64(guide)
+    t = _f64(target)
+    if g.ndim == 3:
+        g, t = g[None], t[None]
+    B, H, W, _ = g.shape
+    p = _f32(params)
+    a = _f32(ad_params)
+    grad = np.zeros(p.size, dtype=np.float64)
+    grad_ad = np.zeros(a.size, dtype=np.float64)
+    loss = np.zeros(1, dtype=np.float64)
+    st = lib().orc_adapters_loss_grad(levels, base, _fp(p), p.size, _fp(a), a.size, B, H, W, _dp(g), _dp(t),
+                                      _dp(loss), _dp(grad), _dp(grad_ad))
+    if st:
+        raise ValueError(f"orc_adapters_loss_grad status {st}")
+    return float(loss[0]), grad, grad_ad
 
 
 def unet_loss_grad(params, levels, base, guide, target):

@@ -792,41 +792,14 @@ ORC_EXPORT int orc_unet_forward(int levels, int base, const float* params, long 
   return 0;
 }
 
-/* Loss (mean squared error over B*H*W*6 against target_srgb[B][H][W][6]) and
- * its gradient with respect to every parameter (grad[n_params], written). */
-ORC_EXPORT int orc_unet_loss_grad(int levels, int base, const float* params, long n_params, int B, int H, int W,
-                                  const double* guide, const double* target, double* loss, double* grad) {
-  Net net;
-  int st = net_setup(levels, base, params, n_params, &net);
-  if (st) return st;
-  int div = 1 << (levels - 1);
-  if (B < 1 || H < 1 || W < 1 || H % div || W % div) return 3;
-  Fwd f;
-  unet_forward_saved(&net, B, H, W, guide, &f);
-  const size_t npix = (size_t)B * H * W;
-  const double inv = 1.0 / (double)(npix * 6);
-  double* t = malloc(sizeof(double) * npix * 6);
-  /* target to NCHW */
-  for (int b = 0; b < B; ++b)
-    for (int c = 0; c < 6; ++c)
-      for (size_t q = 0; q < (size_t)H * W; ++q) t[((size_t)b * 6 + c) * H * W + q] = target[((size_t)b * H * W + q) * 6 + c];
-  double l = 0.0;
-  double* dz = malloc(sizeof(double) * npix * 6);
-  for (size_t q = 0; q < npix * 6; ++q) {
-    double e = f.pred[q] - t[q];
-    l += e * e;
-    dz[q] = 2.0 * e * inv * f.pred[q] * (1.0 - f.pred[q]);
-  }
-  *loss = l * inv;
-  memset(grad, 0, sizeof(double) * (size_t)net.n_params);
-  free(t);
-  /* backward through the layers in reverse */
-  const int L = levels;
-  int li = net.n - 1;
-  double* g = malloc(sizeof(double) * npix * net.L[li].ci);
-  conv_bwd(f.x_in[li], dz, B, f.hh[li], f.ww[li], &net.L[li], grad, g); /* head */
-  free(dz);
-  --li;
+/* Backward through the trunk (every layer but the head), from g, the
+ * gradient with respect to the head's input (the last decoder layer's
+ * output, NCHW; freed here), adding each layer's parameter gradient to grad. */
+static void trunk_backward(const Net* net_p, const Fwd* fp, int B, double* g, double* grad) {
+  const Net net = *net_p;
+  const Fwd f = *fp;
+  const int L = net.levels;
+  int li = net.n - 2;
   /* gradient flowing into each encoder skip from the decoder concat */
   double* skip_grad[16] = {0};
   int skip_layer[16];
@@ -888,6 +861,42 @@ ORC_EXPORT int orc_unet_loss_grad(int levels, int base, const float* params, lon
   }
   free(g);
   for (int lv = 0; lv < L - 1; ++lv) free(skip_grad[lv]);
+}
+
+/* Loss (mean squared error over B*H*W*6 against target_srgb[B][H][W][6]) and
+ * its gradient with respect to every parameter (grad[n_params], written). */
+ORC_EXPORT int orc_unet_loss_grad(int levels, int base, const float* params, long n_params, int B, int H, int W,
+                                  const double* guide, const double* target, double* loss, double* grad) {
+  Net net;
+  int st = net_setup(levels, base, params, n_params, &net);
+  if (st) return st;
+  int div = 1 << (levels - 1);
+  if (B < 1 || H < 1 || W < 1 || H % div || W % div) return 3;
+  Fwd f;
+  unet_forward_saved(&net, B, H, W, guide, &f);
+  const size_t npix = (size_t)B * H * W;
+  const double inv = 1.0 / (double)(npix * 6);
+  double* t = malloc(sizeof(double) * npix * 6);
+  /* target to NCHW */
+  for (int b = 0; b < B; ++b)
+    for (int c = 0; c < 6; ++c)
+      for (size_t q = 0; q < (size_t)H * W; ++q) t[((size_t)b * 6 + c) * H * W + q] = target[((size_t)b * H * W + q) * 6 + c];
+  double l = 0.0;
+  double* dz = malloc(sizeof(double) * npix * 6);
+  for (size_t q = 0; q < npix * 6; ++q) {
+    double e = f.pred[q] - t[q];
+    l += e * e;
+    dz[q] = 2.0 * e * inv * f.pred[q] * (1.0 - f.pred[q]);
+  }
+  *loss = l * inv;
+  memset(grad, 0, sizeof(double) * (size_t)net.n_params);
+  free(t);
+  /* backward through the head, then the trunk */
+  const int li = net.n - 1;
+  double* g = malloc(sizeof(double) * npix * net.L[li].ci);
+  conv_bwd(f.x_in[li], dz, B, f.hh[li], f.ww[li], &net.L[li], grad, g);
+  free(dz);
+  trunk_backward(&net, &f, B, g, grad);
   fwd_free(&f, net.n);
   return 0;
 }
@@ -1029,6 +1038,317 @@ ORC_EXPORT int orc_adapters_forward(int c, const float* params, long n_params, i
       }
   }
   free(o2);
+  return 0;
+}
+
+/* ------------------------------------------------- channel adapters: training */
+/*
+ * The adapters' backward pass, for training them with the network (Section
+ * 4.3 puts them on the decoder output; Section 5 trains the whole model on
+ * the lightmap loss).  adapter_forward_saved takes the same steps in the
+ * same order as adapter_forward and keeps every intermediate; the backward
+ * pass applies the chain rule to them in reverse.  The layer norm's
+ * gradient is the textbook one: with xh = (x - mu) r, r = 1 / sqrt(var +
+ * eps) and dxh the gradient at xh, dx = r (dxh - mean(dxh) - xh mean(dxh
+ * xh)).  The depthwise conv's input gradient is the transposed
+ * correlation (each tap sends dw * g back to the input pixel it read).
+ */
+typedef struct {
+  double *xh1, *r1;        /* layer norm 1: normalised input [n][c], 1 / sigma [n] */
+  double *u, *d;           /* conv1 output, depthwise output [n][2c] */
+  double *gt;              /* simple gate [n][c] */
+  double *m, *s;           /* image mean of gt, attention scale [B][c] */
+  double *t3, *y;          /* conv3 output, first residual [n][c] */
+  double *xh2, *r2;        /* layer norm 2: normalised y [n][c], 1 / sigma [n] */
+  double *e, *h, *t5, *z;  /* conv4 output [n][2c], its gate, conv5 output, block output [n][c] */
+  double *out;             /* sigmoid outputs [n][2] */
+} AdSaved;
+
+static void adsaved_free(AdSaved* S) {
+  free(S->xh1); free(S->r1); free(S->u); free(S->d); free(S->gt); free(S->m); free(S->s); free(S->t3); free(S->y);
+  free(S->xh2); free(S->r2); free(S->e); free(S->h); free(S->t5); free(S->z); free(S->out);
+}
+
+/* the tensors of one adapter's parameter (or gradient) slice */
+#define AD_OFFSETS(c)                                                                                          \
+  const long o_ln1w = 0, o_ln1b = (c), o_c1w = 2L * (c), o_c1b = o_c1w + 2L * (c) * (c), o_dww = o_c1b + 2L * (c), \
+             o_dwb = o_dww + 18L * (c), o_scaw = o_dwb + 2L * (c), o_scab = o_scaw + (long)(c) * (c),             \
+             o_c3w = o_scab + (c), o_c3b = o_c3w + (long)(c) * (c), o_beta = o_c3b + (c), o_ln2w = o_beta + (c),   \
+             o_ln2b = o_ln2w + (c), o_c4w = o_ln2b + (c), o_c4b = o_c4w + 2L * (c) * (c), o_c5w = o_c4b + 2L * (c), \
+             o_c5b = o_c5w + (long)(c) * (c), o_gamma = o_c5b + (c), o_hw = o_gamma + (c), o_hb = o_hw + 2L * (c)
+
+/* layer norm over c values with the normalised values and 1 / sigma kept */
+static void layer_norm_saved(const double* x, int c, const float* w, const float* b, double* xh, double* r,
+                             double* out) {
+  double mu = 0.0, var = 0.0;
+  for (int i = 0; i < c; ++i) mu += x[i];
+  mu /= c;
+  for (int i = 0; i < c; ++i) var += (x[i] - mu) * (x[i] - mu);
+  var /= c;
+  *r = 1.0 / sqrt(var + 1e-6);
+  for (int i = 0; i < c; ++i) {
+    xh[i] = (x[i] - mu) * *r;
+    out[i] = xh[i] * w[i] + b[i];
+  }
+}
+
+static void adapter_forward_saved(int c, const float* P, int B, int H, int W, const double* feat, AdSaved* S) {
+  AD_OFFSETS(c);
+  const size_t HW = (size_t)H * W, n = (size_t)B * HW;
+  S->xh1 = malloc(sizeof(double) * n * c); S->r1 = malloc(sizeof(double) * n);
+  S->u = malloc(sizeof(double) * n * 2 * c); S->d = malloc(sizeof(double) * n * 2 * c);
+  S->gt = malloc(sizeof(double) * n * c);
+  S->m = malloc(sizeof(double) * B * c); S->s = malloc(sizeof(double) * B * c);
+  S->t3 = malloc(sizeof(double) * n * c); S->y = malloc(sizeof(double) * n * c);
+  S->xh2 = malloc(sizeof(double) * n * c); S->r2 = malloc(sizeof(double) * n);
+  S->e = malloc(sizeof(double) * n * 2 * c); S->h = malloc(sizeof(double) * n * c);
+  S->t5 = malloc(sizeof(double) * n * c); S->z = malloc(sizeof(double) * n * c);
+  S->out = malloc(sizeof(double) * n * 2);
+  double* t = malloc(sizeof(double) * 2 * c);
+  double* a = malloc(sizeof(double) * c);
+  for (int b = 0; b < B; ++b) {
+    const size_t q0 = (size_t)b * HW;
+    for (size_t q = q0; q < q0 + HW; ++q) {
+      layer_norm_saved(feat + q * c, c, P + o_ln1w, P + o_ln1b, S->xh1 + q * c, S->r1 + q, t);
+      dense(t, c, 2 * c, P + o_c1w, P + o_c1b, S->u + q * 2 * c);
+    }
+    for (int y = 0; y < H; ++y)
+      for (int x = 0; x < W; ++x) {
+        const size_t q = q0 + (size_t)y * W + x;
+        for (int ch = 0; ch < 2 * c; ++ch) {
+          double sum = P[o_dwb + ch];
+          for (int dy = 0; dy < 3; ++dy)
+            for (int dx = 0; dx < 3; ++dx) {
+              const int yy = y + dy - 1, xx = x + dx - 1;
+              if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+              sum += (double)P[o_dww + ch * 9 + dy * 3 + dx] * S->u[(q0 + (size_t)yy * W + xx) * 2 * c + ch];
+            }
+          S->d[q * 2 * c + ch] = sum;
+        }
+        for (int ch = 0; ch < c; ++ch) S->gt[q * c + ch] = S->d[q * 2 * c + ch] * S->d[q * 2 * c + c + ch];
+      }
+    for (int ch = 0; ch < c; ++ch) {
+      double sum = 0.0;
+      for (size_t q = q0; q < q0 + HW; ++q) sum += S->gt[q * c + ch];
+      S->m[(size_t)b * c + ch] = sum / (double)HW;
+    }
+    dense(S->m + (size_t)b * c, c, c, P + o_scaw, P + o_scab, S->s + (size_t)b * c);
+    for (size_t q = q0; q < q0 + HW; ++q) {
+      for (int ch = 0; ch < c; ++ch) a[ch] = S->gt[q * c + ch] * S->s[(size_t)b * c + ch];
+      dense(a, c, c, P + o_c3w, P + o_c3b, S->t3 + q * c);
+      for (int ch = 0; ch < c; ++ch) S->y[q * c + ch] = feat[q * c + ch] + (double)P[o_beta + ch] * S->t3[q * c + ch];
+      layer_norm_saved(S->y + q * c, c, P + o_ln2w, P + o_ln2b, S->xh2 + q * c, S->r2 + q, t);
+      dense(t, c, 2 * c, P + o_c4w, P + o_c4b, S->e + q * 2 * c);
+      for (int ch = 0; ch < c; ++ch) S->h[q * c + ch] = S->e[q * 2 * c + ch] * S->e[q * 2 * c + c + ch];
+      dense(S->h + q * c, c, c, P + o_c5w, P + o_c5b, S->t5 + q * c);
+      for (int ch = 0; ch < c; ++ch) S->z[q * c + ch] = S->y[q * c + ch] + (double)P[o_gamma + ch] * S->t5[q * c + ch];
+      double zz[2];
+      dense(S->z + q * c, c, 2, P + o_hw, P + o_hb, zz);
+      for (int k = 0; k < 2; ++k) S->out[q * 2 + k] = 1.0 / (1.0 + exp(-zz[k]));
+    }
+  }
+  free(t); free(a);
+}
+
+/* dx += r (dxh - mean(dxh) - xh mean(dxh xh)) over c values */
+static void layer_norm_bwd(const double* xh, double r, const double* dxh, int c, double* dx) {
+  double m1 = 0.0, m2 = 0.0;
+  for (int i = 0; i < c; ++i) {
+    m1 += dxh[i];
+    m2 += dxh[i] * xh[i];
+  }
+  m1 /= c;
+  m2 /= c;
+  for (int i = 0; i < c; ++i) dx[i] += r * (dxh[i] - m1 - xh[i] * m2);
+}
+
+/* dout[n][2]: the loss gradient at this adapter's two sigmoid outputs.
+ * Adds the parameter gradient to G (this adapter's slice, laid out as P)
+ * and the gradient with respect to the features to dfeat[n][c]. */
+static void adapter_backward(int c, const float* P, int B, int H, int W, const AdSaved* S, const double* dout,
+                             double* G, double* dfeat) {
+  AD_OFFSETS(c);
+  const size_t HW = (size_t)H * W, n = (size_t)B * HW;
+  double* dgt = malloc(sizeof(double) * n * c);
+  double* du = calloc(n * 2 * c, sizeof(double));
+  double* ds = calloc((size_t)B * c, sizeof(double));
+  double *dz = malloc(sizeof(double) * c), *dy = malloc(sizeof(double) * c), *dt = malloc(sizeof(double) * c),
+         *dh = malloc(sizeof(double) * c), *de = malloc(sizeof(double) * 2 * c), *dxh = malloc(sizeof(double) * c),
+         *da = malloc(sizeof(double) * c);
+  for (size_t q = 0; q < n; ++q) {
+    const size_t b = q / HW;
+    const double *z = S->z + q * c, *t5 = S->t5 + q * c, *h = S->h + q * c, *e = S->e + q * 2 * c,
+                 *xh2 = S->xh2 + q * c, *t3 = S->t3 + q * c, *gt = S->gt + q * c, *sv = S->s + b * c;
+    /* sigmoid, then the head */
+    double dop[2];
+    for (int k = 0; k < 2; ++k) {
+      const double o = S->out[q * 2 + k];
+      dop[k] = dout[q * 2 + k] * o * (1.0 - o);
+      G[o_hb + k] += dop[k];
+      for (int ch = 0; ch < c; ++ch) G[o_hw + k * c + ch] += dop[k] * z[ch];
+    }
+    for (int ch = 0; ch < c; ++ch) dz[ch] = (double)P[o_hw + ch] * dop[0] + (double)P[o_hw + c + ch] * dop[1];
+    /* z = y + gamma t5 */
+    for (int ch = 0; ch < c; ++ch) {
+      G[o_gamma + ch] += dz[ch] * t5[ch];
+      dt[ch] = (double)P[o_gamma + ch] * dz[ch];
+      dy[ch] = dz[ch];
+    }
+    /* t5 = W5 h + b5 */
+    for (int o = 0; o < c; ++o) {
+      G[o_c5b + o] += dt[o];
+      for (int i = 0; i < c; ++i) G[o_c5w + (long)o * c + i] += dt[o] * h[i];
+    }
+    for (int i = 0; i < c; ++i) {
+      double sum = 0.0;
+      for (int o = 0; o < c; ++o) sum += (double)P[o_c5w + (long)o * c + i] * dt[o];
+      dh[i] = sum;
+    }
+    /* h = e[:c] e[c:] */
+    for (int i = 0; i < c; ++i) {
+      de[i] = dh[i] * e[c + i];
+      de[c + i] = dh[i] * e[i];
+    }
+    /* e = W4 n2 + b4, n2 = xh2 w2 + b2 */
+    for (int o = 0; o < 2 * c; ++o) {
+      G[o_c4b + o] += de[o];
+      for (int i = 0; i < c; ++i) G[o_c4w + (long)o * c + i] += de[o] * (xh2[i] * P[o_ln2w + i] + P[o_ln2b + i]);
+    }
+    for (int i = 0; i < c; ++i) {
+      double sum = 0.0;
+      for (int o = 0; o < 2 * c; ++o) sum += (double)P[o_c4w + (long)o * c + i] * de[o];
+      G[o_ln2w + i] += sum * xh2[i];
+      G[o_ln2b + i] += sum;
+      dxh[i] = sum * P[o_ln2w + i];
+    }
+    layer_norm_bwd(xh2, S->r2[q], dxh, c, dy);
+    /* y = feat + beta t3 */
+    for (int ch = 0; ch < c; ++ch) {
+      dfeat[q * c + ch] += dy[ch];
+      G[o_beta + ch] += dy[ch] * t3[ch];
+      dt[ch] = (double)P[o_beta + ch] * dy[ch];
+    }
+    /* t3 = W3 a + b3, a = gt s */
+    for (int o = 0; o < c; ++o) {
+      G[o_c3b + o] += dt[o];
+      for (int i = 0; i < c; ++i) G[o_c3w + (long)o * c + i] += dt[o] * (gt[i] * sv[i]);
+    }
+    for (int i = 0; i < c; ++i) {
+      double sum = 0.0;
+      for (int o = 0; o < c; ++o) sum += (double)P[o_c3w + (long)o * c + i] * dt[o];
+      da[i] = sum;
+      dgt[q * c + i] = sum * sv[i];
+      ds[b * c + i] += sum * gt[i];
+    }
+  }
+  /* s = Wsca m + bsca, m = mean of gt over the image */
+  for (int b = 0; b < B; ++b) {
+    const double *dsb = ds + (size_t)b * c, *mb = S->m + (size_t)b * c;
+    for (int o = 0; o < c; ++o) {
+      G[o_scab + o] += dsb[o];
+      for (int i = 0; i < c; ++i) G[o_scaw + (long)o * c + i] += dsb[o] * mb[i];
+    }
+    for (int i = 0; i < c; ++i) {
+      double sum = 0.0;
+      for (int o = 0; o < c; ++o) sum += (double)P[o_scaw + (long)o * c + i] * dsb[o];
+      da[i] = sum / (double)HW;
+    }
+    for (size_t q = (size_t)b * HW; q < (size_t)(b + 1) * HW; ++q)
+      for (int i = 0; i < c; ++i) dgt[q * c + i] += da[i];
+  }
+  /* gt = d[:c] d[c:]; d = depthwise(u) + dwb (zero padded) */
+  for (int b = 0; b < B; ++b) {
+    const size_t q0 = (size_t)b * HW;
+    for (int y = 0; y < H; ++y)
+      for (int x = 0; x < W; ++x) {
+        const size_t q = q0 + (size_t)y * W + x;
+        for (int ch = 0; ch < 2 * c; ++ch) {
+          const int i = ch < c ? ch : ch - c;
+          const double g = dgt[q * c + i] * S->d[q * 2 * c + (ch < c ? c + i : i)];
+          G[o_dwb + ch] += g;
+          for (int dy = 0; dy < 3; ++dy)
+            for (int dx = 0; dx < 3; ++dx) {
+              const int yy = y + dy - 1, xx = x + dx - 1;
+              if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+              const size_t nb = (q0 + (size_t)yy * W + xx) * 2 * c + ch;
+              G[o_dww + ch * 9 + dy * 3 + dx] += g * S->u[nb];
+              du[nb] += (double)P[o_dww + ch * 9 + dy * 3 + dx] * g;
+            }
+        }
+      }
+  }
+  /* u = W1 n1 + b1, n1 = xh1 w1 + b1 */
+  for (size_t q = 0; q < n; ++q) {
+    const double* xh1 = S->xh1 + q * c;
+    const double* duq = du + q * 2 * c;
+    for (int o = 0; o < 2 * c; ++o) {
+      G[o_c1b + o] += duq[o];
+      for (int i = 0; i < c; ++i) G[o_c1w + (long)o * c + i] += duq[o] * (xh1[i] * P[o_ln1w + i] + P[o_ln1b + i]);
+    }
+    for (int i = 0; i < c; ++i) {
+      double sum = 0.0;
+      for (int o = 0; o < 2 * c; ++o) sum += (double)P[o_c1w + (long)o * c + i] * duq[o];
+      G[o_ln1w + i] += sum * xh1[i];
+      G[o_ln1b + i] += sum;
+      dxh[i] = sum * P[o_ln1w + i];
+    }
+    layer_norm_bwd(xh1, S->r1[q], dxh, c, dfeat + q * c);
+  }
+  free(dgt); free(du); free(ds); free(dz); free(dy); free(dt); free(dh); free(de); free(dxh); free(da);
+}
+
+/* The network with the four adapters in place of its plain head, trained
+ * jointly: lightmaps from the adapters (groups 0-2; group 3's alpha and
+ * emissive have no target here and take no gradient), loss = mean squared
+ * error over B*H*W*6 against target_srgb[B][H][W][6] as orc_unet_loss_grad,
+ * and its gradient with respect to the trunk's parameters (grad[n_params];
+ * the unused head's entries are 0) and the adapters' (grad_ad[n_ad]). */
+ORC_EXPORT int orc_adapters_loss_grad(int levels, int base, const float* params, long n_params,
+                                      const float* ad_params, long n_ad, int B, int H, int W, const double* guide,
+                                      const double* target, double* loss, double* grad, double* grad_ad) {
+  Net net;
+  int st = net_setup(levels, base, params, n_params, &net);
+  if (st) return st;
+  const int c = base;
+  if (c > 512 || n_ad != orc_adapter_param_count(c)) return 1;
+  int div = 1 << (levels - 1);
+  if (B < 1 || H < 1 || W < 1 || H % div || W % div) return 3;
+  static const int dst[4][2] = {{4, 5}, {0, 1}, {2, 3}, {-1, -2}};
+  const long per = 7L * c * c + 35L * c + 2;
+  const size_t HW = (size_t)H * W, n = (size_t)B * HW;
+  Fwd f;
+  unet_forward_saved(&net, B, H, W, guide, &f);
+  double* feat = malloc(sizeof(double) * n * c);
+  nchw_to_nhwc(f.x_in[net.n - 1], B, c, H, W, feat);
+  AdSaved S[4];
+  for (int g = 0; g < 4; ++g) adapter_forward_saved(c, ad_params + g * per, B, H, W, feat, &S[g]);
+  const double inv = 1.0 / (double)(n * 6);
+  double l = 0.0;
+  double* dout = malloc(sizeof(double) * n * 2);
+  double* dfeat = calloc(n * c, sizeof(double));
+  memset(grad, 0, sizeof(double) * (size_t)net.n_params);
+  memset(grad_ad, 0, sizeof(double) * (size_t)n_ad);
+  for (int g = 0; g < 4; ++g) {
+    for (size_t q = 0; q < n; ++q)
+      for (int k = 0; k < 2; ++k) {
+        dout[q * 2 + k] = 0.0;
+        if (dst[g][k] < 0) continue;
+        const double e = S[g].out[q * 2 + k] - target[q * 6 + dst[g][k]];
+        l += e * e;
+        dout[q * 2 + k] = 2.0 * e * inv;
+      }
+    adapter_backward(c, ad_params + g * per, B, H, W, &S[g], dout, grad_ad + g * per, dfeat);
+  }
+  *loss = l * inv;
+  /* the trunk, from the features' gradient (to NCHW) */
+  double* gf = malloc(sizeof(double) * n * c);
+  for (int b = 0; b < B; ++b)
+    for (int ch = 0; ch < c; ++ch)
+      for (size_t q = 0; q < HW; ++q) gf[((size_t)b * c + ch) * HW + q] = dfeat[((size_t)b * HW + q) * c + ch];
+  trunk_backward(&net, &f, B, gf, grad);
+  for (int g = 0; g < 4; ++g) adsaved_free(&S[g]);
+  free(feat); free(dout); free(dfeat);
+  fwd_free(&f, net.n);
   return 0;
 }
 

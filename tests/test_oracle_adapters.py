@@ -1,7 +1,10 @@
 """Pins of the oracle's channel adapters (Section 4.3: four NAFBlock adapters
 on the decoder output, one per output group) against torch CPU float64
 library routines, the identity initialisation of the block, per-image
-pooling and the group-to-channel routing.  CPU only."""
+pooling and the group-to-channel routing; and of their training gradient
+(orc_adapters_loss_grad: the network with the adapters in place of its
+head) against torch float64 autograd, central differences and the zeros
+the identity initialisation and the target-less group force.  CPU only."""
 import numpy as np
 import torch
 import torch.nn.functional as F
@@ -138,3 +141,110 @@ def test_unet_features_are_the_head_input(orc):
     hb = params[-6:].astype(np.float64)
     np.testing.assert_allclose(feat @ hw.T + hb, logits, rtol=1e-12, atol=1e-13)
     assert feat.min() >= 0.0 and unet_layers(levels, base)[-1][1] == base
+
+
+def _torch_joint_loss(params, levels, base, ad_params, guide, target):
+    """Loss of the network with the adapters in place of its head, and
+    torch autograd's gradients of both parameter vectors."""
+    from tests.test_oracle_unet import torch_unet
+
+    p = torch.tensor(np.asarray(params, np.float64), requires_grad=True)
+    a = torch.tensor(np.asarray(ad_params, np.float64), requires_grad=True)
+    x = torch_unet(p, levels, base, torch.as_tensor(guide), features=True)
+    c = base
+    outs = []
+    off = 0
+    for _ in range(4):
+        d = {}
+        for name, shape, _ in adapter_tensors(c):
+            n = int(np.prod(shape))
+            d[name] = a[off: off + n].reshape(shape)
+            off += n
+        outs.append(torch_adapter(d, x).permute(0, 2, 3, 1))
+    lm = torch.cat([outs[1], outs[2], outs[0]], dim=-1)
+    loss = torch.mean((lm - torch.as_tensor(target)) ** 2)
+    loss.backward()
+    return loss.item(), p.grad.numpy(), a.grad.numpy()
+
+
+def test_joint_gradient_matches_torch_autograd(orc):
+    levels, base, B, H, W = 2, 4, 2, 6, 4
+    rng = np.random.default_rng(11)
+    params = he_normal_params(levels, base, seed=11, bias="uniform")
+    ad = adapter_params(base, seed=12)
+    guide = rng.random((B, H, W, 3))
+    target = rng.random((B, H, W, 6))
+    loss, g, ga = orc.adapters_loss_grad(params, levels, base, ad, guide, target)
+    tl, tg, tga = _torch_joint_loss(params, levels, base, ad, guide, target)
+    assert abs(loss - tl) <= 1e-13 * max(1.0, abs(tl))
+    np.testing.assert_allclose(g, tg, rtol=1e-9, atol=1e-13)
+    np.testing.assert_allclose(ga, tga, rtol=1e-9, atol=1e-13)
+    assert np.abs(ga).max() > 1e-4 and np.abs(g).max() > 1e-4
+
+
+def test_joint_gradient_central_differences(orc):
+    """A few entries of each adapter tensor and of the trunk against central
+    differences of the oracle's own loss (fp64 on fp32-rounded parameters:
+    the step moves a parameter by a representable amount)."""
+    levels, base, B, H, W = 2, 4, 1, 4, 6
+    rng = np.random.default_rng(13)
+    params = he_normal_params(levels, base, seed=13, bias="uniform").astype(np.float32)
+    ad = adapter_params(base, seed=14).astype(np.float32)
+    guide = rng.random((B, H, W, 3))
+    target = rng.random((B, H, W, 6))
+    _, g, ga = orc.adapters_loss_grad(params, levels, base, ad, guide, target)
+    h = np.float32(2.0 ** -10)
+    per = len(ad) // 4
+    off = 0
+    picks = []
+    for name, shape, _ in adapter_tensors(base):
+        n = int(np.prod(shape))
+        picks.append(off + n // 2)  # one entry of each tensor of group 1
+        off += n
+    for i in [per + k for k in picks]:
+        up, dn = ad.copy(), ad.copy()
+        up[i] += h
+        dn[i] -= h
+        lu = orc.adapters_loss_grad(params, levels, base, up, guide, target)[0]
+        ld = orc.adapters_loss_grad(params, levels, base, dn, guide, target)[0]
+        fd = (lu - ld) / (float(up[i]) - float(dn[i]))
+        assert abs(fd - ga[i]) <= 2e-4 * max(abs(fd), 1e-3), (i, fd, ga[i])
+    for i in (0, len(params) // 3, len(params) - 7 * base - 20):
+        up, dn = params.copy(), params.copy()
+        up[i] += h
+        dn[i] -= h
+        lu = orc.adapters_loss_grad(up, levels, base, ad, guide, target)[0]
+        ld = orc.adapters_loss_grad(dn, levels, base, ad, guide, target)[0]
+        fd = (lu - ld) / (float(up[i]) - float(dn[i]))
+        assert abs(fd - g[i]) <= 2e-4 * max(abs(fd), 1e-3), (i, fd, g[i])
+
+
+def test_joint_gradient_structural_zeros(orc):
+    """The alpha/emissive group has no target, so its slice takes no
+    gradient, and the unused plain head neither; with the identity
+    initialisation (beta = gamma = 0) no gradient reaches the block's inner
+    layers, while beta and gamma themselves do get one."""
+    levels, base, B, H, W = 2, 4, 1, 4, 4
+    rng = np.random.default_rng(15)
+    params = he_normal_params(levels, base, seed=15, bias="uniform")
+    guide = rng.random((B, H, W, 3))
+    target = rng.random((B, H, W, 6))
+    per = 7 * base * base + 35 * base + 2
+    for init in ("random", "identity"):
+        ad = adapter_params(base, seed=16, init=init)
+        _, g, ga = orc.adapters_loss_grad(params, levels, base, ad, guide, target)
+        assert np.all(ga[3 * per:] == 0.0)
+        assert np.all(g[-(6 * base + 6):] == 0.0)
+    off, spans = 0, {}
+    for name, shape, _ in adapter_tensors(base):
+        n = int(np.prod(shape))
+        spans[name] = (off, off + n)
+        off += n
+    for grp in range(3):
+        for name in ("ln1_w", "ln1_b", "conv1_w", "conv1_b", "dw_w", "dw_b", "sca_w", "sca_b", "conv3_w", "conv3_b",
+                     "ln2_w", "ln2_b", "conv4_w", "conv4_b", "conv5_w", "conv5_b"):
+            lo, hi = spans[name]
+            assert np.all(ga[grp * per + lo: grp * per + hi] == 0.0), (grp, name)
+        for name in ("beta", "gamma", "head_w", "head_b"):
+            lo, hi = spans[name]
+            assert np.abs(ga[grp * per + lo: grp * per + hi]).max() > 0.0, (grp, name)

@@ -9,8 +9,9 @@ import torch.nn.functional as F
 from synth.weights import he_normal_params, n_params, unet_layers
 
 
-def torch_unet(params, levels, base, guide_bhwc):
-    """The same network built from torch.nn.functional float64 CPU ops."""
+def torch_unet(params, levels, base, guide_bhwc, features=False):
+    """The same network built from torch.nn.functional float64 CPU ops
+    (features=True: the decoder output, the head's input, NCHW)."""
     p = params if isinstance(params, torch.Tensor) else torch.as_tensor(np.asarray(params, np.float64))
     layers = unet_layers(levels, base)
     ws, off = [], 0
@@ -39,6 +40,8 @@ def torch_unet(params, levels, base, guide_bhwc):
         x = torch.cat([skips[l], F.interpolate(x, scale_factor=2, mode="nearest")], dim=1)
         x = F.relu(conv(x))
         x = F.relu(conv(x))
+    if features:
+        return x
     z = conv(x)
     return torch.sigmoid(z).permute(0, 2, 3, 1), z.permute(0, 2, 3, 1)
 
@@ -172,3 +175,19 @@ def test_adam_matches_torch(orc):
         tp.grad = torch.tensor(g)
         opt.step()
         np.testing.assert_allclose(p, tp.detach().numpy(), rtol=1e-12, atol=1e-15)
+
+
+def test_window_interior_is_border_free(orc):
+    """Locality of the 4-level network (two 3x3 convolutions per level, 2x2
+    max-pools, nearest upsampling): on a window whose offset is a multiple
+    of 8, the outputs 48 or more pixels inside it equal the whole image's
+    (the GPU comparison at 1024x1024 relies on this, with a 64-pixel margin);
+    with a 24-pixel margin they do not."""
+    p = he_normal_params(4, 8, seed=3, bias="uniform")
+    g = np.random.default_rng(5).random((1, 256, 256, 3))
+    full, _ = orc.unet_forward(p, 4, 8, g)
+    y0, x0, C = 48, 64, 160
+    win, _ = orc.unet_forward(p, 4, 8, g[:, y0:y0 + C, x0:x0 + C])
+    d = np.abs(win[0] - full[0, y0:y0 + C, x0:x0 + C])
+    assert d[48:C - 48, 48:C - 48].max() == 0.0
+    assert d[24:C - 24, 24:C - 24].max() > 1e-6
