@@ -53,8 +53,12 @@ typedef enum { LNM_LIGHTS_TOP_BOTTOM = 0, LNM_LIGHTS_LEFT_RIGHT = 1 } lnm_light_
  * order.  LNM_ORDER_BANDS: screen bands (best when the bricked grid fits the
  * XCDs' L2 caches); LNM_ORDER_Z: the samples sorted by brick layer first
  * (best for large grids, one more kernel and a larger workspace);
- * LNM_ORDER_AUTO: z order when the bricked grid exceeds 32 MiB. */
-typedef enum { LNM_ORDER_AUTO = 0, LNM_ORDER_BANDS = 1, LNM_ORDER_Z = 2 } lnm_work_order;
+ * LNM_ORDER_CELLS: the samples sorted by the grid cell of their z, each
+ * workgroup reading the two grid planes of its cell from LDS (grids with
+ * (nx + 2)(ny + 2) <= 19968 and nz < 256; LNM_ERR_UNSUPPORTED otherwise);
+ * LNM_ORDER_AUTO: z order when the bricked grid exceeds 32 MiB, else cells
+ * for the top/bottom lights when they fit, else bands. */
+typedef enum { LNM_ORDER_AUTO = 0, LNM_ORDER_BANDS = 1, LNM_ORDER_Z = 2, LNM_ORDER_CELLS = 3 } lnm_work_order;
 
 typedef struct lnm_ctx_s* lnm_ctx; /* per-device state: properties, error text */
 typedef struct lnm_net_s* lnm_net; /* host descriptor of a packed network */
@@ -222,7 +226,8 @@ LNM_API size_t lnm_net_device_bytes(int32_t levels, int32_t base, int32_t precis
  * and activations rounded to nearest even, fp32 accumulation, bias and ReLU
  * on the fp32 accumulator, fp32 head), LNM_FP8_E4M3 (OCP e4m3 weights with
  * one scale per output channel, max|W[o]|/448; activations stored as e4m3
- * with one scale per tensor, amax/448, the two inputs of each decoder
+ * with one scale per tensor, 4 amax/448 (headroom for inputs beyond the
+ * calibrated maxima), the two inputs of each decoder
  * concatenation sharing the larger; fp32 accumulation; the 3-channel input
  * layer and the last 3x3 layer, whose features the head reads, in bf16, the
  * layer before that storing bf16 for it).  Other values:
@@ -284,7 +289,7 @@ LNM_API size_t lnm_frame_workspace_bytes(lnm_net net, const lnm_volume* vol, con
  * calls no allocating routine.  The caller still provides guide, lightmaps
  * and rgba (rgba may be NULL) as for lnm_frame.  A frame whose
  * lnm_frame_workspace_bytes exceeds LNM_STATIC_SCRATCH_BYTES (the 128^3 grid
- * at 256 x 256 takes about 120 MiB) returns LNM_ERR_SHAPE with nothing
+ * at 256 x 256 takes about 123 MiB) returns LNM_ERR_SHAPE with nothing
  * enqueued.  All calls on one device share its one workspace: calls that
  * may overlap on a device (other streams, other threads, other contexts)
  * race and must be serialised by the caller.  Nothing needs clearing between

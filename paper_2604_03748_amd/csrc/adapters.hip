@@ -1,30 +1,42 @@
 // Channel adapters on the U-Net decoder output (Section 4.3): four NAFBlocks
 // (Chen et al. 2022), one per output group (front/back, left/right,
 // up/down, alpha/emissive), each followed by a 1x1 head to its two channels
-// and a sigmoid.  fp32 arithmetic.
+// and a sigmoid.  fp32 arithmetic; the 1x1 convolutions run on the fp32
+// matrix cores (v_mfma_f32_16x16x4_f32).
 //
-// Four kernels, because the block's channel attention needs the mean of the
-// gated features over the whole image between its two halves:
-//   adapt_expand    lane per pixel: layer norm 1, 1x1 conv c -> 2c for all
-//                   four groups -> u[g][2c][P] (channel planes, so lanes write
-//                   coalesced rows);
-//   adapt_dw_gate   lane per (pixel, group, channel pair): 3x3 depthwise conv
-//                   of channels ch and ch + c, their product -> v[g][c][P],
-//                   and per 256-pixel block partial sums for the attention;
-//   adapt_attend    workgroup per (image, group): the image mean of v (partial
-//                   sums added in a fixed order) and the attention's 1x1 conv
-//                   -> s[b][g][c];
-//   adapt_out       lane per pixel, one group at a time: v * s, 1x1 conv,
-//                   residual with beta, layer norm 2, 1x1 c -> 2c, gate,
-//                   1x1 c -> c, residual with gamma, head, sigmoid.
-// Weights are staged in LDS and read as broadcasts; every lane keeps its
-// pixel's channels in registers (c is a template parameter).
+// Every 1x1 convolution is computed transposed, out[channel][pixel] =
+// W[channel][:] x[:][pixel]: channels are the MFMA rows and 16 pixels its
+// columns.  A lane then holds four consecutive channels (16 mb + 4 (lane /
+// 16) + r, r < 4, of each 16-channel block mb) of one pixel (lane % 16).
+// That is the operand layout the next product reads when its K step (kb, r)
+// takes input channel 16 kb + 4 (lane / 16) + r in both operands, so a chain
+// of 1x1 convolutions stays in registers.  Per-pixel reductions over the
+// channels (the layer norms, the head) add a lane's own channels and then
+// the four lanes of the pixel (shuffles across 16 and 32 lanes).
+//
+// Three kernels, because the block's channel attention needs the mean of
+// the gated features over the whole image between its two halves:
+//   adapt_front  workgroup per (8 x 32 pixel tile, group, image): layer norm
+//                1 and the 1x1 conv c -> 2c on the tile and a one-pixel halo
+//                (recomputed, so the 2c-channel tensor never goes to
+//                memory), 32 of the 2c channels at a time into LDS; then the
+//                3x3 depthwise conv and the gate of those 16 channel pairs ->
+//                v[g][P][c], and the tile's sum of v per channel;
+//   adapt_attend workgroup per (group, image): the image mean of v (tile
+//                sums added in a fixed order) and the attention's 1x1 conv
+//                -> s[b][g][c];
+//   adapt_tail   workgroup per (256 pixels, group): v * s, 1x1 conv c -> c,
+//                residual with beta, layer norm 2, 1x1 c -> 2c, gate, 1x1
+//                c -> c, residual with gamma, head, sigmoid; the three
+//                weight matrices staged in LDS.
 #include <cmath>
 
 #include "internal.h"
 
 namespace lnm {
 namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 // offsets of one adapter's tensors (parameter-file order) for width C
 template <int C>
@@ -37,157 +49,190 @@ struct Off {
 
 __device__ __forceinline__ float bf16f(uint32_t h) { return __uint_as_float(h << 16); }
 
-// feature channel i of pixel p as fp32 (IN: 0 fp32, 1 bf16, 2 e4m3 x scale)
-template <int C, int IN>
-__device__ __forceinline__ void load_feat(const AdapterArgs& a, size_t p, float (&x)[C]) {
-  if constexpr (IN == 0) {
-    const float4* s = reinterpret_cast<const float4*>(static_cast<const float*>(a.feat) + p * C);
-#pragma unroll
-    for (int i = 0; i < C / 4; ++i) {
-      const float4 v = s[i];
-      x[4 * i] = v.x;
-      x[4 * i + 1] = v.y;
-      x[4 * i + 2] = v.z;
-      x[4 * i + 3] = v.w;
-    }
-  } else if constexpr (IN == 1) {
-    const uint2* s = reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(a.feat) + p * C);
-#pragma unroll
-    for (int i = 0; i < C / 4; ++i) {
-      const uint2 q = s[i];
-      x[4 * i] = bf16f(q.x & 0xffffu);
-      x[4 * i + 1] = bf16f(q.x >> 16);
-      x[4 * i + 2] = bf16f(q.y & 0xffffu);
-      x[4 * i + 3] = bf16f(q.y >> 16);
-    }
-  } else {
-    const int* s = reinterpret_cast<const int*>(static_cast<const uint8_t*>(a.feat) + p * C);
-#pragma unroll
-    for (int i = 0; i < C / 4; ++i) {
-      const int q = s[i];
-      x[4 * i] = __builtin_amdgcn_cvt_f32_fp8(q, 0) * a.feat_scale;
-      x[4 * i + 1] = __builtin_amdgcn_cvt_f32_fp8(q, 1) * a.feat_scale;
-      x[4 * i + 2] = __builtin_amdgcn_cvt_f32_fp8(q, 2) * a.feat_scale;
-      x[4 * i + 3] = __builtin_amdgcn_cvt_f32_fp8(q, 3) * a.feat_scale;
-    }
-  }
+// four floats from global memory (a group's parameters start 4-byte aligned)
+__device__ __forceinline__ f4 ld4(const float* p) { return f4{p[0], p[1], p[2], p[3]}; }
+
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// the same into the LDS column [channel][lane]
-template <int C, int IN, int T>
-__device__ __forceinline__ void load_feat(const AdapterArgs& a, size_t p, float (&col)[C][T], int lane) {
-  float x[C];
-  load_feat<C, IN>(a, p, x);
-#pragma unroll
-  for (int i = 0; i < C; ++i) col[i][lane] = x[i];
-}
-
-// (x - mean) / sqrt(var + 1e-6) over the C channels, biased variance
-template <int C>
-__device__ __forceinline__ void normalise(float (&x)[C]) {
-  float mu = 0.0f;
-#pragma unroll
-  for (int i = 0; i < C; ++i) mu += x[i];
-  mu *= 1.0f / (float)C;
-  float var = 0.0f;
-#pragma unroll
-  for (int i = 0; i < C; ++i) {
-    x[i] -= mu;
-    var += x[i] * x[i];
-  }
-  const float r = 1.0f / sqrtf(var * (1.0f / (float)C) + 1e-6f);
-#pragma unroll
-  for (int i = 0; i < C; ++i) x[i] *= r;
-}
-
-// out = b + W x for one output row o: W row-major [o][C] in LDS
-template <int C>
-__device__ __forceinline__ float row_dot(const float* __restrict__ w, float b, const float (&x)[C]) {
-  float s = b;
-#pragma unroll
-  for (int i = 0; i < C; i += 4) {
-    const float4 q = *reinterpret_cast<const float4*>(w + i);
-    s += q.x * x[i] + q.y * x[i + 1] + q.z * x[i + 2] + q.w * x[i + 3];
-  }
+// sum over the four lanes holding one pixel's channels (every lane of the
+// four gets the same value: the two additions are commutative pairings)
+__device__ __forceinline__ float pixel_sum(float s) {
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
   return s;
 }
 
+__device__ __forceinline__ float hsum(f4 v) { return (v.x + v.y) + (v.z + v.w); }
+
+// channels c0 .. c0 + 3 of feature pixel p as fp32 (IN: 0 fp32, 1 bf16,
+// 2 e4m3 x scale); c0 is a multiple of 4
 template <int C, int IN>
-__global__ __launch_bounds__(256) void adapt_expand(AdapterArgs a) {
-  using O = Off<C>;
-  __shared__ __attribute__((aligned(16))) float sw[2 * C * C + 4 * C];  // conv1 W, conv1 b, ln1 w, ln1 b
-  const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
-  const bool live = p < a.P;
-  float xh[C], t[C];
-  if (live) {
-    load_feat<C, IN>(a, p, xh);
-    normalise<C>(xh);
-  }
-#pragma unroll 1
-  for (int g = 0; g < 4; ++g) {
-    const float* P = a.prm + (size_t)g * O::total;
-    __syncthreads();
-    for (int q = threadIdx.x; q < 2 * C * C; q += 256) sw[q] = P[O::c1w + q];
-    for (int q = threadIdx.x; q < 2 * C; q += 256) sw[2 * C * C + q] = P[O::c1b + q];
-    for (int q = threadIdx.x; q < C; q += 256) {
-      sw[2 * C * C + 2 * C + q] = P[O::ln1w + q];
-      sw[2 * C * C + 3 * C + q] = P[O::ln1b + q];
-    }
-    __syncthreads();
-    if (!live) continue;
-#pragma unroll
-    for (int i = 0; i < C; ++i) t[i] = xh[i] * sw[2 * C * C + 2 * C + i] + sw[2 * C * C + 3 * C + i];
-    float* u = a.u + (size_t)g * 2 * C * a.P + p;
-#pragma unroll 4
-    for (int o = 0; o < 2 * C; ++o) u[(size_t)o * a.P] = row_dot<C>(sw + o * C, sw[2 * C * C + o], t);
+__device__ __forceinline__ f4 feat4(const AdapterArgs& a, size_t p, int c0) {
+  if constexpr (IN == 0) {
+    return *reinterpret_cast<const f4*>(static_cast<const float*>(a.feat) + p * C + c0);
+  } else if constexpr (IN == 1) {
+    const uint2 q = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(a.feat) + p * C + c0);
+    return f4{bf16f(q.x & 0xffffu), bf16f(q.x >> 16), bf16f(q.y & 0xffffu), bf16f(q.y >> 16)};
+  } else {
+    const int q = *reinterpret_cast<const int*>(static_cast<const uint8_t*>(a.feat) + p * C + c0);
+    return f4{__builtin_amdgcn_cvt_f32_fp8(q, 0), __builtin_amdgcn_cvt_f32_fp8(q, 1),
+              __builtin_amdgcn_cvt_f32_fp8(q, 2), __builtin_amdgcn_cvt_f32_fp8(q, 3)} *
+           a.feat_scale;
   }
 }
 
-// grid: (ceil(HW / 256), 4 C, B); block (bx, g * C + ch, b)
-template <int C>
-__global__ __launch_bounds__(256) void adapt_dw_gate(AdapterArgs a) {
+// front tile: kAdaptTileY x kAdaptTileX (8 x 32) interior pixels and a
+// one-pixel halo around them (10 x 34 = 340 pixels, 22 MFMA column blocks of
+// 16), 32 conv1 channels per pass in LDS at 36 floats per halo pixel (the
+// pad keeps the 16-byte accesses of neighbouring pixels on distinct banks)
+constexpr int kTY = kAdaptTileY, kTX = kAdaptTileX;
+constexpr int kHX = kTX + 2, kHalo = (kTY + 2) * kHX;
+constexpr int kHaloCols = (kHalo + 15) / 16;
+constexpr int kUPitch = 36;
+static_assert(kTY == 8 && kTX == 32, "the depthwise stage maps 256 threads onto 8 x 32 pixels x 4 channel quads");
+
+template <int C, int IN>
+__global__ __launch_bounds__(256) void adapt_front(AdapterArgs a) {
   using O = Off<C>;
-  __shared__ float red[4];
-  const int HW = a.H * a.W;
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  const int g = blockIdx.y / C, ch = blockIdx.y - g * C, b = blockIdx.z;
+  constexpr int KB = C / 16;
+  __shared__ __attribute__((aligned(16))) float us[kHaloCols * 16 * kUPitch];
+  __shared__ __attribute__((aligned(16))) float wdw[2][9][16];  // the pass's depthwise taps [half][tap][channel]
+  __shared__ f4 red[256];
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, G = lane >> 4, wave = tid >> 6;
+  const int g = blockIdx.y, b = blockIdx.z;
+  const int tiles_x = (a.W + kTX - 1) / kTX;
+  const int ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
+  const int y0 = ty * kTY, x0 = tx * kTX;
   const float* P = a.prm + (size_t)g * O::total;
-  float v = 0.0f;
-  if (q < HW) {
-    const int y = q / a.W, x = q - y * a.W;
-    const size_t base = (size_t)b * HW;
-    const float* u1 = a.u + ((size_t)g * 2 * C + ch) * a.P + base;
-    const float* u2 = u1 + (size_t)C * a.P;
-    float s1 = P[O::dwb + ch], s2 = P[O::dwb + C + ch];
+  const size_t img = (size_t)b * a.H * a.W;
+  // layer norm 1 weight and bias of this lane's channels 16 kb + 4 G + r
+  f4 lw[KB], lb[KB];
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy) {
-      const int yy = y + dy - 1;
-      if (yy < 0 || yy >= a.H) continue;
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const int xx = x + dx - 1;
-        if (xx < 0 || xx >= a.W) continue;
-        const int nb = yy * a.W + xx;
-        s1 += P[O::dww + ch * 9 + dy * 3 + dx] * u1[nb];
-        s2 += P[O::dww + (C + ch) * 9 + dy * 3 + dx] * u2[nb];
-      }
-    }
-    v = s1 * s2;
-    a.v[((size_t)g * C + ch) * a.P + base + q] = v;
+  for (int kb = 0; kb < KB; ++kb) {
+    lw[kb] = ld4(P + O::ln1w + 16 * kb + 4 * G);
+    lb[kb] = ld4(P + O::ln1b + 16 * kb + 4 * G);
   }
-  // block sum of v in a fixed order: a butterfly within each wavefront, then
-  // the four wavefront sums in order
+  // depthwise stage: thread (quad qd, column xc, half hh) takes interior rows
+  // 4 hh .. 4 hh + 3 of column xc and gate channels 16 j + 4 qd + (0..3)
+  const int qd = tid & 3, xc = (tid >> 2) & 31, hh = tid >> 7;
+
+#pragma unroll 1
+  for (int j = 0; j < KB; ++j) {
+    // the pass's conv1 rows: block 0 = channels 16 j + i, block 1 = C + 16 j + i
+    f4 wa[2][KB];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    a.part[(((size_t)b * 4 + g) * C + ch) * a.n_blk + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) wa[m][kb] = ld4(P + O::c1w + (size_t)(m * C + 16 * j + li) * C + 16 * kb + 4 * G);
+    const f4 bias0 = ld4(P + O::c1b + 16 * j + 4 * G), bias1 = ld4(P + O::c1b + C + 16 * j + 4 * G);
+    for (int q = tid; q < 2 * 9 * 16; q += 256) {
+      const int h = q / 144, t = (q / 16) % 9, c = q % 16;
+      wdw[h][t][c] = P[O::dww + (h * C + 16 * j + c) * 9 + t];
+    }
+#pragma unroll 1
+    for (int nb = wave; nb < kHaloCols; nb += 4) {  // uniform per wavefront: the MFMAs see every lane
+      const int hp = nb * 16 + li;
+      const int hy = hp / kHX, hx = hp - hy * kHX;
+      const int y = y0 + hy - 1, x = x0 + hx - 1;
+      const bool in = hp < kHalo && y >= 0 && y < a.H && x >= 0 && x < a.W;
+      const size_t p = img + (size_t)min(max(y, 0), a.H - 1) * a.W + min(max(x, 0), a.W - 1);
+      f4 xv[KB];
+      float s = 0.0f;
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        xv[kb] = feat4<C, IN>(a, p, 16 * kb + 4 * G);
+        s += hsum(xv[kb]);
+      }
+      const float mu = pixel_sum(s) * (1.0f / (float)C);
+      float sq = 0.0f;
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        xv[kb] -= mu;
+        sq += hsum(xv[kb] * xv[kb]);
+      }
+      const float rs = 1.0f / sqrtf(pixel_sum(sq) * (1.0f / (float)C) + 1e-6f);
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) xv[kb] = xv[kb] * rs * lw[kb] + lb[kb];
+      f4 acc0 = bias0, acc1 = bias1;
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          acc0 = mfma(wa[0][kb][r], xv[kb][r], acc0);
+          acc1 = mfma(wa[1][kb][r], xv[kb][r], acc1);
+        }
+      // the depthwise conv pads its input with zeros outside the image
+      const f4 zero = f4{0.0f, 0.0f, 0.0f, 0.0f};
+      float* dst = us + hp * kUPitch + 4 * G;
+      *reinterpret_cast<f4*>(dst) = in ? acc0 : zero;
+      *reinterpret_cast<f4*>(dst + 16) = in ? acc1 : zero;
+    }
+    __syncthreads();
+    {
+      const int ch = 16 * j + 4 * qd;
+      const f4 d1 = ld4(P + O::dwb + ch), d2 = ld4(P + O::dwb + C + ch);
+      f4 s1[4], s2[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        s1[i] = d1;
+        s2[i] = d2;
+      }
+      // halo rows 4 hh + hr feed interior rows 4 hh + i at tap row hr - i
+      // (a loop, not unrolled: unrolled, the compiler hoists all 36 LDS
+      // loads and the kernel runs one wavefront per SIMD)
+#pragma unroll 1
+      for (int hr = 0; hr < 6; ++hr) {
+        f4 ua[3], ub[3];
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+          const float* src = us + ((4 * hh + hr) * kHX + xc + dx) * kUPitch + 4 * qd;
+          ua[dx] = *reinterpret_cast<const f4*>(src);
+          ub[dx] = *reinterpret_cast<const f4*>(src + 16);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int dy = hr - i;
+          if (dy < 0 || dy > 2) continue;
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) {
+            s1[i] += *reinterpret_cast<const f4*>(&wdw[0][dy * 3 + dx][4 * qd]) * ua[dx];
+            s2[i] += *reinterpret_cast<const f4*>(&wdw[1][dy * 3 + dx][4 * qd]) * ub[dx];
+          }
+        }
+      }
+      f4 part = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int y = y0 + 4 * hh + i, x = x0 + xc;
+        if (y < a.H && x < a.W) {
+          const size_t p = img + (size_t)y * a.W + x;
+          const f4 v = s1[i] * s2[i];
+          *reinterpret_cast<f4*>(a.v + ((size_t)g * a.P + p) * C + ch) = v;
+          part += v;
+          if (a.dsave) {  // training keeps the depthwise outputs for the backward pass
+            *reinterpret_cast<f4*>(a.dsave + ((size_t)g * a.P + p) * 2 * C + ch) = s1[i];
+            *reinterpret_cast<f4*>(a.dsave + ((size_t)g * a.P + p) * 2 * C + C + ch) = s2[i];
+          }
+        }
+      }
+      red[tid] = part;
+    }
+    __syncthreads();  // LDS u of this pass consumed; the sums in red complete
+    if (tid < 16) {
+      // channel 16 j + 4 q + r: the 64 threads of quad q, in thread order
+      const int q = tid >> 2, r = tid & 3;
+      float s = 0.0f;
+      for (int t = 0; t < 64; ++t) s += red[(t << 2) | q][r];
+      a.part[(((size_t)b * 4 + g) * C + 16 * j + 4 * q + r) * a.n_blk + blockIdx.x] = s;
+    }
+  }
 }
 
 // grid: (4, B); image mean of v per channel (thread (slice, ch) sums the
-// block partials slice, slice + S, ... in order, then the S slices are added
-// in order), then the attention's 1x1 conv
+// tile sums slice, slice + S, ... in order, then the S slices are added in
+// order), then the attention's 1x1 conv
 template <int C>
 __global__ __launch_bounds__(256) void adapt_attend(AdapterArgs a) {
   using O = Off<C>;
@@ -208,6 +253,7 @@ __global__ __launch_bounds__(256) void adapt_attend(AdapterArgs a) {
     float s = 0.0f;
     for (int q = 0; q < S; ++q) s += red[q][threadIdx.x];
     pooled[threadIdx.x] = s / (float)(a.H * a.W);
+    if (a.msave) a.msave[((size_t)b * 4 + g) * C + threadIdx.x] = pooled[threadIdx.x];
   }
   __syncthreads();
   if (threadIdx.x < C) {
@@ -220,111 +266,208 @@ __global__ __launch_bounds__(256) void adapt_attend(AdapterArgs a) {
 // output channels of each group: lightmaps (+Z, -Z), (+X, -X), (+Y, -Y); extra (alpha, emissive)
 __constant__ int kDst[4][2] = {{4, 5}, {0, 1}, {2, 3}, {-1, -2}};
 
-// Outputs of a dense layer are produced one channel at a time (a runtime
-// loop, so code size and registers stay bounded) into per-lane LDS columns
-// [channel][lane]; inputs are loaded back into registers for the next layer.
-constexpr int kOutThreads = 128;
+constexpr int kTailPix = 256;  // pixels per tail workgroup (64 per wavefront)
+
+// Wide adapters: keep the scheduler from moving one output block's weight
+// loads above the previous block's products (hoisted, they take every
+// register of the wavefront)
+template <int C>
+__device__ __forceinline__ void fence_schedule() {
+  if constexpr (C > 32) __builtin_amdgcn_sched_barrier(0);
+}
 
 template <int C, int IN>
-__global__ __launch_bounds__(kOutThreads) void adapt_out(AdapterArgs a) {
+__global__ __launch_bounds__(256) void adapt_tail(AdapterArgs a, int n_tiles) {
   using O = Off<C>;
-  // conv3 W, conv4 W, conv5 W, head W, then the vectors
-  constexpr int W3 = 0, W4 = C * C, W5 = 3 * C * C, WH = 4 * C * C, V = WH + 2 * C;
-  constexpr int B3 = V, BETA = V + C, L2W = V + 2 * C, L2B = V + 3 * C, B4 = V + 4 * C, B5 = V + 6 * C,
-                GAM = V + 7 * C, HB = V + 8 * C, NW = V + 8 * C + 4;
+  constexpr int KB = C / 16;
+  constexpr int NB = C <= 32 ? 4 : 2;  // 16-pixel column blocks per MFMA batch (register budget)
+  constexpr int WP = C + 4;            // LDS row pitch of the weight matrices (bank spread)
+  constexpr int W3 = 0, W4 = C * WP, W5 = 3 * C * WP, VEC = 4 * C * WP;
+  constexpr int B3 = VEC, BETA = B3 + C, L2W = BETA + C, L2B = L2W + C, B4 = L2B + C, B5 = B4 + 2 * C,
+                GAM = B5 + C, HWT = GAM + C, HB = HWT + 2 * C, NW = HB + 4;
   __shared__ __attribute__((aligned(16))) float sw[NW];
-  __shared__ float ys[C][kOutThreads];  // y = in + beta conv3(.), then + gamma conv5(.)
-  __shared__ float hs[C][kOutThreads];  // gated conv4 output
-  const int tid = threadIdx.x;
-  const size_t p = (size_t)blockIdx.x * kOutThreads + tid;
-  const bool live = p < a.P;
-  const int b = live ? (int)(p / ((size_t)a.H * a.W)) : 0;
-  float t[C];
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, G = lane >> 4, wave = tid >> 6;
+  // the four groups of a tile are blocks 8 apart: round-robin placement puts
+  // them on one XCD, whose L2 then serves the tile's features to all four
+  const int id = blockIdx.x;
+  const int g = (id >> 3) & 3, tile = ((id >> 5) << 3) | (id & 7);
+  if (tile >= n_tiles) return;  // whole workgroup, before any barrier
+  const float* P = a.prm + (size_t)g * O::total;
+  for (int q = tid; q < C * C; q += 256) {
+    const int r = q / C, col = q - r * C;
+    sw[W3 + r * WP + col] = P[O::c3w + q];
+    sw[W5 + r * WP + col] = P[O::c5w + q];
+  }
+  for (int q = tid; q < 2 * C * C; q += 256) {
+    const int r = q / C, col = q - r * C;
+    sw[W4 + r * WP + col] = P[O::c4w + q];
+  }
+  for (int q = tid; q < C; q += 256) {
+    sw[B3 + q] = P[O::c3b + q];
+    sw[BETA + q] = P[O::beta + q];
+    sw[L2W + q] = P[O::ln2w + q];
+    sw[L2B + q] = P[O::ln2b + q];
+    sw[B5 + q] = P[O::c5b + q];
+    sw[GAM + q] = P[O::gamma + q];
+  }
+  for (int q = tid; q < 2 * C; q += 256) {
+    sw[B4 + q] = P[O::c4b + q];
+    sw[HWT + q] = P[O::hw + q];
+  }
+  if (tid < 2) sw[HB + tid] = P[O::hb + tid];
+  __syncthreads();
+  // this lane's four channels of a vector, and of weight row `row` at K block kb
+  auto vec = [&](int off) { return *reinterpret_cast<const f4*>(sw + off + 4 * G); };
+  auto wrow = [&](int off, int row, int kb) {
+    return *reinterpret_cast<const f4*>(sw + off + row * WP + 16 * kb + 4 * G);
+  };
+  const size_t HWn = (size_t)a.H * a.W;
+
 #pragma unroll 1
-  for (int g = 0; g < 4; ++g) {
-    const float* P = a.prm + (size_t)g * O::total;
-    __syncthreads();
-    for (int q = tid; q < C * C; q += kOutThreads) {
-      sw[W3 + q] = P[O::c3w + q];
-      sw[W5 + q] = P[O::c5w + q];
+  for (int sub = 0; sub < 64 / (16 * NB); ++sub) {
+    const size_t pbase = (size_t)tile * kTailPix + (size_t)wave * 64 + (size_t)sub * 16 * NB;
+    size_t pix[NB];
+    bool ok[NB];
+    f4 t[KB][NB];
+    // t = v * s
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const size_t p = pbase + 16 * nb + li;
+      ok[nb] = p < a.P;
+      pix[nb] = ok[nb] ? p : a.P - 1;
+      const float* s = a.sca + ((size_t)(pix[nb] / HWn) * 4 + g) * C;
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+        t[kb][nb] = *reinterpret_cast<const f4*>(a.v + ((size_t)g * a.P + pix[nb]) * C + 16 * kb + 4 * G) *
+                    *reinterpret_cast<const f4*>(s + 16 * kb + 4 * G);
     }
-    for (int q = tid; q < 2 * C * C; q += kOutThreads) sw[W4 + q] = P[O::c4w + q];
-    for (int q = tid; q < 2 * C; q += kOutThreads) {
-      sw[WH + q] = P[O::hw + q];
-      sw[B4 + q] = P[O::c4b + q];
+    // y = in + beta (W3 t + b3)
+    f4 y[KB][NB];
+#pragma unroll
+    for (int mb = 0; mb < KB; ++mb) {
+      f4 acc[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = vec(B3 + 16 * mb);
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        const f4 w = wrow(W3, 16 * mb + li, kb);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma(w[r], t[kb][nb][r], acc[nb]);
+      }
+      const f4 beta = vec(BETA + 16 * mb);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) y[mb][nb] = feat4<C, IN>(a, pix[nb], 16 * mb + 4 * G) + beta * acc[nb];
+      fence_schedule<C>();
     }
-    for (int q = tid; q < C; q += kOutThreads) {
-      sw[B3 + q] = P[O::c3b + q];
-      sw[BETA + q] = P[O::beta + q];
-      sw[L2W + q] = P[O::ln2w + q];
-      sw[L2B + q] = P[O::ln2b + q];
-      sw[B5 + q] = P[O::c5b + q];
-      sw[GAM + q] = P[O::gamma + q];
+    // t = LN2(y) w + b over each pixel's C channels
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      float s = 0.0f;
+#pragma unroll
+      for (int mb = 0; mb < KB; ++mb) s += hsum(y[mb][nb]);
+      const float mu = pixel_sum(s) * (1.0f / (float)C);
+      float sq = 0.0f;
+#pragma unroll
+      for (int mb = 0; mb < KB; ++mb) {
+        t[mb][nb] = y[mb][nb] - mu;
+        sq += hsum(t[mb][nb] * t[mb][nb]);
+      }
+      const float rs = 1.0f / sqrtf(pixel_sum(sq) * (1.0f / (float)C) + 1e-6f);
+#pragma unroll
+      for (int mb = 0; mb < KB; ++mb) t[mb][nb] = t[mb][nb] * rs * vec(L2W + 16 * mb) + vec(L2B + 16 * mb);
     }
-    if (tid < 2) sw[HB + tid] = P[O::hb + tid];
-    __syncthreads();
-    if (!live) continue;  // no barrier below this point
-    // attended gate output
-    const float* s = a.sca + ((size_t)b * 4 + g) * C;
+    // h = gate(W4 t + b4): output rows 16 mb + i and C + 16 mb + i multiply
+    f4 h[KB][NB];
 #pragma unroll
-    for (int i = 0; i < C; ++i) t[i] = a.v[((size_t)g * C + i) * a.P + p] * s[i];
-    // y = in + beta * conv3(t)
-    load_feat<C, IN>(a, p, ys, tid);
-#pragma unroll 2
-    for (int o = 0; o < C; ++o) ys[o][tid] += sw[BETA + o] * row_dot<C>(sw + W3 + o * C, sw[B3 + o], t);
-    // t = LN2(y)
+    for (int mb = 0; mb < KB; ++mb) {
+      f4 a1[NB], a2[NB];
 #pragma unroll
-    for (int i = 0; i < C; ++i) t[i] = ys[i][tid];
-    normalise<C>(t);
+      for (int nb = 0; nb < NB; ++nb) {
+        a1[nb] = vec(B4 + 16 * mb);
+        a2[nb] = vec(B4 + C + 16 * mb);
+      }
 #pragma unroll
-    for (int i = 0; i < C; ++i) t[i] = t[i] * sw[L2W + i] + sw[L2B + i];
-    // h = gate(conv4(t))
-#pragma unroll 2
-    for (int o = 0; o < C; ++o)
-      hs[o][tid] =
-          row_dot<C>(sw + W4 + o * C, sw[B4 + o], t) * row_dot<C>(sw + W4 + (C + o) * C, sw[B4 + C + o], t);
-    // y += gamma * conv5(h)
+      for (int kb = 0; kb < KB; ++kb) {
+        const f4 w1 = wrow(W4, 16 * mb + li, kb), w2 = wrow(W4, C + 16 * mb + li, kb);
 #pragma unroll
-    for (int i = 0; i < C; ++i) t[i] = hs[i][tid];
-#pragma unroll 2
-    for (int o = 0; o < C; ++o) ys[o][tid] += sw[GAM + o] * row_dot<C>(sw + W5 + o * C, sw[B5 + o], t);
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int i = 0; i < C; ++i) t[i] = ys[i][tid];
+          for (int nb = 0; nb < NB; ++nb) {
+            a1[nb] = mfma(w1[r], t[kb][nb][r], a1[nb]);
+            a2[nb] = mfma(w2[r], t[kb][nb][r], a2[nb]);
+          }
+      }
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const float z = row_dot<C>(sw + WH + k * C, sw[HB + k], t);
-      const float sig = 1.0f / (1.0f + expf(-z));
-      const int d = kDst[g][k];
-      if (d >= 0)
-        a.lm[p * 6 + d] = sig;
-      else if (a.extra)
-        a.extra[p * 2 + (-1 - d)] = sig;
+      for (int nb = 0; nb < NB; ++nb) h[mb][nb] = a1[nb] * a2[nb];
+      fence_schedule<C>();
+    }
+    // y += gamma (W5 h + b5)
+#pragma unroll
+    for (int mb = 0; mb < KB; ++mb) {
+      f4 acc[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[nb] = vec(B5 + 16 * mb);
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        const f4 w = wrow(W5, 16 * mb + li, kb);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma(w[r], h[kb][nb][r], acc[nb]);
+      }
+      const f4 gam = vec(GAM + 16 * mb);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) y[mb][nb] += gam * acc[nb];
+      fence_schedule<C>();
+    }
+    // head and sigmoid
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      float z0 = 0.0f, z1 = 0.0f;
+#pragma unroll
+      for (int mb = 0; mb < KB; ++mb) {
+        z0 += hsum(vec(HWT + 16 * mb) * y[mb][nb]);
+        z1 += hsum(vec(HWT + C + 16 * mb) * y[mb][nb]);
+      }
+      z0 = pixel_sum(z0) + sw[HB];
+      z1 = pixel_sum(z1) + sw[HB + 1];
+      if (G == 0 && ok[nb]) {
+        const float o[2] = {1.0f / (1.0f + expf(-z0)), 1.0f / (1.0f + expf(-z1))};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int d = kDst[g][k];
+          if (d >= 0)
+            a.lm[pix[nb] * 6 + d] = o[k];
+          else if (a.extra)
+            a.extra[pix[nb] * 2 + (-1 - d)] = o[k];
+        }
+      }
     }
   }
 }
 
 template <int C>
 hipError_t launch_c(const AdapterArgs& a, int in_type, hipStream_t s) {
-  const unsigned blk = (unsigned)((a.P + 255) / 256);
+  const dim3 fgrid((unsigned)a.n_blk, 4, (unsigned)a.B);
   switch (in_type) {
-    case 0: hipLaunchKernelGGL((adapt_expand<C, 0>), dim3(blk), dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((adapt_expand<C, 1>), dim3(blk), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((adapt_expand<C, 2>), dim3(blk), dim3(256), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((adapt_front<C, 0>), fgrid, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((adapt_front<C, 1>), fgrid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((adapt_front<C, 2>), fgrid, dim3(256), 0, s, a); break;
   }
-  hipLaunchKernelGGL(adapt_dw_gate<C>, dim3(a.n_blk, 4 * C, a.B), dim3(256), 0, s, a);
   hipLaunchKernelGGL(adapt_attend<C>, dim3(4, a.B), dim3(256), 0, s, a);
-  const unsigned oblk = (unsigned)((a.P + kOutThreads - 1) / kOutThreads);
+  const int n_tiles = (int)((a.P + kTailPix - 1) / kTailPix);
+  const unsigned tblk = 32u * (unsigned)((n_tiles + 7) / 8);
   switch (in_type) {
-    case 0: hipLaunchKernelGGL((adapt_out<C, 0>), dim3(oblk), dim3(kOutThreads), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((adapt_out<C, 1>), dim3(oblk), dim3(kOutThreads), 0, s, a); break;
-    default: hipLaunchKernelGGL((adapt_out<C, 2>), dim3(oblk), dim3(kOutThreads), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((adapt_tail<C, 0>), dim3(tblk), dim3(256), 0, s, a, n_tiles); break;
+    case 1: hipLaunchKernelGGL((adapt_tail<C, 1>), dim3(tblk), dim3(256), 0, s, a, n_tiles); break;
+    default: hipLaunchKernelGGL((adapt_tail<C, 2>), dim3(tblk), dim3(256), 0, s, a, n_tiles); break;
   }
   return hipGetLastError();
 }
 
 }  // namespace
-
-bool adapter_width_supported(int c) { return c == 16 || c == 32 || c == 48 || c == 64; }
 
 hipError_t launch_adapters(int c, const AdapterArgs& a, int in_type, hipStream_t s) {
   switch (c) {

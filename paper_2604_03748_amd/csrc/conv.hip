@@ -497,55 +497,6 @@ hipError_t launch_splitk_reduce(const ConvArgs& a, int out_type, hipStream_t s) 
   return hipGetLastError();
 }
 
-int conv_splits(long wgs, int nchunks, int target) {
-  // grow the split until the layer has `target` workgroups; keep at least
-  // two chunks per split
-  int s = 1;
-  while (wgs * s < target && 2 * (s * 2) <= nchunks && s < 16) s *= 2;
-  return s;
-}
-
-// Tile height and split-K factor of conv layer i at level size h x w (tiles
-// of th x 16 pixels x 32 output channels); the 3-channel input layer is
-// never split.  The split grows until the layer has 256 workgroups (fp32) or
-// 512 (bf16, fp8), the targets measured fastest per precision with the
-// split-K reductions counted.  fp32 and bf16 layers take 4-row tiles where
-// that needs a smaller split than 8-row tiles (the deep levels: twice the
-// workgroups without partial sums to write, read and reduce) or where 8-row
-// tiles leave one workgroup per CU (nothing else on the CU hides a
-// workgroup's chunk-boundary stalls): 5 us per fp32 frame, 9 us per bf16
-// frame.  fp8 layers, whose LDS footprint lets five 4-row workgroups share
-// a CU, take 4-row tiles throughout: 19 us per frame.  Large bf16 layers
-// take the 8-row x 64-channel form when it still gives two workgroups per
-// CU.
-//
-// The split and the tile height follow the workgroup count of one image, so
-// an image's sums (whose order the split sets) are the same alone and in any
-// batch; only the bf16 large form, which sums in the same order as the
-// default form, looks at the batch.
-LayerTiling conv_layer_tiling(const lnm_net_s* net, int i, int B, int h, int w) {
-  const LayerDesc& d = net->layers[i];
-  if (d.ci == 3) return {8, 1};
-  const int target = d.prec == LNM_FP32 ? 256 : 512, nch = d.ci_pad / d.ck;
-  auto wgs = [&](int th) { return (long)((w + 15) / 16) * ((h + th - 1) / th) * (d.co_pad / kBN); };
-  const int s8 = conv_splits(wgs(8), nch, target);
-  if (d.prec == LNM_BF16 && s8 == 1) {
-    // large bf16 layers: the 64-channel tile, when it still gives two
-    // workgroups per CU
-    const int nt = d.co_pad / kBN;
-    const long large =
-        (long)((w + 15) / 16) * ((h + kBf16LargeRows - 1) / kBf16LargeRows) * B * ((nt + 1) / 2);
-    if (nt >= 2 && large >= 512) return {kBf16Large, 1};
-  }
-  const bool fp8 = d.prec == LNM_FP8_E4M3;
-  if (s8 > 1 || wgs(8) <= 256 || fp8) {
-    // the longest fp32 layers (16+ chunks) split on to two workgroups per CU
-    const int s4 = conv_splits(wgs(4), nch, d.prec == LNM_FP32 && nch >= 16 ? 512 : target);
-    if (s4 < s8 || wgs(8) <= 256 || fp8) return {4, s4};
-  }
-  return {8, s8};
-}
-
 hipError_t launch_wgrad3x3(int mode, const WgradArgs& a, int* n_partials, hipStream_t s) {
   const int tiles = a.x.B * ((a.x.W + kTW - 1) / kTW) * ((a.x.H + kWTH - 1) / kWTH);
   const int groups = (tiles + a.tiles_per_group - 1) / a.tiles_per_group;

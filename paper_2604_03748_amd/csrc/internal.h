@@ -45,7 +45,7 @@ struct MarchDev {
   int quadrature;
   float wf, wt, wb;  // front and side light intensities
   int light_set;     // lnm_light_set
-  int zorder;        // light marches in z order (march_use_zorder), else band order
+  int zorder;        // order of the light marches (march_order): bands, z layers or z cells
   const float* brick;  // bricked copy of rho (4^3 cells + apron per 128-float slot); caller's or scratch
   int nbx, nby, nbz;   // bricks per axis
 };
@@ -59,6 +59,7 @@ struct MarchBuf {
   int* ctr;    // counter block: entries in each band's work list, the z-order unit counters, start[0..9)
                // of the bands' tile ranges, the records per z bucket and the z-order scatter cursors
   int2* rec;   // work lists of the primary march, (pixel, k); band e's from entry start[e] * 64 * K
+               // (NULL in cell order)
   size_t cap;  // entries per band at equal bands (the lists hold 8 * cap)
   uint8_t* zb;  // z order: [K][P] z bucket (brick layer) of each record's sample, else NULL
   int2* srt;    // z order: [P * K] the records of all bands in z-bucket order, else NULL
@@ -72,11 +73,30 @@ struct MarchBuf {
 struct TileMap {
   int tiles_x, tiles_y, per_xcd, band_rows;
 };
+// The march's layout constants.  kBrickSlot: floats per brick (5^3 values
+// of a 4^3-cell brick and the next layer, padded).  kTile: side of the
+// primary march's screen tiles.  The counter block (ints): the 8 band
+// counters, the light marches' per-XCD next-unit counters from kUnitNext (z
+// order), start[0..8] of the band tile ranges from kBandStart, the record
+// count of each z bucket from kZHist and the z-order scatter cursors from
+// kZCursor.
+constexpr int kBrickSlot = 128;
+constexpr int kTile = 8;
+constexpr int kUnitNext = 8, kBandStart = 16;
+constexpr int kZBuckets = 256;
+constexpr int kZHist = 32, kZCursor = kZHist + kZBuckets;
+constexpr size_t kCounterBytes = 4 * (kZCursor + kZBuckets);
+// Bricks along an axis of n cells; bytes of a z cell's two grid planes in LDS.
+int bricks_along(int n);
+size_t cell_planes_bytes(int nx, int ny);
 // Capacity per pixel: the most primary samples a ray can take in the support box.
 int march_capacity(const MarchDev& m);
-// Whether a march takes the z order (lnm_work_order; AUTO: grids whose
-// bricks exceed the XCDs' L2s together).
-bool march_use_zorder(int work_order, int nx, int ny, int nz);
+// Order of a march's light marches (MarchDev::zorder) for lnm_work_order
+// work_order; AUTO: z layers for grids whose bricks exceed the XCDs' L2s
+// together, z cells for the top/bottom lights when a cell's two grid planes
+// fit in LDS, else bands; -1 when LNM_ORDER_CELLS does not fit.
+constexpr int kOrderBands = 0, kOrderLayers = 1, kOrderCells = 2;
+int march_order(int work_order, int light_set, int nx, int ny, int nz);
 // Scratch of one march; the bricked grid is part of it unless m.brick is set.
 size_t march_scratch_bytes(const MarchDev& m, int K, int W, int H);
 MarchBuf march_buffers(void* ws, const MarchDev& m, int K, int W, int H);
@@ -206,14 +226,18 @@ struct AdapterArgs {
   const float* prm;   // four adapters' parameters (parameter-file order)
   int B, H, W;
   size_t P;           // B H W
-  float* u;           // [4][2c][P] conv1 outputs
-  float* v;           // [4][c][P] gated depthwise outputs
-  float* part;        // [B][4][c][n_blk] per-block sums of v
-  int n_blk;          // 256-pixel blocks per image
+  float* v;           // [4][P][c] gated depthwise outputs
+  float* part;        // [B][4][c][n_blk] per-tile sums of v
+  int n_blk;          // adapter tiles per image (adapter_tiles)
   float* sca;         // [B][4][c] attention scales
   float* lm;          // [P][6]
   float* extra;       // [P][2] or NULL
+  float* dsave;       // training: [4][P][2c] depthwise outputs, else NULL
+  float* msave;       // training: [B][4][c] image means of v, else NULL
 };
+// the adapters' first kernel works on tiles of 8 x 32 pixels
+constexpr int kAdaptTileY = 8, kAdaptTileX = 32;
+int adapter_tiles(int H, int W);
 bool adapter_width_supported(int c);
 hipError_t launch_adapters(int c, const AdapterArgs& a, int in_type, hipStream_t s);
 

@@ -54,17 +54,17 @@ __device__ __forceinline__ float sample_sigma_linear(const MarchDev& m, float px
   return m.sigma_scale * v * (inside ? 1.0f : 0.0f);
 }
 
-// Bricked grid: index i' = i + 1 over [0, n + 1] (a zero layer on each side),
-// cut into bricks of 4 cells per axis that also store the next layer
-// (5 x 5 x 5 values in a 128-float slot).  The 8 corners of the cell holding
-// a point are then in one brick at fixed offsets, and the zero layers make
-// the grid's zero border explicit.  Same value as sample_sigma_linear.
+// Bricked grid (kBrickSlot): index i' = i + 1 over [0, n + 1] (a zero layer
+// on each side), cut into bricks of 4 cells per axis that also store the
+// next layer (5 x 5 x 5 values in a 128-float slot).  The 8 corners of the
+// cell holding a point are then in one brick at fixed offsets, and the zero
+// layers make the grid's zero border explicit.  Same value as
+// sample_sigma_linear.
 //
 // The sample is branch-free so that a caller's batch of samples issues all
 // its loads before waiting on any: a point outside the support box is
 // moved to the grid origin for the loads and its value discarded.  Slot
 // offsets are 32-bit (the bricked grid is limited to 4 GiB).
-constexpr int kBrickSlot = 128;
 
 // Address and interpolation weights of one bricked sample (split from the
 // loads so that callers can issue the loads of several samples together).
@@ -75,7 +75,7 @@ struct BrickTap {
 };
 
 __device__ __forceinline__ BrickTap brick_tap(const MarchDev& m, float px, float py, float pz) {
-  const float gx = px * (float)m.nx - 0.5f, gy = py * (float)m.ny - 0.5f, gz = pz * (float)m.nz - 0.5f;
+  const float gx = fmaf(px, (float)m.nx, -0.5f), gy = fmaf(py, (float)m.ny, -0.5f), gz = fmaf(pz, (float)m.nz, -0.5f);
   const bool inside = gx > -1.0f && gy > -1.0f && gz > -1.0f && gx < (float)m.nx && gy < (float)m.ny &&
                       gz < (float)m.nz;
   // outside points are moved to the origin for the loads (their value is masked)
@@ -107,15 +107,20 @@ __device__ __forceinline__ BrickVals brick_load(const BrickTap& t) {
   c.v[7] = t.r[31];
   return c;
 }
+// Trilinear value of the 8 corners (v[0] at (i, j, k), then +x, +y, +x+y,
+// and the same at k + 1) with fractions fx, fy, fz: each linear blend
+// (1 - f) a + f b written as one fused multiply-add, so that every sampler
+// (bricks in global memory, grid planes in LDS) computes it identically.
+__device__ __forceinline__ float lerp1(float a, float b, float f) { return fmaf(f, b, (1.0f - f) * a); }
+__device__ __forceinline__ float trilerp(const float (&v)[8], float fx, float fy, float fz) {
+  const float c00 = lerp1(v[0], v[1], fx), c10 = lerp1(v[2], v[3], fx);
+  const float c01 = lerp1(v[4], v[5], fx), c11 = lerp1(v[6], v[7], fx);
+  return lerp1(lerp1(c00, c10, fy), lerp1(c01, c11, fy), fz);
+}
 // sigma_scale x the trilinear value, times the inside mask (a multiply, not a
 // select, which the compiler would turn back into a branch around the loads)
 __device__ __forceinline__ float brick_lerp(const MarchDev& m, const BrickTap& t, const BrickVals& c) {
-  const float c00 = (1.0f - t.fx) * c.v[0] + t.fx * c.v[1];
-  const float c10 = (1.0f - t.fx) * c.v[2] + t.fx * c.v[3];
-  const float c01 = (1.0f - t.fx) * c.v[4] + t.fx * c.v[5];
-  const float c11 = (1.0f - t.fx) * c.v[6] + t.fx * c.v[7];
-  const float v = (1.0f - t.fz) * ((1.0f - t.fy) * c00 + t.fy * c10) + t.fz * ((1.0f - t.fy) * c01 + t.fy * c11);
-  return m.sigma_scale * v * t.mask;
+  return m.sigma_scale * trilerp(c.v, t.fx, t.fy, t.fz) * t.mask;
 }
 
 __device__ __forceinline__ float sample_sigma(const MarchDev& m, float px, float py, float pz) {
@@ -150,7 +155,7 @@ struct FlatZ {
   float fz;
 };
 __device__ __forceinline__ FlatZ flat_z(const MarchDev& m, float pz) {
-  const float gz = pz * (float)m.nz - 0.5f;
+  const float gz = fmaf(pz, (float)m.nz, -0.5f);
   FlatZ z;
   z.in = gz > -1.0f && gz < (float)m.nz;
   const float cz = z.in ? gz : 0.0f, fz0 = floorf(cz);
@@ -161,7 +166,7 @@ __device__ __forceinline__ FlatZ flat_z(const MarchDev& m, float pz) {
   return z;
 }
 __device__ __forceinline__ BrickTap brick_tap_flat(const MarchDev& m, float px, float py, const FlatZ& z) {
-  const float gx = px * (float)m.nx - 0.5f, gy = py * (float)m.ny - 0.5f;
+  const float gx = fmaf(px, (float)m.nx, -0.5f), gy = fmaf(py, (float)m.ny, -0.5f);
   const bool inside = z.in && gx > -1.0f && gy > -1.0f && gx < (float)m.nx && gy < (float)m.ny;
   const float cx = inside ? gx : 0.0f, cy = inside ? gy : 0.0f;
   const float fx0 = floorf(cx), fy0 = floorf(cy);
@@ -329,9 +334,9 @@ __device__ __forceinline__ float light_transmittance_batched(const MarchDev& m, 
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const float t = (float)(k + q) * h;
-      px[q] = x.x + t * l.x;
-      py[q] = x.y + t * l.y;
-      pz[q] = x.z + t * l.z;
+      px[q] = fmaf(t, l.x, x.x);
+      py[q] = fmaf(t, l.y, x.y);
+      pz[q] = fmaf(t, l.z, x.z);
     }
     if constexpr (FLAT)
       sample_batch_flat<4>(m, px, py, fz, sv);
@@ -340,6 +345,67 @@ __device__ __forceinline__ float light_transmittance_batched(const MarchDev& m, 
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       acc += k + q <= kmax ? sv[q] : 0.0f;
+      if (acc > lim) return 0.0f;
+    }
+  }
+  return expf(-acc * h);
+}
+
+// The light march of a flat light (no z component) with the density of its
+// sample's z cell staged in LDS: pl[ny + 2][nx + 2] pairs (value of the grid
+// plane below the cell, value of the plane above), with a zero border (index
+// i + 1 holds grid column i), so one 8-byte read gives both planes' corner.
+// The taps, interpolation weights and sums are those of
+// light_transmittance_batched<true>, so the result is the same bit for bit;
+// the corners come from LDS instead of the bricks.
+struct LdsTap {
+  int o;      // LDS pair index of corner (i, j)
+  float fx, fy, mask;
+};
+__device__ __forceinline__ LdsTap lds_tap(const MarchDev& m, float px, float py, bool zin, int pitch) {
+  const float gx = fmaf(px, (float)m.nx, -0.5f), gy = fmaf(py, (float)m.ny, -0.5f);
+  const bool inside = zin && gx > -1.0f && gy > -1.0f && gx < (float)m.nx && gy < (float)m.ny;
+  const float cx = inside ? gx : 0.0f, cy = inside ? gy : 0.0f;
+  const float fx0 = floorf(cx), fy0 = floorf(cy);
+  LdsTap t;
+  t.o = ((int)fy0 + 1) * pitch + (int)fx0 + 1;
+  t.fx = cx - fx0;
+  t.fy = cy - fy0;
+  t.mask = inside ? 1.0f : 0.0f;
+  return t;
+}
+__device__ __forceinline__ float light_transmittance_lds(const MarchDev& m, V3 x, V3 l, const float2* __restrict__ pl,
+                                                         int pitch) {
+  const float h = m.h, lim = m.tau_max / h;
+  const int kmax = light_steps(m, x, l, h);
+  const FlatZ fz = flat_z(m, x.z);
+  float acc = 0.0f;
+  for (int k = 1; k <= kmax; k += 4) {
+    LdsTap t[4];
+    float c[4][8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float tt = (float)(k + q) * h;
+      t[q] = lds_tap(m, fmaf(tt, l.x, x.x), fmaf(tt, l.y, x.y), fz.in, pitch);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float2* a = pl + t[q].o;
+      const float2 v00 = a[0], v10 = a[1], v01 = a[pitch], v11 = a[pitch + 1];
+      c[q][0] = v00.x;
+      c[q][1] = v10.x;
+      c[q][2] = v01.x;
+      c[q][3] = v11.x;
+      c[q][4] = v00.y;
+      c[q][5] = v10.y;
+      c[q][6] = v01.y;
+      c[q][7] = v11.y;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float fzz = t[q].mask != 0.0f ? fz.fz : 0.0f;
+      const float sv = m.sigma_scale * trilerp(c[q], t[q].fx, t[q].fy, fzz) * t[q].mask;
+      acc += k + q <= kmax ? sv : 0.0f;
       if (acc > lim) return 0.0f;
     }
   }
@@ -358,25 +424,19 @@ __device__ __forceinline__ void tile_pixel(int* i, int* j) {
 // light marches stay inside one slab of the volume.  A workgroup of 256
 // lanes covers one tile with four lanes per pixel; each wavefront an 8x2
 // block.
-constexpr int kTile = 8;
-// The march's counter block (ints): the 8 band counters, the light marches'
-// per-XCD next-unit counters from kUnitNext (z order), start[0..8] of the
-// band tile ranges from kBandStart, the record count of each z bucket from
-// kZHist and the z-order scatter cursors from kZCursor.
-constexpr int kUnitNext = 8, kBandStart = 16;
-constexpr int kZBuckets = 256;
-constexpr int kZHist = 32, kZCursor = kZHist + kZBuckets;
-constexpr size_t kCounterBytes = 4 * (kZCursor + kZBuckets);
 
-// z bucket of a sample point: the brick layer of its trilinear cell (the
-// bricks hold cells k' = floor(gz) + 1 in layer k' / 4), capped at the last
-// bucket.  A side light has no z component, so a light march stays in its
-// sample's bucket (the fallback lights of a ray along z and the left/right
-// set do not; the order then only loses locality).
+// z bucket of a sample point: its trilinear cell k' = floor(gz) + 1 (the
+// cell between grid planes k' - 1 and k'), in z order grouped by brick layer
+// (the bricks hold cells in layers k' / 4), capped at the last bucket.  A
+// side light has no z component, so a light march stays in its sample's
+// cell (the fallback lights of a ray along z and the left/right set do not;
+// the order then only loses locality).
 __device__ __forceinline__ int z_bucket(const MarchDev& m, float pz) {
-  const float gz = fminf(fmaxf(pz * (float)m.nz - 0.5f, -1.0f), (float)m.nz);
-  return min(((int)floorf(gz) + 1) >> 2, kZBuckets - 1);
+  const float gz = fminf(fmaxf(fmaf(pz, (float)m.nz, -0.5f), -1.0f), (float)m.nz);
+  const int cell = (int)floorf(gz) + 1;
+  return min(m.zorder == kOrderCells ? cell : cell >> 2, kZBuckets - 1);
 }
+
 __device__ __forceinline__ void tile_origin(const TileMap& tm, int L, int* tx, int* ty) {
   if (tm.band_rows) {
     *ty = L / tm.tiles_x;
@@ -548,6 +608,8 @@ __device__ __forceinline__ void primary_tile(const MarchDev& m, const CamDev& c,
     g[1] = term ? 0.0f : expf(-tau);
     g[2] = dmin == big ? 0.0f : (float)dmin * h;
   }
+  // cell order reads the records through the per-pixel counts instead
+  if (m.zorder == kOrderCells) return;
   // append the tile's records to the band's list: one atomic per block (the
   // four waves' totals summed in LDS; a wave's share follows the lower
   // waves'), then k-major order within each wave (pixels in lane order within
@@ -594,7 +656,7 @@ __global__ __launch_bounds__(256) void march_primary(MarchDev m, CamDev c, TileM
   const int band = blockIdx.x & 7, slots = gridDim.x >> 3;
   const int* start = buf.ctr + kBandStart;
   const int lo = start[band], hi = start[band + 1];
-  int2* list = buf.rec + (size_t)lo * (kTile * kTile) * (size_t)buf.K;
+  int2* list = buf.rec ? buf.rec + (size_t)lo * (kTile * kTile) * (size_t)buf.K : nullptr;
   for (int L = lo + (int)(blockIdx.x >> 3); L < hi; L += slots)
     primary_tile(m, c, tm, buf, guide, L, band, list, zh, agg);
   if (m.zorder) {
@@ -744,20 +806,109 @@ __global__ __launch_bounds__(256) void zsort_records(MarchBuf buf) {
   }
   const long per = ((long)total + gridDim.x - 1) / gridDim.x;
   const int r0 = (int)min((long)total, (long)blockIdx.x * per), r1 = (int)min((long)total, (long)r0 + per);
-  for (int r = r0 + tid; r < r1; r += 256) {
-    const int2 en = band_entry(buf, count, r);
-    atomicAdd(&lcount[buf.zb[(size_t)en.y * buf.P + en.x]], 1);
+  // U entries per lane at a time, their loads and LDS atomics issued together
+  constexpr int U = 4;
+  for (int r = r0 + tid; r < r1; r += U * 256) {
+    int zk[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ru = r + u * 256;
+      zk[u] = -1;
+      if (ru < r1) {
+        const int2 en = band_entry(buf, count, ru);
+        zk[u] = buf.zb[(size_t)en.y * buf.P + en.x];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (zk[u] >= 0) atomicAdd(&lcount[zk[u]], 1);
   }
   __syncthreads();
   const int mine = lcount[tid];
   if (mine) lbase[tid] = atomicAdd(buf.ctr + kZCursor + tid, mine);
   lcount[tid] = 0;  // now the block's cursor per bucket
   __syncthreads();
-  for (int r = r0 + tid; r < r1; r += 256) {
-    const int2 en = band_entry(buf, count, r);
-    const int b = buf.zb[(size_t)en.y * buf.P + en.x];
-    const long pos = (long)bstart[b] + lbase[b] + atomicAdd(&lcount[b], 1);
-    if (pos < bend[b]) buf.srt[pos] = en;
+  for (int r = r0 + tid; r < r1; r += U * 256) {
+    int2 en[U];
+    int zk[U], at[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ru = r + u * 256;
+      zk[u] = -1;
+      en[u] = make_int2(0, 0);
+      if (ru < r1) {
+        en[u] = band_entry(buf, count, ru);
+        zk[u] = buf.zb[(size_t)en[u].y * buf.P + en[u].x];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) at[u] = zk[u] >= 0 ? atomicAdd(&lcount[zk[u]], 1) : 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (zk[u] < 0) continue;
+      const long pos = (long)bstart[zk[u]] + lbase[zk[u]] + at[u];
+      if (pos < bend[zk[u]]) buf.srt[pos] = en[u];
+    }
+  }
+}
+
+// Cell order: the records scattered into z-cell order (srt).  A block takes
+// 64 pixels; wavefront w of the block takes the records k = w, w + 4, ... of
+// each (one lane per pixel; whose cells the primary march wrote to zb), so a
+// CU holds several blocks' loads in flight.  Cell b's records take entries
+// [B_b, B_b + n_b), B the exclusive prefix sum of the counts n; each block
+// counts its records per cell in LDS, reserves each cell's share with one
+// global atomic and writes its entries there on a second pass.  Every write
+// is bounded by its cell's range.
+constexpr int kSortPixels = 64;
+__global__ __launch_bounds__(256) void zsort_cells(MarchBuf buf) {
+  __shared__ int scan[2][kZBuckets];
+  __shared__ int bstart[kZBuckets], bend[kZBuckets], lcount[kZBuckets], lbase[kZBuckets];
+  static_assert(kZBuckets == 256, "one lane per bucket");
+  const int tid = threadIdx.x;
+  const int n = buf.ctr[kZHist + tid];
+  scan[0][tid] = n;
+  lcount[tid] = 0;
+  __syncthreads();
+  int cur = 0;
+  for (int o = 1; o < kZBuckets; o <<= 1) {  // inclusive scan (Hillis-Steele)
+    scan[cur ^ 1][tid] = scan[cur][tid] + (tid >= o ? scan[cur][tid - o] : 0);
+    cur ^= 1;
+    __syncthreads();
+  }
+  bstart[tid] = scan[cur][tid] - n;
+  bend[tid] = scan[cur][tid];
+  const int p = blockIdx.x * kSortPixels + (tid & 63), k1 = tid >> 6;
+  const int cnt = p < buf.P ? min(buf.cnt[p], buf.K) : 0;
+  // U of the lane's records at a time, their loads and LDS atomics issued
+  // together (one record after the other leaves the lane waiting on each load)
+  constexpr int U = 4, S = 4;
+  for (int k0 = k1; k0 < cnt; k0 += U * S) {
+    int zk[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) zk[u] = k0 + u * S < cnt ? buf.zb[(size_t)(k0 + u * S) * buf.P + p] : -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (zk[u] >= 0) atomicAdd(&lcount[zk[u]], 1);
+  }
+  __syncthreads();
+  const int mine = lcount[tid];
+  if (mine) lbase[tid] = atomicAdd(buf.ctr + kZCursor + tid, mine);
+  lcount[tid] = 0;  // now the block's cursor per cell
+  __syncthreads();
+  for (int k0 = k1; k0 < cnt; k0 += U * S) {
+    int zk[U], at[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) zk[u] = k0 + u * S < cnt ? buf.zb[(size_t)(k0 + u * S) * buf.P + p] : -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) at[u] = zk[u] >= 0 ? atomicAdd(&lcount[zk[u]], 1) : 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (zk[u] < 0) continue;
+      const int b = zk[u];
+      const long pos = (long)bstart[b] + lbase[b] + at[u];
+      if (pos < bend[b]) buf.srt[pos] = make_int2(p, k0 + u * S);
+    }
   }
 }
 
@@ -819,6 +970,89 @@ __global__ __launch_bounds__(256) void march_lights(MarchDev m, CamDev c, MarchB
     } else {
       unit += slots;
     }
+  }
+}
+
+// Cell order: one lane per record and light, the records sorted by their
+// sample's z cell (srt), each workgroup staging the two grid planes of its
+// cell in LDS.  The records of cell b form ceil(n_b / kCellRecs) units of
+// kCellRecs records (two lanes each: top and bottom light, side by side, so
+// neighbouring lanes start from the same point).  Block g of the grid takes
+// the contiguous run [g U / G, (g + 1) U / G) of the U units (g numbered so
+// that the blocks of one XCD, b % 8, take adjacent runs: a slab of cells),
+// and stages planes again only when its cell changes.  Flat lights (every
+// light of the top/bottom set except the fallback of a ray along z) read
+// LDS; others read the bricks.
+constexpr int kCellThreads = 1024, kCellRecs = kCellThreads / 2;
+__global__ __launch_bounds__(kCellThreads) void march_lights_cells(MarchDev m, CamDev c, MarchBuf buf) {
+  extern __shared__ float2 planes[];  // [ny + 2][nx + 2] pairs (plane below, plane above)
+  __shared__ int cnt[kZBuckets], ustart[kZBuckets + 1], rstart[kZBuckets];
+  const int tid = threadIdx.x;
+  if (tid < kZBuckets) cnt[tid] = buf.ctr[kZHist + tid];
+  __syncthreads();
+  if (tid == 0) {  // units and record offsets of the cells (exclusive prefix sums)
+    int u = 0, r = 0;
+    ustart[0] = 0;
+    for (int b = 0; b < kZBuckets; ++b) {
+      rstart[b] = r;
+      r += cnt[b];
+      u += (cnt[b] + kCellRecs - 1) / kCellRecs;
+      ustart[b + 1] = u;
+    }
+  }
+  __syncthreads();
+  const long units = ustart[kZBuckets];
+  const int G = gridDim.x, g = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  const int u0 = (int)(units * g / G), u1 = (int)(units * (g + 1) / G);
+  const int pitch = m.nx + 2;
+  const int light = tid & 1;
+  const float w = light ? m.wb : m.wt;
+  int staged = -1;  // the cell whose planes are in LDS (the same in every lane)
+  for (int u = u0; u < u1; ++u) {
+    int b = 0;  // the cell of unit u: the last b with ustart[b] <= u
+    for (int step = 128; step > 0; step >>= 1)
+      if (b + step < kZBuckets && ustart[b + step] <= u) b += step;
+    if (b != staged) {
+      __syncthreads();  // every lane is done with the previous cell's planes
+      // grid planes b - 1 and b, zero outside the grid: rpp rows per pass,
+      // one lane per entry (pitch <= 160 where this order is chosen)
+      const int rpp = max(1, kCellThreads / pitch), x = tid % pitch;
+      for (int y = tid / pitch; y < m.ny + 2 && tid < rpp * pitch && x < pitch; y += rpp) {
+        const int j = y - 1, i = x - 1;
+        const bool in = j >= 0 && j < m.ny && i >= 0 && i < m.nx;
+        const bool ok0 = in && b - 1 >= 0 && b - 1 < m.nz, ok1 = in && b < m.nz;
+        const size_t col = (size_t)j * m.nx + i, ps = (size_t)m.nx * m.ny;
+        planes[y * pitch + x] = make_float2(ok0 ? m.rho[(size_t)(b - 1) * ps + col] : 0.0f,
+                                            ok1 ? m.rho[(size_t)b * ps + col] : 0.0f);
+      }
+      __syncthreads();
+      staged = b;
+    }
+    const int r = (u - ustart[b]) * kCellRecs + (tid >> 1);
+    if (r >= cnt[b] || w == 0.0f) continue;
+    const int2 en = buf.srt[rstart[b] + r];
+    // every entry of the list is written by the scatter; the check keeps a
+    // lane that would see anything else in bounds
+    if ((unsigned)en.x >= (unsigned)buf.P || (unsigned)en.y >= (unsigned)buf.K) continue;
+    const int pix = en.x, k = en.y;
+    const size_t q = (size_t)k * buf.P + pix;
+    V3 o, d;
+    camera_ray(c, pix % c.W, pix / c.W, &o, &d);
+    const float t = buf.t[q];
+    V3 l = side_light(d, m.light_set);
+    if (light) l = v3(-l.x, -l.y, -l.z);
+    const V3 x = v3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
+    // the staged planes serve a flat light whose sample lies in cell b
+    const float gz = fmaf(x.z, (float)m.nz, -0.5f);
+    const bool in_cell = gz > -1.0f && gz < (float)m.nz && (int)floorf(gz) + 1 == b;
+    float T;
+    if (l.z == 0.0f && in_cell)
+      T = light_transmittance_lds(m, x, l, planes, pitch);
+    else if (l.z == 0.0f)
+      T = light_transmittance_batched<true>(m, x, l);
+    else
+      T = light_transmittance_batched<false>(m, x, l);
+    buf.tl[(size_t)light * buf.K * buf.P + q] = T;
   }
 }
 
@@ -895,76 +1129,7 @@ __global__ __launch_bounds__(256) void reference_kernel(MarchDev m, CamDev c, in
 
 }  // namespace
 
-int march_capacity(const MarchDev& m) {
-  double d2 = 0.0;
-  const int n[3] = {m.nx, m.ny, m.nz};
-  for (int a = 0; a < 3; ++a) d2 += (1.0 + 1.0 / n[a]) * (1.0 + 1.0 / n[a]);
-  return (int)std::ceil(std::sqrt(d2) / (double)m.h) + 2;
-}
-
-static size_t a256(size_t x) { return (x + 255) / 256 * 256; }
-static int bricks_along(int n) { return (n >> 2) + 1; }
-size_t bricks_bytes(int nx, int ny, int nz) {
-  return sizeof(float) * kBrickSlot * (size_t)bricks_along(nx) * bricks_along(ny) * bricks_along(nz);
-}
-
 constexpr size_t kLightSlots = 512;  // workgroups per band in march_lights (band order)
-// Bricked grids above this size (the eight XCDs' L2s together) take the z
-// order: measured at 256^3 / 1024^2, march 4.30 -> 2.73 ms; at 128^3 /
-// 256^2 the scatter's launch costs more than the order saves.
-constexpr size_t kZOrderBytes = (size_t)32 << 20;
-static int tiles_per_band(int W, int H) { return (((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile) + 7) / 8; }
-
-// Scratch: [K][P] planes t, A, T_{n-1}, T_top, T_bottom; per-pixel counts; the
-// counter block; 8 band work lists of (pixel, k) with room for every sample
-// of the band's pixels; in z order the [K][P] z-bucket plane and the
-// z-ordered list (room for every sample); the bricked grid unless the
-// caller supplies it.
-size_t march_scratch_bytes(const MarchDev& m, int K, int W, int H) {
-  const size_t P = (size_t)W * H, plane = a256(sizeof(float) * (size_t)K * P);
-  const size_t cap = (size_t)tiles_per_band(W, H) * kTile * kTile * K;
-  return 5 * plane + a256(sizeof(int) * P) + a256(kCounterBytes) + a256(8 * cap * sizeof(int2)) +
-         (m.zorder ? a256((size_t)K * P) + a256(sizeof(int2) * (size_t)K * P) : 0) +
-         (m.brick ? 0 : a256(bricks_bytes(m.nx, m.ny, m.nz)));
-}
-
-bool march_use_zorder(int work_order, int nx, int ny, int nz) {
-  if (work_order != LNM_ORDER_AUTO) return work_order == LNM_ORDER_Z;
-  return bricks_bytes(nx, ny, nz) > kZOrderBytes;
-}
-
-MarchBuf march_buffers(void* ws, const MarchDev& m, int K, int W, int H) {
-  char* p = static_cast<char*>(ws);
-  const size_t P = (size_t)W * H, plane = a256(sizeof(float) * (size_t)K * P);
-  MarchBuf b;
-  b.t = reinterpret_cast<float*>(p);
-  b.a = reinterpret_cast<float*>(p + plane);
-  b.tp = reinterpret_cast<float*>(p + 2 * plane);
-  b.tl = reinterpret_cast<float*>(p + 3 * plane);  // two planes
-  p += 5 * plane;
-  b.cnt = reinterpret_cast<int*>(p);
-  p += a256(sizeof(int) * P);
-  b.ctr = reinterpret_cast<int*>(p);
-  p += a256(kCounterBytes);
-  b.cap = (size_t)tiles_per_band(W, H) * kTile * kTile * K;
-  b.rec = reinterpret_cast<int2*>(p);
-  p += a256(8 * b.cap * sizeof(int2));
-  b.zb = nullptr;
-  b.srt = nullptr;
-  if (m.zorder) {
-    b.zb = reinterpret_cast<uint8_t*>(p);
-    p += a256((size_t)K * P);
-    b.srt = reinterpret_cast<int2*>(p);
-    p += a256(sizeof(int2) * (size_t)K * P);
-  }
-  b.brick = m.brick ? nullptr : reinterpret_cast<float*>(p);
-  b.nbx = bricks_along(m.nx);
-  b.nby = bricks_along(m.ny);
-  b.nbz = bricks_along(m.nz);
-  b.K = K;
-  b.P = (int)P;
-  return b;
-}
 
 hipError_t launch_relayout(const MarchDev& m, float* bricks, hipStream_t s) {
   const int nbx = bricks_along(m.nx), nby = bricks_along(m.ny), nbz = bricks_along(m.nz);
@@ -1009,6 +1174,19 @@ static int light_blocks_per_xcd() {
   return n;
 }
 
+// Cell-order light-march blocks per XCD: the CUs of one XCD (one block per CU).
+static int cell_blocks_per_xcd() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0, cus = 0;
+    n = hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus >= 8
+            ? cus / 8
+            : 32;
+  }
+  return n;
+}
+
 hipError_t launch_march(const MarchDev& m0, const CamDev& cam, const MarchBuf& buf, float* guide, hipStream_t s) {
   MarchDev m = m0;
   m.nbx = buf.nbx;
@@ -1023,7 +1201,13 @@ hipError_t launch_march(const MarchDev& m0, const CamDev& cam, const MarchBuf& b
     hipLaunchKernelGGL(march_balance, dim3(1), dim3(kBalanceThreads), 0, s, m, cam, tm, buf.ctr);
   }
   hipLaunchKernelGGL(march_primary, dim3(8 * tm.per_xcd), dim3(256), 0, s, m, cam, tm, buf, guide);
-  if (m.zorder) {
+  if (m.zorder == kOrderCells) {
+    // the scatter with one lane per pixel; the light marches with one
+    // workgroup per CU (the planes take most of its LDS)
+    hipLaunchKernelGGL(zsort_cells, dim3((buf.P + kSortPixels - 1) / kSortPixels), dim3(256), 0, s, buf);
+    hipLaunchKernelGGL(march_lights_cells, dim3(8 * cell_blocks_per_xcd()), dim3(kCellThreads),
+                       cell_planes_bytes(m.nx, m.ny), s, m, cam, buf);
+  } else if (m.zorder) {
     // the blocks resident at once; each loops over units of its XCD's range
     const int slots = (int)std::min<size_t>((buf.cap + 255) / 256, (size_t)light_blocks_per_xcd());
     hipLaunchKernelGGL(zsort_records, dim3(8 * slots), dim3(256), 0, s, buf);

@@ -1,5 +1,6 @@
 // Training entry points: forward with saved activations, backward through the
 // U-Net in reverse layer order, Adam, and repacking of the weights.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>

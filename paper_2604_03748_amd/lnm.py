@@ -20,7 +20,7 @@ FP32, BF16, FP8_E4M3 = 0, 1, 2
 ORTHOGRAPHIC, PERSPECTIVE = 0, 1
 QUAD_ALPHA, QUAD_RIEMANN = 0, 1
 LIGHTS_TOP_BOTTOM, LIGHTS_LEFT_RIGHT = 0, 1
-ORDER_AUTO, ORDER_BANDS, ORDER_Z = 0, 1, 2
+ORDER_AUTO, ORDER_BANDS, ORDER_Z, ORDER_CELLS = 0, 1, 2, 3
 
 EXPORTS = [
     "lnm_abi_struct_size", "lnm_version", "lnm_ctx_create", "lnm_ctx_destroy", "lnm_last_error",

@@ -58,21 +58,30 @@ def test_param_count_and_device_bytes(L):
 
 
 def test_work_order_choice_by_grid_size(L):
-    """lnm_march_workspace_bytes is host arithmetic, and the z order adds a
-    bucket byte and a list entry per record: the automatic order is the band
-    order for a 128^3 grid (18 MB of bricks) and the z order for a 256^3 grid
-    (141 MB, above the 32 MiB of the eight L2 caches)."""
+    """lnm_march_workspace_bytes is host arithmetic, and the z orders add a
+    bucket byte and a list entry per record: the automatic order for a 128^3
+    grid is the cell order with the top/bottom lights (a cell's two 130 x 130
+    planes fit in LDS) and the band order with the left/right lights (whose
+    marches leave their z cell); 192^3 and 256^3 grids (60 and 141 MB of
+    bricks, above the 32 MiB of the eight L2 caches) take the z order; the
+    cell order is refused where the planes do not fit."""
     from synth.scene import headline
 
     cam = L.make_camera(headline().camera)
     lib = L.lib()
-    for n, z_expected in ((128, False), (256, True)):
+
+    def ws(n, **kw):
         vol = L.Volume()
         vol.density, vol.nx, vol.ny, vol.nz, vol.sigma_scale, vol.bricks = 0x1000, n, n, n, 8.0, None
-        ws = {o: lib.lnm_march_workspace_bytes(C.byref(vol), C.byref(cam),
-                                               C.byref(L.make_params(4.0, work_order=o)))
-              for o in (L.ORDER_AUTO, L.ORDER_BANDS, L.ORDER_Z)}
-        assert ws[L.ORDER_Z] > ws[L.ORDER_BANDS] > 0, n
-        assert ws[L.ORDER_AUTO] == (ws[L.ORDER_Z] if z_expected else ws[L.ORDER_BANDS]), n
-    bad = L.make_params(4.0, work_order=3)
-    assert lib.lnm_march_workspace_bytes(C.byref(vol), C.byref(cam), C.byref(bad)) == 0
+        return lib.lnm_march_workspace_bytes(C.byref(vol), C.byref(cam), C.byref(L.make_params(4.0, **kw)))
+
+    for n in (128, 192, 256):
+        assert ws(n, work_order=L.ORDER_Z) > ws(n, work_order=L.ORDER_BANDS) > 0, n
+    # cell order: the z orders' bucket plane and sorted list, no band lists
+    assert ws(128, work_order=L.ORDER_Z) > ws(128, work_order=L.ORDER_CELLS) > ws(128, work_order=L.ORDER_BANDS)
+    assert ws(128) == ws(128, work_order=L.ORDER_CELLS)
+    assert ws(128, light_set=L.LIGHTS_LEFT_RIGHT) == ws(128, work_order=L.ORDER_BANDS)
+    assert ws(192) == ws(192, work_order=L.ORDER_Z)  # 60 MB of bricks: z layers
+    assert ws(192, work_order=L.ORDER_CELLS) == 0 and ws(256, work_order=L.ORDER_CELLS) == 0
+    assert ws(256) == ws(256, work_order=L.ORDER_Z)
+    assert ws(128, work_order=4) == 0

@@ -40,7 +40,7 @@ def _both(ctx, orc, levels, base, B, H, W, seed, precision=0, init="random"):
 
 
 @pytest.mark.parametrize("levels,base,B,H,W", [(3, 16, 2, 32, 32), (4, 32, 1, 24, 40), (3, 48, 1, 16, 24),
-                                               (2, 64, 2, 10, 6)])
+                                               (2, 64, 2, 10, 6), (4, 32, 2, 72, 104), (3, 64, 1, 40, 72)])
 def test_adapters_fp32_match_oracle(ctx, orc, levels, base, B, H, W):
     lm, ex, rlm, rex = _both(ctx, orc, levels, base, B, H, W, seed=levels * 7 + base)
     d_lm, d_ex = np.abs(lm - rlm).max(), np.abs(ex - rex).max()

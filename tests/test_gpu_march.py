@@ -163,10 +163,11 @@ def test_prebuilt_bricks(ctx, orc):
 
 
 def test_work_orders_agree(ctx, orc):
-    """The light marches' work order (screen bands, or records sorted by
-    brick layer and taken by each XCD in turn) changes nothing in the
-    guiding map: bit for bit equal, on cameras whose side lights stay in z
-    planes and on ones whose lights do not (view along z, left/right set)."""
+    """The light marches' work order (screen bands, records sorted by brick
+    layer and taken by each XCD in turn, or records sorted by z cell with the
+    cell's grid planes read from LDS) changes nothing in the guiding map: bit
+    for bit equal, on cameras whose side lights stay in z planes and on ones
+    whose lights do not (view along z, left/right set)."""
     from paper_2604_03748_amd import lnm
 
     wl = headline()
@@ -187,13 +188,22 @@ def test_work_orders_agree(ctx, orc):
         a = _run(ctx, vol, ss, cam, step, work_order=lnm.ORDER_BANDS, **kw)
         b = _run(ctx, vol, ss, cam, step, work_order=lnm.ORDER_Z, **kw)
         assert np.array_equal(a, b), what
-        assert np.array_equal(a, _run(ctx, vol, ss, cam, step, **kw)), what  # auto: bands on these grids
+        c = _run(ctx, vol, ss, cam, step, work_order=lnm.ORDER_CELLS, **kw)
+        d = np.abs(a - c)
+        log(f"  cells vs bands: max abs {d.max():.3g} over {int((d > 0).sum())} values")
+        assert np.array_equal(a, c), what
+        assert np.array_equal(a, _run(ctx, vol, ss, cam, step, **kw)), what  # auto (bands or cells)
     dens = to_dev(ragged)
     cam = cases[1][3]
     pb, pz = lnm.make_params(1.5, work_order=lnm.ORDER_BANDS), lnm.make_params(1.5, work_order=lnm.ORDER_Z)
     assert ctx.march_workspace_bytes(dens, 6.0, cam, pz) > ctx.march_workspace_bytes(dens, 6.0, cam, pb)
     with pytest.raises(lnm.LnmError):
-        ctx.march(dens, 6.0, cam, lnm.make_params(1.5, work_order=3))
+        ctx.march(dens, 6.0, cam, lnm.make_params(1.5, work_order=4))
+    # cell order needs a cell's two grid planes in LDS: 144 x 144 planes do not fit
+    big = to_dev(make_volume((16, 144, 144), 3, 1))
+    with pytest.raises(lnm.LnmError) as e:
+        ctx.march(big, 6.0, cam, lnm.make_params(1.5, work_order=lnm.ORDER_CELLS))
+    assert e.value.status == lnm.LNM_ERR_UNSUPPORTED
 
 
 def test_march_batch_equals_single_marches(ctx):
