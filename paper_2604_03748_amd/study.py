@@ -2,26 +2,59 @@
 guiding-light ablation and the density-scale robustness check (Section 5),
 and the gain of the trained network over the method without it.
 
-Data: seeded synthetic scenes (32^3 volumes of 6 Gaussian blobs seen from a
-random orbit, perspective or orthographic), guiding maps from lnm_march and
-targets from the fine-step reference lightmaps (lnm_reference_lightmaps, in
-sRGB).  Training: lnm_train_step (Adam) on the fp32 network.  Quality: PSNR
-of the predicted six lightmaps against the references on held-out scenes."""
+Two data setups, both seeded and synthetic:
+* SMALL: 32^3 volumes of 6 Gaussian blobs seen from a random orbit
+  (perspective 40 degrees or orthographic) at 64x64, step 2 voxels, the
+  3-level base-16 network;
+* HEADLINE: the configured frame's scale, 128^3 volumes of 24 blobs + 3-octave
+  noise seen by a 60-degree perspective camera at distance 2.5 from a random
+  direction at 256x256, step 4 voxels, the 4-level base-32 network.
+Guiding maps come from lnm_march and targets from the fine-step reference
+lightmaps (lnm_reference_lightmaps, in sRGB).  Training: lnm_train_step
+(Adam) on the fp32 network.  Quality: PSNR of the predicted six lightmaps
+against the references on held-out scenes."""
 import math
 from dataclasses import dataclass
 
 import numpy as np
 
 from synth.rng import substream
-from synth.scene import Camera, ORTHOGRAPHIC, PERSPECTIVE, make_volume
+from synth.scene import Camera, ORTHOGRAPHIC, PERSPECTIVE, make_volume, make_volume_torch
 from synth.weights import he_normal_params
 
 from . import lnm
 
-GRID, RES, STEP, REF_STEP, SIGMA = 32, 64, 2.0, 0.5, 8.0
-LEVELS, BASE = 3, 16
-TRAIN_SEEDS = range(100, 196)
-TEST_SEEDS = range(1000, 1016)
+SIGMA = 8.0
+
+
+@dataclass(frozen=True)
+class Setup:
+    grid: int
+    blobs: int
+    noise: float
+    res: int
+    step: float      # march step (voxels)
+    ref_step: float  # reference lightmap step (voxels)
+    levels: int
+    base: int
+    fov: float
+    ortho_mix: bool  # half the cameras orthographic
+    train_seeds: range
+    test_seeds: range
+    lr: float        # Adam learning rate
+
+
+# The paper trains with Adam at lr 1e-3 (Section 5); from He-normal weights
+# the 4-level base-32 network at 256x256 collapses at that rate into a
+# constant prediction (training loss stuck at the targets' variance), and
+# trains at 3e-4.
+SMALL = Setup(32, 6, 0.0, 64, 2.0, 0.5, 3, 16, 40.0, True, range(100, 196), range(1000, 1016), 1e-3)
+HEADLINE = Setup(128, 24, 0.3, 256, 4.0, 0.5, 4, 32, 60.0, False, range(2000, 2096), range(5000, 5032), 3e-4)
+
+# the small setup's values, as module constants
+GRID, RES, STEP, REF_STEP = SMALL.grid, SMALL.res, SMALL.step, SMALL.ref_step
+LEVELS, BASE = SMALL.levels, SMALL.base
+TRAIN_SEEDS, TEST_SEEDS = SMALL.train_seeds, SMALL.test_seeds
 
 # Guiding-light configurations of the ablation: (light_w, light_set)
 LIGHT_CONFIGS = {
@@ -31,30 +64,37 @@ LIGHT_CONFIGS = {
 }
 
 
-def scene(seed: int):
-    """32^3 volume of 6 blobs and a camera on a random orbit around it."""
-    vol = make_volume(GRID, 6, seed)
+def camera(seed: int, setup: Setup = SMALL) -> Camera:
+    """A camera at distance 2.5 from the cube centre on a random orbit."""
     u = substream(seed, "view").uniform(3)
     az, el = 2 * math.pi * u[0], 0.5 * (u[1] - 0.5)
     d = 2.5
     eye = (0.5 + d * math.cos(el) * math.cos(az), 0.5 + d * math.sin(el), 0.5 + d * math.cos(el) * math.sin(az))
-    proj = PERSPECTIVE if u[2] < 0.5 else ORTHOGRAPHIC
-    cam = Camera(proj, eye, fov_y_deg=40.0, ortho_half_extent=0.8, width=RES, height=RES)
-    return vol, cam
+    proj = PERSPECTIVE if (not setup.ortho_mix or u[2] < 0.5) else ORTHOGRAPHIC
+    return Camera(proj, eye, fov_y_deg=setup.fov, ortho_half_extent=0.8, width=setup.res, height=setup.res)
 
 
-def make_set(ctx, seeds, light_w=(1.0, 1.0, 1.0), light_set=0, density_scale=1.0):
-    """Guiding maps [N][RES][RES][3] and sRGB reference lightmaps [N][RES][RES][6]
+def scene(seed: int):
+    """SMALL setup: 32^3 volume of 6 blobs (host array) and its camera."""
+    return make_volume(GRID, 6, seed), camera(seed, SMALL)
+
+
+def make_set(ctx, seeds, light_w=(1.0, 1.0, 1.0), light_set=0, density_scale=1.0, setup: Setup = SMALL):
+    """Guiding maps [N][res][res][3] and sRGB reference lightmaps [N][res][res][6]
     (device tensors).  density_scale multiplies the extinction of both."""
     import torch
 
     gs, ts = [], []
     for s in seeds:
-        vol, cam = scene(s)
-        dens = torch.as_tensor(vol, device="cuda")
+        if setup is SMALL:
+            dens = torch.as_tensor(make_volume(setup.grid, setup.blobs, s), device="cuda")
+        else:
+            dens = make_volume_torch(setup.grid, setup.blobs, s, setup.noise, device="cuda")
+        cam = camera(s, setup)
         ss = SIGMA * density_scale
-        gs.append(ctx.march(dens, ss, cam, lnm.make_params(STEP, seed=s, light_w=light_w, light_set=light_set)))
-        ts.append(ctx.reference_lightmaps(dens, ss, cam, REF_STEP, srgb=True))
+        gs.append(ctx.march(dens, ss, cam, lnm.make_params(setup.step, seed=s, light_w=light_w,
+                                                            light_set=light_set)))
+        ts.append(ctx.reference_lightmaps(dens, ss, cam, setup.ref_step, srgb=True))
     return torch.stack(gs), torch.stack(ts)
 
 
@@ -69,11 +109,15 @@ class TrainResult:
     losses: list
 
 
-def train(ctx, g, t, steps=600, batch=12, lr=1e-3, seed=0, init_seed=0) -> TrainResult:
-    """Adam on random minibatches drawn with a seeded generator."""
+def train(ctx, g, t, steps=600, batch=12, lr=None, seed=0, init_seed=0, setup: Setup = SMALL,
+          progress=None) -> TrainResult:
+    """Adam on random minibatches drawn with a seeded generator (lr: the
+    setup's unless given); progress(step, loss) is called every 100 steps
+    when given."""
     import torch
 
-    tr = lnm.Trainer(ctx, LEVELS, BASE, he_normal_params(LEVELS, BASE, seed=init_seed))
+    lr = setup.lr if lr is None else lr
+    tr = lnm.Trainer(ctx, setup.levels, setup.base, he_normal_params(setup.levels, setup.base, seed=init_seed))
     rng = np.random.default_rng(seed)
     n = g.shape[0]
     loss = torch.empty(1, dtype=torch.float32, device=g.device)
@@ -83,6 +127,8 @@ def train(ctx, g, t, steps=600, batch=12, lr=1e-3, seed=0, init_seed=0) -> Train
         tr.step(g[idx].contiguous(), t[idx].contiguous(), lr=lr, loss=loss)
         if it % 100 == 0 or it == steps - 1:
             hist.append(float(loss.cpu()[0]))
+            if progress:
+                progress(it, hist[-1])
     return TrainResult(tr, hist)
 
 

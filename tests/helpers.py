@@ -14,7 +14,12 @@ ERT_EPS = 1e-6
 FLOOR_L = 3 * ERT_EPS
 FLOOR_T = ERT_EPS
 # D is a threshold crossing: pixels whose deciding sample is within this
-# fraction of tau_D of the threshold may legitimately differ by a step.
+# fraction of tau_D of the threshold may legitimately differ by a step.  An
+# fp32 sample position is off by about |eye| 2^-24 (1.5e-7 world units at
+# distance 2.5); times the steepest density gradient of the synthetic fields
+# (sigma_scale 8 x peak 2 over radius 0.05, plus the noise octaves) that moves
+# sigma by up to about 3e-5 = 3e-4 tau_D, so the margin is 1e-3 tau_D.  At
+# most 0.5% of a map's pixels may be flagged (measured 0 to 0.3%).
 D_MARGIN = 1e-3
 
 # fp32 network against fp64: max |d lightmap| and |d logit| / max(1, |logit|).
@@ -98,7 +103,7 @@ def check_march(g_gpu, g_ref, margin, depth_tau, step_world, what="", allow=None
     assert okL.all(), (what, summary, np.argwhere(~okL)[:5])
     assert okT.all(), (what, summary, np.argwhere(~okT)[:5])
     assert okD.all(), (what, summary, np.argwhere(~okD)[:5])
-    assert flagged.mean() <= 0.01, summary
+    assert flagged.mean() <= 0.005, summary
     assert needed <= 0.01 * dL.size, summary
     return summary
 

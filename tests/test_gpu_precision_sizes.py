@@ -1,13 +1,23 @@
-"""The precision forms at the configured full sizes: the 512x512 guiding map
-of the precision configuration (headline volume and camera) through the
-fp32, bf16 and fp8 networks against the fp64 oracle's network on the same
-guiding map, and the dynamic scene's 1024x1024 frame through the base-48
-bf16 network against the fp32 one (a property that holds at any size: the
-two differ only by the bf16 roundings)."""
+"""The precision forms at the configured full sizes.
+
+* The 256x256 and 512x512 guiding maps of the headline volume and camera
+  (computed by the oracle's march) through the fp32, bf16 and fp8 forms of
+  the configured network (4 levels, base 32) with trained weights
+  (tests/golden/trained_L4b32.npy, trained by the oracle) against the fp64
+  oracle's network on the same map, at the bounds stated per lightmap
+  channel; the same with untrained He-normal weights as information
+  (gross-failure bounds only).
+* The dynamic scene's 1024x1024 frame through the base-48 network: fp32 and
+  bf16 against the oracle's network on a 256x256 window of the same guiding
+  map (the window's interior does not depend on its border), and the whole
+  bf16 frame against the fp32 one (the two differ only by the bf16
+  roundings, a property that holds at any size)."""
+import os
+
 import numpy as np
 import pytest
 
-from synth.scene import dynamic, headline, make_volume_torch, orbit_camera
+from synth.scene import dynamic, headline, make_volume, make_volume_torch, orbit_camera
 from synth.weights import he_normal_params
 from tests.helpers import NET_ABS, log, to_dev, to_host
 
@@ -15,6 +25,10 @@ pytestmark = pytest.mark.gpu
 
 BF16_MAX_ABS_UNTRAINED = 4e-2  # He-normal networks, per channel (see test_gpu_bf16)
 FP8_MEAN_ABS_UNTRAINED = 0.05  # gross-failure bound for untrained fp8 networks (see test_gpu_fp8)
+# trained configured network, per lightmap channel
+BF16_MAX_ABS = 2e-2
+FP8_MAX_ABS, FP8_MEAN_ABS = 6e-2, 1e-2
+TRAINED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "trained_L4b32.npy")
 
 
 @pytest.fixture(scope="module")
@@ -29,15 +43,49 @@ def per_channel(lm, ref):
     return d.max(axis=0), d.mean(axis=0)
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("res", [256, 512])
+def test_trained_configured_network(ctx, orc, res):
+    """fp8 activation maxima are calibrated with the fp32 network on four
+    other scenes of the same recipe (seeds 1-4), not on the tested frame."""
+    from paper_2604_03748_amd import lnm
+
+    wl = headline(res=res)
+    log(f"trained L4b32 precision forms on {wl.name}")
+    params = np.load(TRAINED)
+    g = orc.march(wl.volume(), 8.0, wl.camera, wl.step_voxels, seed=0)[0].astype(np.float32)
+    ref, _ = orc.unet_forward(params, wl.levels, wl.base, g.astype(np.float64))
+    n32 = lnm.Net(ctx, wl.levels, wl.base, params)
+    calib = [ctx.march(to_dev(headline(seed=s, res=res).volume()), 8.0, wl.camera,
+                       lnm.make_params(wl.step_voxels, seed=s)) for s in (1, 2, 3, 4)]
+    amax = np.max([n32.calibrate_amax(c) for c in calib], axis=0)
+    nets = {"fp32": n32, "bf16": lnm.Net(ctx, wl.levels, wl.base, params, precision=lnm.BF16),
+            "fp8": lnm.Net(ctx, wl.levels, wl.base, params, precision=lnm.FP8_E4M3, act_scales=amax)}
+    errs = {}
+    for k, net in nets.items():
+        mx, mean = per_channel(to_host(net.infer(to_dev(g))), ref)
+        errs[k] = (mx, mean)
+        log(f"trained {k} at {res}x{res}: max abs per channel {np.round(mx, 5).tolist()}, "
+            f"mean {np.round(mean, 6).tolist()}")
+    assert np.all(errs["fp32"][0] <= NET_ABS)
+    assert np.all(errs["bf16"][0] <= BF16_MAX_ABS), errs["bf16"][0]
+    assert np.all(errs["fp8"][0] <= FP8_MAX_ABS), errs["fp8"][0]
+    assert np.all(errs["fp8"][1] <= FP8_MEAN_ABS), errs["fp8"][1]
+    assert errs["fp8"][0].max() > errs["bf16"][0].max() > errs["fp32"][0].max()
+
+
 def test_precision_forms_at_512(ctx, orc):
+    """Untrained He-normal weights: the errors are reported; only gross
+    failures are rejected."""
     from paper_2604_03748_amd import lnm
 
     wl = headline(res=512)
     log(f"precision forms on {wl.name}")
     params = he_normal_params(wl.levels, wl.base, seed=0, bias="uniform")
-    dens = to_dev(wl.volume())
-    g = ctx.march(dens, 8.0, wl.camera, lnm.make_params(wl.step_voxels, seed=0))
-    ref, _ = orc.unet_forward(params, wl.levels, wl.base, to_host(g).astype(np.float64))
+    vol = wl.volume()
+    dens = to_dev(vol)
+    g = orc.march(vol, 8.0, wl.camera, wl.step_voxels, seed=0)[0].astype(np.float32)
+    ref, _ = orc.unet_forward(params, wl.levels, wl.base, g.astype(np.float64))
     n32 = lnm.Net(ctx, wl.levels, wl.base, params)
     calib = [ctx.march(dens, 8.0, wl.camera, lnm.make_params(wl.step_voxels, seed=0, frame=f)) for f in (1, 2)]
     amax = np.max([n32.calibrate_amax(c) for c in calib], axis=0)
@@ -45,7 +93,7 @@ def test_precision_forms_at_512(ctx, orc):
             "fp8": lnm.Net(ctx, wl.levels, wl.base, params, precision=lnm.FP8_E4M3, act_scales=amax)}
     errs = {}
     for k, net in nets.items():
-        mx, mean = per_channel(to_host(net.infer(g)), ref)
+        mx, mean = per_channel(to_host(net.infer(to_dev(g))), ref)
         errs[k] = (mx, mean)
         log(f"{k} at 512x512: max abs per channel {np.round(mx, 5).tolist()}, mean {np.round(mean, 6).tolist()}")
     assert np.all(errs["fp32"][0] <= NET_ABS)
@@ -73,3 +121,37 @@ def test_dynamic_frame_bf16_against_fp32(ctx):
         f"mean {np.round(mean, 6).tolist()}")
     assert np.all(mx <= BF16_MAX_ABS_UNTRAINED)
     assert mx.max() > 1e-5
+
+
+WINDOW, MARGIN = 256, 64  # outputs 48+ pixels inside a window are border-free (tests/test_oracle_unet.py)
+
+
+@pytest.mark.timeout(600)
+def test_dynamic_network_against_oracle_on_a_window(ctx, orc):
+    """Frame 5 of the dynamic scene: the oracle's guiding map (1024x1024,
+    256^3 grid with the obstacle) through the base-48 network in fp32 and
+    bf16 on the GPU, and through the oracle's network on a 256x256 window
+    at offset (384, 512) (multiples of 8, so the three 2x2 poolings align);
+    the window's interior 128x128 is compared."""
+    from paper_2604_03748_amd import lnm
+
+    wl = dynamic()
+    log(f"base-48 network on {wl.name} against the oracle on a {WINDOW}x{WINDOW} window")
+    vol = make_volume(wl.grid, wl.n_blobs, wl.seed, wl.noise_amp, frame=5, obstacle_radius=0.15)
+    g = orc.march(vol, 8.0, orbit_camera(5), wl.step_voxels, seed=0, frame=5)[0].astype(np.float32)
+    params = he_normal_params(wl.levels, wl.base, seed=0, bias="uniform")
+    y0, x0 = 384, 512
+    ref, _ = orc.unet_forward(params, wl.levels, wl.base, g[y0:y0 + WINDOW, x0:x0 + WINDOW].astype(np.float64))
+    inner = (slice(y0 + MARGIN, y0 + WINDOW - MARGIN), slice(x0 + MARGIN, x0 + WINDOW - MARGIN))
+    ref = ref[MARGIN:WINDOW - MARGIN, MARGIN:WINDOW - MARGIN]
+    gd = to_dev(g)
+    errs = {}
+    for k, prec in (("fp32", lnm.FP32), ("bf16", lnm.BF16)):
+        lm = to_host(lnm.Net(ctx, wl.levels, wl.base, params, precision=prec).infer(gd))
+        mx, mean = per_channel(lm[inner], ref)
+        errs[k] = mx
+        log(f"{k} base 48, 1024x1024, window interior: max abs per channel {np.round(mx, 6).tolist()}, "
+            f"mean {np.round(mean, 7).tolist()}")
+    assert np.all(errs["fp32"] <= NET_ABS), errs["fp32"]
+    assert np.all(errs["bf16"] <= BF16_MAX_ABS_UNTRAINED), errs["bf16"]
+    assert errs["bf16"].max() > errs["fp32"].max()
