@@ -350,10 +350,13 @@ def precision_report(lnm, ctx, wl, params, dens, weights="He-normal seed 0 (untr
 
 
 # the conv kernels, their tiling / split-K choice (conv_layer_tiling in
-# conv.hip) and the head epilogue; the march kernels
+# plan.hip) and the head epilogue; the march kernels and their work order
+# and buffers (plan.hip)
 CONV_SOURCES = ("paper_2604_03748_amd/csrc/conv.hip", "paper_2604_03748_amd/csrc/conv_bf16.hip",
-                "paper_2604_03748_amd/csrc/conv_fp8.hip", "paper_2604_03748_amd/csrc/head.h")
-MARCH_SOURCES = ("paper_2604_03748_amd/csrc/march.hip", "paper_2604_03748_amd/csrc/ray.h")
+                "paper_2604_03748_amd/csrc/conv_fp8.hip", "paper_2604_03748_amd/csrc/head.h",
+                "paper_2604_03748_amd/csrc/plan.hip")
+MARCH_SOURCES = ("paper_2604_03748_amd/csrc/march.hip", "paper_2604_03748_amd/csrc/ray.h",
+                 "paper_2604_03748_amd/csrc/plan.hip")
 
 
 def source_hash(sources=CONV_SOURCES) -> str:

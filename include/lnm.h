@@ -415,6 +415,33 @@ LNM_API lnm_status lnm_trainer_save(lnm_trainer tr, float* host_m, float* host_v
                                     void* stream);
 LNM_API lnm_status lnm_trainer_load(lnm_trainer tr, const float* host_params, const float* host_m,
                                     const float* host_v, int32_t step, size_t n_params, void* stream);
+/* Channel adapters (Section 4.3) trained with the network: once attached
+ * (before the first step), lnm_train_grad and lnm_train_step compute the
+ * loss on the adapters' lightmaps in place of the plain head's (same loss as
+ * above; the alpha/emissive group has no target, so its gradient is zero,
+ * and so is the unused head's), back-propagate through the four NAFBlocks
+ * into the trunk, and lnm_train_step applies Adam to both parameter sets
+ * with the same step count.  Backward of the blocks: layer norm dx = r (dxh
+ * - mean(dxh) - xh mean(dxh xh)) with xh the normalised input and r = 1 /
+ * sqrt(var + 1e-6); the channel attention's mean over each image passes its
+ * gradient back divided by H W; the depthwise conv's input gradient uses
+ * the mirrored taps; every sum runs in a fixed order.  The adapters' state
+ * (parameters, gradient, Adam moments, each 256-byte aligned) lives in
+ * state_buf (device, lnm_trainer_adapters_state_bytes, 256-byte aligned);
+ * parameters: lnm_adapters_param_count(base) floats in the order of
+ * lnm_adapters_create.  Checkpoints (lnm_trainer_save/load) cover the trunk
+ * only.  LNM_ERR_UNSUPPORTED for a base width other than 16, 32, 48, 64;
+ * LNM_ERR_ARG if adapters are attached twice or after a step. */
+LNM_API size_t lnm_trainer_adapters_state_bytes(int32_t c);
+LNM_API lnm_status lnm_trainer_attach_adapters(lnm_trainer tr, const float* host_params, size_t n_params,
+                                               void* state_buf, size_t state_bytes, void* stream);
+/* Workspace of lnm_train_grad / lnm_train_step for this trainer (with its
+ * adapters, if attached); 0 for invalid sizes. */
+LNM_API size_t lnm_trainer_workspace_bytes(lnm_trainer tr, int32_t batch, int32_t H, int32_t W);
+/* The adapters' current parameters to host memory (synchronises), and the
+ * last computed adapter gradient to device memory (n_params floats). */
+LNM_API lnm_status lnm_trainer_read_adapters(lnm_trainer tr, float* host_params, size_t n_params, void* stream);
+LNM_API lnm_status lnm_trainer_adapter_grad(lnm_trainer tr, float* grad, size_t n_params, void* stream);
 /* Forward pass with the trainer's current weights (same as lnm_infer on an
  * fp32 net holding those weights). */
 LNM_API lnm_status lnm_trainer_infer(lnm_ctx ctx, lnm_trainer tr, int32_t batch, int32_t H, int32_t W,

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblnm.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 SOURCES = ["api.hip", "march.hip", "conv.hip", "conv_bf16.hip", "conv_fp8.hip", "train.hip", "train_api.hip", "shadow.hip",
-           "adapters.hip", "frame_static.hip", "plan.hip"]
+           "adapters.hip", "adapters_train.hip", "frame_static.hip", "plan.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

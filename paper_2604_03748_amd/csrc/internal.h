@@ -239,7 +239,35 @@ struct AdapterArgs {
 constexpr int kAdaptTileY = 8, kAdaptTileX = 32;
 int adapter_tiles(int H, int W);
 bool adapter_width_supported(int c);
+// Training of the adapters with the network (adapters_train.hip): the three
+// groups with a lightmap target; per-pixel tensors [3][P][..]
+struct AdapterTrainArgs {
+  AdapterArgs f;           // forward (feat: the fp32 decoder output), dsave and msave set
+  const float* target;     // [P][6] sRGB
+  float* grad;             // adapter parameter gradient (parameter-file order), written
+  float *dgt, *dyf, *dxf;  // [3][P][c] gate gradient (tail side), features' gradient (tail, front side)
+  float *d5, *x5, *d3, *x3, *x4, *x1;  // [3][P][c] deltas and inputs of the 1x1 convolutions
+  float *d4, *d1;          // [3][P][2c]
+  float* tpart;            // [3][B * tpi][11c + 4] tail workgroup sums
+  float* fpart;            // [3][B][n_blk][24c] front workgroup sums
+  float* dmh;              // [B][4][c] image-mean term of the gate gradient
+  float* lossg;            // [3] squared-error sums per group
+  float* loss;             // the loss (1 float)
+  int tpi;                 // tail workgroups per image (adapter_tail_blocks_per_image)
+  float inv_n;             // 1 / (P * 6)
+};
+constexpr int kAdaptWgradChunk = 1024;  // pixels per partial sum of a 1x1 weight gradient
+int adapter_tail_blocks_per_image(int H, int W);
+size_t adapter_wgrad_partial_bytes(size_t P, int c);
+// adapters' forward (keeping d, m), backward, weight gradients, and the
+// features' gradient through the decoder's ReLU into g_last
+hipError_t launch_adapters_train(int c, const AdapterTrainArgs& t, const float* y_last, float* g_last, float* wpart,
+                                 hipStream_t s);
+hipError_t launch_fill_zero(float* p, long n, hipStream_t s);
 hipError_t launch_adapters(int c, const AdapterArgs& a, int in_type, hipStream_t s);
+// the first two kernels only (v, the tile sums, the attention scales; with
+// dsave and msave set, also d and m)
+hipError_t launch_adapters_front(int c, const AdapterArgs& a, int in_type, hipStream_t s);
 
 // ---------------------------------------------------------------- shadows
 struct ShadowArgs {
@@ -379,4 +407,9 @@ struct lnm_trainer_s {
   std::vector<size_t> dgrad_off;       // byte offset of each transposed weight block in the state
   float* zeros;          // zero bias for the data-gradient convolutions
   int step;
+  // channel adapters trained with the network (attached before the first
+  // step): width, parameter count, flat parameters, gradient, Adam moments
+  int ad_c = 0;
+  size_t ad_n = 0;
+  float *ad_p = nullptr, *ad_g = nullptr, *ad_m = nullptr, *ad_v = nullptr;
 };

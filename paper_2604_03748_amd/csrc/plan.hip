@@ -147,6 +147,12 @@ LayerTiling conv_layer_tiling(const lnm_net_s* net, int i, int B, int h, int w) 
 // ---------------------------------------------------------------- channel adapters
 bool adapter_width_supported(int c) { return c == 16 || c == 32 || c == 48 || c == 64; }
 
+int adapter_tail_blocks_per_image(int H, int W) { return (H * W + 255) / 256; }
+
+size_t adapter_wgrad_partial_bytes(size_t P, int c) {
+  return sizeof(float) * ((P + kAdaptWgradChunk - 1) / kAdaptWgradChunk) * 2 * (size_t)c * c;
+}
+
 int adapter_tiles(int H, int W) {
   return ((H + kAdaptTileY - 1) / kAdaptTileY) * ((W + kAdaptTileX - 1) / kAdaptTileX);
 }

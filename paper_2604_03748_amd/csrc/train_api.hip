@@ -84,15 +84,23 @@ bool state_layout(int levels, int base, StateLayout* s, std::string* why) {
   return true;
 }
 
+// workspace of the adapters' training (offsets; per-pixel tensors of the
+// three groups with a lightmap target, forward tensors of all four)
+struct AdapterTrainPlan {
+  size_t v, dsave, part, sca, msave, dgt, dyf, dxf, d5, x5, d3, x3, x4, x1, d4, d1, tpart, fpart, dmh, lossg, wpart;
+  int n_blk, tpi;
+};
+
 struct TrainPlan {
   Plan fwd;
   size_t g_base, lm, dz, dx, part, colpart, losspart, loss, bytes;
   std::vector<int> tiles_per_group;
+  AdapterTrainPlan ad;
 };
 
 constexpr size_t kPartialBudget = 48u << 20;  // bytes of weight-gradient partial sums per layer
 
-TrainPlan train_plan(const lnm_net_s* net, int B, int H, int W) {
+TrainPlan train_plan(const lnm_net_s* net, int B, int H, int W, int ad_c = 0) {
   TrainPlan t;
   t.fwd = plan_workspace(net, B, H, W);
   const auto sch = schedule(net->levels);
@@ -128,6 +136,26 @@ TrainPlan train_plan(const lnm_net_s* net, int B, int H, int W) {
   t.colpart = take(sizeof(float) * kColsumBlocks * maxc);
   t.losspart = take(sizeof(float) * kLossBlocks);
   t.loss = take(sizeof(float));
+  t.ad = AdapterTrainPlan{};
+  if (ad_c > 0) {
+    AdapterTrainPlan& a = t.ad;
+    const size_t c = ad_c, f = sizeof(float);
+    a.n_blk = adapter_tiles(H, W);
+    a.tpi = adapter_tail_blocks_per_image(H, W);
+    a.v = take(f * 4 * P * c);
+    a.dsave = take(f * 4 * P * 2 * c);
+    a.part = take(f * (size_t)B * 4 * c * a.n_blk);
+    a.sca = take(f * (size_t)B * 4 * c);
+    a.msave = take(f * (size_t)B * 4 * c);
+    for (size_t* o : {&a.dgt, &a.dyf, &a.dxf, &a.d5, &a.x5, &a.d3, &a.x3, &a.x4, &a.x1}) *o = take(f * 3 * P * c);
+    a.d4 = take(f * 3 * P * 2 * c);
+    a.d1 = take(f * 3 * P * 2 * c);
+    a.tpart = take(f * 3 * (size_t)B * a.tpi * (11 * c + 4));
+    a.fpart = take(f * 3 * (size_t)B * a.n_blk * 24 * c);
+    a.dmh = take(f * (size_t)B * 4 * c);
+    a.lossg = take(f * 4);
+    a.wpart = take(adapter_wgrad_partial_bytes(P, ad_c));
+  }
   t.bytes = align256(off);
   return t;
 }
@@ -156,7 +184,7 @@ lnm_status check_train(lnm_ctx ctx, lnm_trainer tr, int B, int H, int W, const f
   const int div = 1 << (tr->net.levels - 1);
   if (H % div || W % div) return fail(LNM_ERR_SHAPE, "H and W must be divisible by 2^(levels-1)");
   if ((double)B * H * W > 2.0e9 / 64) return fail(LNM_ERR_SHAPE, "batch x H x W too large");
-  const size_t need = train_plan(&tr->net, B, H, W).bytes;
+  const size_t need = train_plan(&tr->net, B, H, W, tr->ad_c).bytes;
   if (!ws || ws_bytes < need) return fail(LNM_ERR_SHAPE, "workspace too small: need " + std::to_string(need));
   return LNM_OK;
 }
@@ -164,7 +192,7 @@ lnm_status check_train(lnm_ctx ctx, lnm_trainer tr, int B, int H, int W, const f
 lnm_status grad_impl(lnm_ctx ctx, lnm_trainer tr, int B, int H, int W, const float* guide, const float* target,
                      char* ws, hipStream_t s) {
   const lnm_net_s* net = &tr->net;
-  const TrainPlan tp = train_plan(net, B, H, W);
+  const TrainPlan tp = train_plan(net, B, H, W, tr->ad_c);
   const auto sch = schedule(net->levels);
   const size_t P = (size_t)B * H * W;
   float* lm = reinterpret_cast<float*>(ws + tp.lm);
@@ -175,14 +203,64 @@ lnm_status grad_impl(lnm_ctx ctx, lnm_trainer tr, int B, int H, int W, const flo
   float* part = reinterpret_cast<float*>(ws + tp.part);
   float* colpart = reinterpret_cast<float*>(ws + tp.colpart);
 
-  lnm_status st = run_unet(ctx, net, B, H, W, guide, lm, nullptr, ws, s);
-  if (st) return st;
-  LNM_HIP_CHECK(launch_loss(lm, target, dz, reinterpret_cast<float*>(ws + tp.losspart), (long)P * 6,
-                            reinterpret_cast<float*>(ws + tp.loss), s));
   const int nl = (int)net->layers.size(), hi = nl - 1, last = nl - 2;
   const LayerDesc& hd = net->layers[hi];
-  LNM_HIP_CHECK(launch_head_bwd(dz, reinterpret_cast<const float*>(net->dev + hd.w_off), Y(last), (long)P, hd.ci,
-                                G(last), tr->g + tr->flat_w[hi], tr->g + tr->flat_b[hi], nullptr, s));
+  if (tr->ad_c) {
+    // the adapters in place of the head: trunk forward, the adapters' forward
+    // and backward (their gradient into ad_g), the features' gradient into
+    // G(last); the unused head takes a zero gradient
+    lnm_status st = run_unet(ctx, net, B, H, W, guide, nullptr, nullptr, ws, s);
+    if (st) return st;
+    const AdapterTrainPlan& ap = tp.ad;
+    auto F = [&](size_t off) { return reinterpret_cast<float*>(ws + off); };
+    AdapterTrainArgs t{};
+    AdapterArgs& a = t.f;
+    a.feat = Y(last);
+    a.feat_scale = 1.0f;
+    a.prm = tr->ad_p;
+    a.B = B;
+    a.H = H;
+    a.W = W;
+    a.P = P;
+    a.v = F(ap.v);
+    a.part = F(ap.part);
+    a.n_blk = ap.n_blk;
+    a.sca = F(ap.sca);
+    a.dsave = F(ap.dsave);
+    a.msave = F(ap.msave);
+    t.target = target;
+    t.grad = tr->ad_g;
+    t.dgt = F(ap.dgt);
+    t.dyf = F(ap.dyf);
+    t.dxf = F(ap.dxf);
+    t.d5 = F(ap.d5);
+    t.x5 = F(ap.x5);
+    t.d3 = F(ap.d3);
+    t.x3 = F(ap.x3);
+    t.x4 = F(ap.x4);
+    t.x1 = F(ap.x1);
+    t.d4 = F(ap.d4);
+    t.d1 = F(ap.d1);
+    t.tpart = F(ap.tpart);
+    t.fpart = F(ap.fpart);
+    t.dmh = F(ap.dmh);
+    t.lossg = F(ap.lossg);
+    t.loss = F(tp.loss);
+    t.tpi = ap.tpi;
+    t.inv_n = (float)(1.0 / ((double)P * 6.0));
+    {
+      ProfScope ps(ctx, LNM_K_ADAPTERS, s);
+      LNM_HIP_CHECK(launch_adapters_train(tr->ad_c, t, Y(last), G(last), F(ap.wpart), s));
+    }
+    LNM_HIP_CHECK(launch_fill_zero(tr->g + tr->flat_w[hi], (long)(6 * hd.ci + 6), s));
+  } else {
+    lnm_status st = run_unet(ctx, net, B, H, W, guide, lm, nullptr, ws, s);
+    if (st) return st;
+    LNM_HIP_CHECK(launch_loss(lm, target, dz, reinterpret_cast<float*>(ws + tp.losspart), (long)P * 6,
+                              reinterpret_cast<float*>(ws + tp.loss), s));
+    LNM_HIP_CHECK(launch_head_bwd(dz, reinterpret_cast<const float*>(net->dev + hd.w_off), Y(last), (long)P,
+                                  hd.ci, G(last), tr->g + tr->flat_w[hi], tr->g + tr->flat_b[hi], nullptr, s));
+  }
   for (int i = last; i >= 0; --i) {
     const LayerDesc& d = net->layers[i];
     const ConvStep& c = sch[i];
@@ -341,7 +419,7 @@ lnm_status lnm_train_grad(lnm_ctx ctx, lnm_trainer tr, int32_t batch, int32_t H,
   char* ws = static_cast<char*>(workspace);
   st = grad_impl(ctx, tr, batch, H, W, guide, target, ws, s);
   if (st) return st;
-  const TrainPlan tp = train_plan(&tr->net, batch, H, W);
+  const TrainPlan tp = train_plan(&tr->net, batch, H, W, tr->ad_c);
   if (loss) LNM_HIP_CHECK(hipMemcpyAsync(loss, ws + tp.loss, sizeof(float), hipMemcpyDeviceToDevice, s));
   if (grad)
     LNM_HIP_CHECK(hipMemcpyAsync(grad, tr->g, sizeof(float) * tr->n_params, hipMemcpyDeviceToDevice, s));
@@ -358,7 +436,75 @@ lnm_status lnm_train_step(lnm_ctx ctx, lnm_trainer tr, int32_t batch, int32_t H,
   hipStream_t s = (hipStream_t)stream;
   tr->step += 1;
   LNM_HIP_CHECK(launch_adam(tr->p, tr->g, tr->m, tr->v, (long)tr->n_params, lr, beta1, beta2, eps, tr->step, s));
+  if (tr->ad_c)
+    LNM_HIP_CHECK(launch_adam(tr->ad_p, tr->ad_g, tr->ad_m, tr->ad_v, (long)tr->ad_n, lr, beta1, beta2, eps,
+                              tr->step, s));
   return repack(tr, s);
+}
+
+size_t lnm_trainer_adapters_state_bytes(int32_t c) {
+  if (!adapter_width_supported(c)) return 0;
+  return 4 * align256(sizeof(float) * 4 * (7 * (size_t)c * c + 35 * (size_t)c + 2));
+}
+
+lnm_status lnm_trainer_attach_adapters(lnm_trainer tr, const float* host_params, size_t n_params, void* state_buf,
+                                       size_t state_bytes, void* stream) {
+  if (!tr || !host_params || !state_buf) return fail(LNM_ERR_ARG, "NULL argument");
+  const int c = tr->net.base;
+  if (!adapter_width_supported(c)) return fail(LNM_ERR_UNSUPPORTED, "adapters need a base width of 16, 32, 48 or 64");
+  if (tr->ad_c) return fail(LNM_ERR_ARG, "the trainer already has adapters");
+  if (tr->step != 0) return fail(LNM_ERR_ARG, "adapters are attached before the first step");
+  const size_t n = 4 * (7 * (size_t)c * c + 35 * (size_t)c + 2);
+  if (n_params != n) return fail(LNM_ERR_SHAPE, "adapter parameters: expected " + std::to_string(n));
+  if (state_bytes < lnm_trainer_adapters_state_bytes(c))
+    return fail(LNM_ERR_SHAPE, "adapter state buffer too small: need " +
+                                   std::to_string(lnm_trainer_adapters_state_bytes(c)));
+  if (reinterpret_cast<uintptr_t>(state_buf) % 256) return fail(LNM_ERR_ARG, "state_buf must be 256-byte aligned");
+  for (size_t i = 0; i < n_params; ++i)
+    if (!std::isfinite(host_params[i])) return fail(LNM_ERR_ARG, "adapter parameters must be finite");
+  char* st = static_cast<char*>(state_buf);
+  const size_t one = align256(sizeof(float) * n);
+  float* p = reinterpret_cast<float*>(st);
+  float* g = reinterpret_cast<float*>(st + one);
+  float* m = reinterpret_cast<float*>(st + 2 * one);
+  float* v = reinterpret_cast<float*>(st + 3 * one);
+  hipStream_t s = (hipStream_t)stream;
+  LNM_HIP_CHECK(hipMemcpyAsync(p, host_params, sizeof(float) * n, hipMemcpyHostToDevice, s));
+  LNM_HIP_CHECK(launch_fill_zero(g, (long)n, s));
+  LNM_HIP_CHECK(launch_fill_zero(m, (long)n, s));
+  LNM_HIP_CHECK(launch_fill_zero(v, (long)n, s));
+  LNM_HIP_CHECK(hipStreamSynchronize(s));
+  tr->ad_c = c;
+  tr->ad_n = n;
+  tr->ad_p = p;
+  tr->ad_g = g;
+  tr->ad_m = m;
+  tr->ad_v = v;
+  return LNM_OK;
+}
+
+size_t lnm_trainer_workspace_bytes(lnm_trainer tr, int32_t batch, int32_t H, int32_t W) {
+  if (!tr || batch < 1 || H < 1 || W < 1) return 0;
+  return train_plan(&tr->net, batch, H, W, tr->ad_c).bytes;
+}
+
+lnm_status lnm_trainer_read_adapters(lnm_trainer tr, float* host_params, size_t n_params, void* stream) {
+  if (!tr || !host_params) return fail(LNM_ERR_ARG, "NULL argument");
+  if (!tr->ad_c) return fail(LNM_ERR_ARG, "the trainer has no adapters");
+  if (n_params != tr->ad_n) return fail(LNM_ERR_SHAPE, "n_params does not match the adapters");
+  LNM_HIP_CHECK(hipMemcpyAsync(host_params, tr->ad_p, sizeof(float) * n_params, hipMemcpyDeviceToHost,
+                               (hipStream_t)stream));
+  LNM_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
+  return LNM_OK;
+}
+
+lnm_status lnm_trainer_adapter_grad(lnm_trainer tr, float* grad, size_t n_params, void* stream) {
+  if (!tr || !grad) return fail(LNM_ERR_ARG, "NULL argument");
+  if (!tr->ad_c) return fail(LNM_ERR_ARG, "the trainer has no adapters");
+  if (n_params != tr->ad_n) return fail(LNM_ERR_SHAPE, "n_params does not match the adapters");
+  LNM_HIP_CHECK(hipMemcpyAsync(grad, tr->ad_g, sizeof(float) * n_params, hipMemcpyDeviceToDevice,
+                               (hipStream_t)stream));
+  return LNM_OK;
 }
 
 lnm_status lnm_trainer_read_params(lnm_trainer tr, float* host_params, size_t n_params, void* stream) {

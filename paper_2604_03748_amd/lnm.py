@@ -33,6 +33,8 @@ EXPORTS = [
     "lnm_shadow_map_sphere", "lnm_composite_shadowed", "lnm_bricks_bytes", "lnm_make_bricks",
     "lnm_adapters_param_count", "lnm_adapters_device_bytes", "lnm_adapters_create", "lnm_adapters_destroy",
     "lnm_adapters_workspace_bytes", "lnm_infer_adapters", "lnm_frame_static", "lnm_composite_batch",
+    "lnm_trainer_adapters_state_bytes", "lnm_trainer_attach_adapters", "lnm_trainer_workspace_bytes",
+    "lnm_trainer_read_adapters", "lnm_trainer_adapter_grad",
 ]
 STATIC_SCRATCH_BYTES = 128 << 20  # LNM_STATIC_SCRATCH_BYTES
 K_MARCH, K_CONV, K_HEAD, K_COMPOSITE, K_REFERENCE, K_ADAPTERS = range(6)
@@ -584,6 +586,16 @@ def _train_sigs(L):
     L.lnm_trainer_load.argtypes = [vp, vp, vp, vp, i32, sz, vp]
     L.lnm_trainer_infer.restype = i32
     L.lnm_trainer_infer.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, sz, vp]
+    L.lnm_trainer_adapters_state_bytes.restype = sz
+    L.lnm_trainer_adapters_state_bytes.argtypes = [i32]
+    L.lnm_trainer_attach_adapters.restype = i32
+    L.lnm_trainer_attach_adapters.argtypes = [vp, vp, sz, vp, sz, vp]
+    L.lnm_trainer_workspace_bytes.restype = sz
+    L.lnm_trainer_workspace_bytes.argtypes = [vp, i32, i32, i32]
+    L.lnm_trainer_read_adapters.restype = i32
+    L.lnm_trainer_read_adapters.argtypes = [vp, vp, sz, vp]
+    L.lnm_trainer_adapter_grad.restype = i32
+    L.lnm_trainer_adapter_grad.argtypes = [vp, vp, sz, vp]
 
 
 class Trainer:
@@ -608,18 +620,49 @@ class Trainer:
                                    nbytes, _stream(stream), C.byref(h)))
         self.handle = h
         self._ws = {}
+        self.n_adapter_params = 0
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.lnm_trainer_destroy(self.handle)
             self.handle = None
 
+    def attach_adapters(self, adapter_params, stream=None):
+        """Train the four channel adapters with the network in place of its
+        plain head (before the first step)."""
+        import torch
+
+        a = np.ascontiguousarray(adapter_params, dtype=np.float32)
+        nbytes = int(lib().lnm_trainer_adapters_state_bytes(self.base))
+        if nbytes == 0:
+            raise LnmError(LNM_ERR_UNSUPPORTED, f"no adapters for base {self.base}")
+        self.ad_state = torch.empty(nbytes, dtype=torch.uint8, device=self.state.device)
+        check(lib().lnm_trainer_attach_adapters(self.handle, a.ctypes.data_as(C.c_void_p), a.size,
+                                                _ptr(self.ad_state), nbytes, _stream(stream)))
+        self.n_adapter_params = a.size
+        self._ws = {}
+
+    def adapter_params(self, stream=None) -> np.ndarray:
+        out = np.empty(self.n_adapter_params, dtype=np.float32)
+        check(lib().lnm_trainer_read_adapters(self.handle, out.ctypes.data_as(C.c_void_p), out.size,
+                                              _stream(stream)))
+        return out
+
+    @_on_stream
+    def adapter_grad(self, stream=None):
+        """The adapters' gradient of the last grad / step call (device tensor)."""
+        import torch
+
+        g = torch.empty(self.n_adapter_params, dtype=torch.float32, device=self.state.device)
+        check(lib().lnm_trainer_adapter_grad(self.handle, _ptr(g), g.numel(), _stream(stream)))
+        return g
+
     def workspace(self, B, H, W):
         import torch
 
         key = (B, H, W)
         if key not in self._ws:
-            n = int(lib().lnm_train_workspace_bytes(self.levels, self.base, B, H, W))
+            n = int(lib().lnm_trainer_workspace_bytes(self.handle, B, H, W))
             self._ws[key] = torch.empty(max(n, 1), dtype=torch.uint8, device=self.state.device)
         return self._ws[key]
 

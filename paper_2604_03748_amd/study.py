@@ -20,7 +20,7 @@ import numpy as np
 
 from synth.rng import substream
 from synth.scene import Camera, ORTHOGRAPHIC, PERSPECTIVE, make_volume, make_volume_torch
-from synth.weights import he_normal_params
+from synth.weights import adapter_params, he_normal_params
 
 from . import lnm
 
@@ -108,16 +108,30 @@ class TrainResult:
     trainer: "lnm.Trainer"
     losses: list
 
+    def predict(self, ctx, g):
+        """Lightmaps of the trained model on guiding maps g [B][H][W][3]
+        (with its adapters, when it was trained with them)."""
+        tr = self.trainer
+        if not tr.n_adapter_params:
+            return tr.infer(g)
+        net = lnm.Net(ctx, tr.levels, tr.base, tr.params())
+        lm, _ = lnm.Adapters(net, tr.adapter_params()).infer(g)
+        return lm
+
 
 def train(ctx, g, t, steps=600, batch=12, lr=None, seed=0, init_seed=0, setup: Setup = SMALL,
-          progress=None) -> TrainResult:
+          progress=None, adapters=False) -> TrainResult:
     """Adam on random minibatches drawn with a seeded generator (lr: the
     setup's unless given); progress(step, loss) is called every 100 steps
-    when given."""
+    when given.  adapters: the four channel adapters in place of the plain
+    head (Section 4.3), from their identity initialisation, trained with the
+    network."""
     import torch
 
     lr = setup.lr if lr is None else lr
     tr = lnm.Trainer(ctx, setup.levels, setup.base, he_normal_params(setup.levels, setup.base, seed=init_seed))
+    if adapters:
+        tr.attach_adapters(adapter_params(setup.base, seed=init_seed, init="identity"))
     rng = np.random.default_rng(seed)
     n = g.shape[0]
     loss = torch.empty(1, dtype=torch.float32, device=g.device)
@@ -167,4 +181,18 @@ def density_robustness(ctx, steps=600, scales=(0.5, 1.0, 2.0)) -> dict:
         ref = te_t.cpu().numpy()
         out[s] = {"psnr": psnr(r.trainer.infer(te_g).cpu().numpy(), ref),
                   "psnr_affine": psnr(affine_baseline(tr_g, tr_t, te_g), ref)}
+    return out
+
+
+def adapter_gain(ctx, steps=600, setup: Setup = SMALL) -> dict:
+    """Held-out PSNR of the network trained with the plain 1x1 head and with
+    the four channel adapters in its place (same data, steps, seeds)."""
+    tr_g, tr_t = make_set(ctx, setup.train_seeds, setup=setup)
+    te_g, te_t = make_set(ctx, setup.test_seeds, setup=setup)
+    ref = te_t.cpu().numpy()
+    out = {}
+    for name, ad in (("plain_head", False), ("adapters", True)):
+        r = train(ctx, tr_g, tr_t, steps=steps, setup=setup, adapters=ad)
+        out[name] = {"psnr": psnr(r.predict(ctx, te_g).cpu().numpy(), ref), "loss_first": r.losses[0],
+                     "loss_last": r.losses[-1]}
     return out

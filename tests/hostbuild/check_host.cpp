@@ -30,6 +30,16 @@ static void expect(const char* what, lnm_status got, lnm_status want, long launc
                 lnm_last_error());
   }
 }
+// a condition with no status (sizes), or a call that only copies memory
+#define CHECK(cond)                                              \
+  do {                                                           \
+    ++g_checks;                                                  \
+    if (!(cond)) {                                               \
+      ++g_failures;                                              \
+      std::printf("FAIL %s (error \"%s\")\n", #cond, lnm_last_error()); \
+    }                                                            \
+  } while (0)
+
 #define EXPECT(call, want)                       \
   do {                                           \
     const long before_ = fake_launch_count();    \
@@ -356,6 +366,60 @@ int main() {
     } else {
       ++g_failures;
       std::printf("FAIL lnm_trainer_create: %s\n", lnm_last_error());
+    }
+  }
+  // training with channel adapters
+  {
+    const size_t sb = lnm_trainer_state_bytes(L, base);
+    std::vector<char> state(sb + 512);
+    char* st = state.data() + (256 - reinterpret_cast<uintptr_t>(state.data()) % 256) % 256;
+    const size_t na = lnm_adapters_param_count(base), ab = lnm_trainer_adapters_state_bytes(base);
+    std::vector<char> astate(ab + 512);
+    char* ast = astate.data() + (256 - reinterpret_cast<uintptr_t>(astate.data()) % 256) % 256;
+    std::vector<float> ap(na, 0.01f), back(na);
+    CHECK(lnm_trainer_adapters_state_bytes(17) == 0);
+    lnm_trainer tr = nullptr;
+    if (lnm_trainer_create(ctx, L, base, prm_host.data(), np, st, sb, nullptr, &tr) == LNM_OK) {
+      const int B = 2, H = 32, W = 32;
+      const size_t plain = lnm_trainer_workspace_bytes(tr, B, H, W);
+      CHECK(plain == lnm_train_workspace_bytes(L, base, B, H, W));
+      EXPECT(lnm_trainer_read_adapters(tr, back.data(), na, nullptr), LNM_ERR_ARG);
+      EXPECT(lnm_trainer_attach_adapters(tr, ap.data(), na - 1, ast, ab, nullptr), LNM_ERR_SHAPE);
+      EXPECT(lnm_trainer_attach_adapters(tr, ap.data(), na, ast, ab - 1, nullptr), LNM_ERR_SHAPE);
+      EXPECT(lnm_trainer_attach_adapters(tr, ap.data(), na, ast + 4, ab, nullptr), LNM_ERR_ARG);
+      EXPECT(lnm_trainer_attach_adapters(nullptr, ap.data(), na, ast, ab, nullptr), LNM_ERR_ARG);
+      EXPECT(lnm_trainer_attach_adapters(tr, ap.data(), na, ast, ab, nullptr), LNM_OK);
+      EXPECT(lnm_trainer_attach_adapters(tr, ap.data(), na, ast, ab, nullptr), LNM_ERR_ARG);
+      const size_t tw = lnm_trainer_workspace_bytes(tr, B, H, W);
+      CHECK(tw > plain);
+      std::vector<char> tws(tw);
+      std::vector<float> g(B * H * W * 3), t(B * H * W * 6), ag(na);
+      EXPECT(lnm_train_step(ctx, tr, B, H, W, g.data(), t.data(), 1e-3f, 0.9f, 0.999f, 1e-8f, nullptr, tws.data(), tw,
+                            nullptr),
+             LNM_OK);
+      EXPECT(lnm_train_step(ctx, tr, B, H, W, g.data(), t.data(), 1e-3f, 0.9f, 0.999f, 1e-8f, nullptr, tws.data(),
+                            plain, nullptr),
+             LNM_ERR_SHAPE);
+      EXPECT(lnm_trainer_read_adapters(tr, back.data(), na + 1, nullptr), LNM_ERR_SHAPE);
+      CHECK(lnm_trainer_read_adapters(tr, back.data(), na, nullptr) == LNM_OK && back == ap);
+      CHECK(lnm_trainer_adapter_grad(tr, ag.data(), na, nullptr) == LNM_OK);
+      EXPECT(lnm_trainer_adapter_grad(tr, nullptr, na, nullptr), LNM_ERR_ARG);
+      lnm_trainer_destroy(tr);
+    } else {
+      ++g_failures;
+      std::printf("FAIL lnm_trainer_create: %s\n", lnm_last_error());
+    }
+    // adapters come before the first step
+    if (lnm_trainer_create(ctx, L, base, prm_host.data(), np, st, sb, nullptr, &tr) == LNM_OK) {
+      const int B = 1, H = 16, W = 16;
+      const size_t tw = lnm_trainer_workspace_bytes(tr, B, H, W);
+      std::vector<char> tws(tw);
+      std::vector<float> g(B * H * W * 3), t(B * H * W * 6);
+      EXPECT(lnm_train_step(ctx, tr, B, H, W, g.data(), t.data(), 1e-3f, 0.9f, 0.999f, 1e-8f, nullptr, tws.data(), tw,
+                            nullptr),
+             LNM_OK);
+      EXPECT(lnm_trainer_attach_adapters(tr, ap.data(), na, ast, ab, nullptr), LNM_ERR_ARG);
+      lnm_trainer_destroy(tr);
     }
   }
   // profiling

@@ -83,6 +83,9 @@ hipError_t launch_head(const HeadArgs&, hipStream_t, const CompositeArgs*) LAUNC
 hipError_t launch_composite(const CompositeArgs&, hipStream_t) LAUNCH()
 hipError_t launch_composite_batch(const CompositeBatchArgs&, hipStream_t) LAUNCH()
 hipError_t launch_adapters(int, const AdapterArgs&, int, hipStream_t) LAUNCH()
+hipError_t launch_adapters_front(int, const AdapterArgs&, int, hipStream_t) LAUNCH()
+hipError_t launch_adapters_train(int, const AdapterTrainArgs&, const float*, float*, float*, hipStream_t) LAUNCH()
+hipError_t launch_fill_zero(float*, long, hipStream_t) LAUNCH()
 hipError_t launch_shadow_map_sphere(int, float, float, float, float, float, float*, hipStream_t) LAUNCH()
 hipError_t launch_composite_shadowed(const ShadowArgs&, hipStream_t) LAUNCH()
 hipError_t launch_wgrad3x3(int, const WgradArgs&, int* n_partials, hipStream_t) {
