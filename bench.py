@@ -65,9 +65,30 @@ def cpu_baseline(wl, params, light, seconds):
         log(f"cpu oracle frame {n}: {t_total / n:.2f} s/frame")
         if t_total >= seconds or n >= 64:
             break
-    return {"value": round(n / t_total, 4), "unit": "frames/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{n} whole frame(s) (march + U-Net + shading) of the same 128^3 / 256x256 workload in fp64, "
-                      f"{t_total:.1f} s"}
+    out = {"value": round(n / t_total, 4), "unit": "frames/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"{n} whole frame(s) (march + U-Net + shading) of the same 128^3 / 256x256 workload in fp64, "
+                     f"{t_total:.1f} s"}
+    # the oracle on the other configurations, once each: the small
+    # configuration's whole frame (32^3, 64x64 orthographic, 3-level base-16)
+    # and the precision configuration's network alone (512x512, 4-level base 32)
+    from synth.scene import headline, small_ortho
+    from synth.weights import he_normal_params
+
+    sm = small_ortho()
+    sp = he_normal_params(sm.levels, sm.base, seed=0)
+    t0 = time.perf_counter()
+    g, _, _ = oracle.march(sm.volume(), 8.0, sm.camera, sm.step_voxels, seed=0)
+    lm, _ = oracle.unet_forward(sp, sm.levels, sm.base, g)
+    oracle.composite(lm, g, sm.camera, [light])
+    t_small = time.perf_counter() - t0
+    c3 = headline(res=512)
+    g3 = np.random.default_rng(0).random((512, 512, 3))
+    t0 = time.perf_counter()
+    oracle.unet_forward(params, c3.levels, c3.base, g3)
+    t_net = time.perf_counter() - t0
+    log(f"cpu oracle: {sm.name} frame {t_small:.3f} s, 512x512 network {t_net:.2f} s")
+    out["other_configs"] = {f"{sm.name}_frame_s": round(t_small, 4), "persp128_512px_network_s": round(t_net, 3)}
+    return out
 
 
 def measure(lnm, ctx, net, dens, wl, light, steps, warmup, stream):
