@@ -40,6 +40,25 @@ def test_jitter_is_uniform_24bit(orc):
     assert orc.jitter(7, 3, 5) != orc.jitter(7, 4, 5) != orc.jitter(8, 3, 5)
 
 
+def test_jitter_key_roles(orc):
+    """The key mix, a reading (the paper fixes no generator): the frame
+    enters the key shifted into the high 32 bits and the pixel index into
+    the low ones, both XORed into the seed.  So a frame is the same as a
+    seed with the frame in its high word, a pixel the same as a seed with
+    the pixel in its low word, and a swap of seed and frame (or frame and
+    pixel) changes the value."""
+    M = 2**64 - 1
+    for seed, frame, pixel in ((7, 3, 5), (0, 1, 0), (123456789, 77, 65535), (2**40 + 9, 2**31 - 1, 2**20)):
+        u = orc.jitter(seed, frame, pixel)
+        assert u == orc.jitter((seed ^ (frame << 32)) & M, 0, pixel)
+        assert u == orc.jitter((seed ^ pixel) & M, frame, 0)
+        # 24 high bits of SplitMix64 of the key, as a fraction
+        key = (seed ^ (frame << 32) ^ pixel) & M
+        assert u == (orc.splitmix64(key) >> 40) / 2**24
+    assert orc.jitter(3, 7, 5) != orc.jitter(7, 3, 5)
+    assert orc.jitter(7, 5, 3) != orc.jitter(7, 3, 5)
+
+
 # ------------------------------------------------------------------ sampling
 def test_sigma_trilinear_special_cases(orc):
     rng = np.random.default_rng(1)
