@@ -976,8 +976,11 @@ __global__ __launch_bounds__(256) void march_lights(MarchDev m, CamDev c, MarchB
 // Cell order: one lane per record and light, the records sorted by their
 // sample's z cell (srt), each workgroup staging the two grid planes of its
 // cell in LDS.  The records of cell b form ceil(n_b / kCellRecs) units of
-// kCellRecs records (two lanes each: top and bottom light, side by side, so
-// neighbouring lanes start from the same point).  Block g of the grid takes
+// kCellRecs records; wavefront w of the workgroup takes records 64 (w / 2)
+// .. 64 (w / 2) + 63 of the unit toward light w % 2, so a wavefront's lanes
+// march neighbouring samples in one direction (similar lengths, nearby
+// taps; with the two lights of a sample in one wavefront, every step waited
+// for the longer of two opposite marches).  Block g of the grid takes
 // the contiguous run [g U / G, (g + 1) U / G) of the U units (g numbered so
 // that the blocks of one XCD, b % 8, take adjacent runs: a slab of cells),
 // and stages planes again only when its cell changes.  Flat lights (every
@@ -1005,7 +1008,7 @@ __global__ __launch_bounds__(kCellThreads) void march_lights_cells(MarchDev m, C
   const int G = gridDim.x, g = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
   const int u0 = (int)(units * g / G), u1 = (int)(units * (g + 1) / G);
   const int pitch = m.nx + 2;
-  const int light = tid & 1;
+  const int light = (tid >> 6) & 1, slot = ((tid >> 7) << 6) | (tid & 63);
   const float w = light ? m.wb : m.wt;
   int staged = -1;  // the cell whose planes are in LDS (the same in every lane)
   for (int u = u0; u < u1; ++u) {
@@ -1028,7 +1031,7 @@ __global__ __launch_bounds__(kCellThreads) void march_lights_cells(MarchDev m, C
       __syncthreads();
       staged = b;
     }
-    const int r = (u - ustart[b]) * kCellRecs + (tid >> 1);
+    const int r = (u - ustart[b]) * kCellRecs + slot;
     if (r >= cnt[b] || w == 0.0f) continue;
     const int2 en = buf.srt[rstart[b] + r];
     // every entry of the list is written by the scatter; the check keeps a
