@@ -488,19 +488,23 @@ __device__ __forceinline__ int wave_max(int v) {
 //   1. march_primary: four lanes per pixel walk the primary samples, write
 //      T and D, and record (t_n, A_n, T_{n-1}) of every sample with a
 //      nonzero weight in [k][P] planes (in z order also the sample's z
-//      bucket, counting the records per bucket); each wavefront then appends
-//      (pixel, k) of its records, k-major, to its XCD band's work list;
+//      bucket, or in cell order its z cell, counting the records per
+//      bucket); in band and z order each wavefront then appends (pixel, k)
+//      of its records, k-major, to its XCD band's work list;
 //   2. (z order: zsort_records scatters the band lists' entries into z-bucket
-//      order;)
+//      order; cell order: zsort_cells scatters the records into cell order;)
 //   3. march_lights: one lane per record and light (the records cut into
 //      eight equal ranges, one per XCD) marches toward that light and
-//      stores its transmittance at (light, k, pixel);
+//      stores its transmittance at (light, k, pixel); in cell order
+//      march_lights_cells does the same from the cell's density planes
+//      staged in LDS;
 //   4. march_accumulate: one lane per pixel sums A_n L_n in sample order.
 // Band order suits grids whose bricks fit the XCDs' L2s (each XCD's screen
-// band sees a slab of them); larger grids take z order (march_use_zorder).
-// The work lists keep the light-march lanes dense and spatially coherent (a
-// wave takes neighbouring pixels at similar depths) whatever the per-pixel
-// sample counts are; all three kernels read the bricked grid.
+// band sees a slab of them); larger grids take z order, and grids whose
+// planes fit in LDS take cell order for the top/bottom lights (march_order
+// in plan.hip).  The work lists keep the light-march lanes dense and
+// spatially coherent (a wave takes neighbouring pixels at similar depths)
+// whatever the per-pixel sample counts are.
 // One optical-depth step (tau_n = tau_{n-1} + sigma_n h).
 __device__ __forceinline__ float depth_step(float L, float sig, float h) { return L + sig * h; }
 
