@@ -227,7 +227,7 @@ struct AdapterArgs {
   int B, H, W;
   size_t P;           // B H W
   float* v;           // [4][P][c] gated depthwise outputs
-  float* part;        // [B][4][c][n_blk] per-tile sums of v
+  float* part;        // [B][4][n_blk][c] per-tile sums of v
   int n_blk;          // adapter tiles per image (adapter_tiles)
   float* sca;         // [B][4][c] attention scales
   float* lm;          // [P][6]

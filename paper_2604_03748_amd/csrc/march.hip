@@ -226,12 +226,14 @@ __device__ __forceinline__ void relayout_block(const float* __restrict__ rho, in
   __syncthreads();
   const int nb = min(kRelayBricks, nbx - bx0);
   float* out = brick + (((size_t)bz * nby + by) * nbx + bx0) * kBrickSlot;
-  for (int e = threadIdx.x; e < nb * kBrickSlot; e += 256) {
-    const int b = e / kBrickSlot, s = e - b * kBrickSlot;
-    float val = 0.0f;
-    if (s < 125) val = rows[(s / 25) * 5 + (s / 5) % 5][4 * b + s % 5];
-    out[e] = val;
-  }
+  // a thread keeps one slot entry s of every brick it writes (256 threads,
+  // 128-entry slots), so its row and column in the staged rows are fixed
+  static_assert(256 % kBrickSlot == 0, "slot entries per thread");
+  const int s = threadIdx.x & (kBrickSlot - 1);
+  const bool live = s < 125;
+  const int rr = live ? (s / 25) * 5 + (s / 5) % 5 : 0, cc = s % 5;
+  for (int b = threadIdx.x / kBrickSlot; b < nb; b += 256 / kBrickSlot)
+    out[b * kBrickSlot + s] = live ? rows[rr][4 * b + cc] : 0.0f;
 }
 
 __global__ __launch_bounds__(256) void relayout_bricks(const float* __restrict__ rho, int nx, int ny, int nz, int nbx,
