@@ -61,6 +61,11 @@ __global__ __launch_bounds__(256) void adapt_front(AdapterArgs a) {
   // depthwise stage: thread (quad qd, column xc, half hh) takes interior rows
   // 4 hh .. 4 hh + 3 of column xc and gate channels 16 j + 4 qd + (0..3)
   const int qd = tid & 3, xc = (tid >> 2) & 31, hh = tid >> 7;
+  // up to width 32 the normed conv1 operands stay in registers across the
+  // passes; wider blocks recompute them per pass (register budget)
+  constexpr bool kCache = C <= 32;
+  FrontOperands<kCache ? C : 16> fo;
+  if constexpr (kCache) front_operands<C, IN>(a, img, y0, x0, lw, lb, fo);
 
 #pragma unroll 1
   for (int j = 0; j < KB; ++j) {
@@ -68,7 +73,10 @@ __global__ __launch_bounds__(256) void adapt_front(AdapterArgs a) {
       const int h = q / 144, t = (q / 16) % 9, c = q % 16;
       wdw[h][t][c] = P[O::dww + (h * C + 16 * j + c) * 9 + t];
     }
-    front_conv1<C, IN>(a, P, img, y0, x0, j, lw, lb, us, nullptr);
+    if constexpr (kCache)
+      front_conv1_cached<C>(P, j, fo, us);
+    else
+      front_conv1<C, IN>(a, P, img, y0, x0, j, lw, lb, us, nullptr);
     __syncthreads();
     {
       const int ch = 16 * j + 4 * qd;
@@ -125,7 +133,7 @@ __global__ __launch_bounds__(256) void adapt_front(AdapterArgs a) {
       const int q = tid >> 2, r = tid & 3;
       float s = 0.0f;
       for (int t = 0; t < 64; ++t) s += red[(t << 2) | q][r];
-      a.part[(((size_t)b * 4 + g) * C + 16 * j + 4 * q + r) * a.n_blk + blockIdx.x] = s;
+      a.part[(((size_t)b * 4 + g) * a.n_blk + blockIdx.x) * C + 16 * j + 4 * q + r] = s;
     }
   }
 }
@@ -143,9 +151,11 @@ __global__ __launch_bounds__(256) void adapt_attend(AdapterArgs a) {
   const int ch = threadIdx.x % C, slice = threadIdx.x / C;
   const float* P = a.prm + (size_t)g * O::total;
   if (slice < S) {
-    const float* src = a.part + (((size_t)b * 4 + g) * C + ch) * a.n_blk;
+    // tile sums [tile][C]: the lanes of a slice read one tile's row together
+    const float* src = a.part + ((size_t)b * 4 + g) * a.n_blk * C + ch;
     float s = 0.0f;
-    for (int k = slice; k < a.n_blk; k += S) s += src[k];
+#pragma unroll 4
+    for (int k = slice; k < a.n_blk; k += S) s += src[(size_t)k * C];
     red[slice][ch] = s;
   }
   __syncthreads();
@@ -158,6 +168,7 @@ __global__ __launch_bounds__(256) void adapt_attend(AdapterArgs a) {
   __syncthreads();
   if (threadIdx.x < C) {
     float s = P[O::scab + threadIdx.x];
+#pragma unroll 8
     for (int i = 0; i < C; ++i) s += P[O::scaw + threadIdx.x * C + i] * pooled[i];
     a.sca[((size_t)b * 4 + g) * C + threadIdx.x] = s;
   }

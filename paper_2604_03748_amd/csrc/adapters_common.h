@@ -126,6 +126,80 @@ __device__ __forceinline__ void front_conv1(const AdapterArgs& a, const float* P
   }
 }
 
+// The conv1 operands of a wavefront's halo column blocks (w, w + 4, ...: at
+// most kHaloUnits of them), layer norm 1 applied, kept in registers across
+// the channel passes (the norm is the same for every pass), with each
+// column's in-image flag.
+constexpr int kHaloUnits = (kHaloCols + 3) / 4;
+template <int C>
+struct FrontOperands {
+  f4 xv[kHaloUnits][C / 16];
+  bool in[kHaloUnits];
+};
+
+template <int C, int IN>
+__device__ __forceinline__ void front_operands(const AdapterArgs& a, size_t img, int y0, int x0,
+                                               const f4 (&lw)[C / 16], const f4 (&lb)[C / 16], FrontOperands<C>& fo) {
+  constexpr int KB = C / 16;
+  const int lane = threadIdx.x & 63, li = lane & 15, G = lane >> 4, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int u = 0; u < kHaloUnits; ++u) {
+    const int hp = (wave + 4 * u) * 16 + li;
+    const int hy = hp / kHX, hx = hp - hy * kHX;
+    const int y = y0 + hy - 1, x = x0 + hx - 1;
+    fo.in[u] = hp < kHalo && y >= 0 && y < a.H && x >= 0 && x < a.W;
+    const size_t p = img + (size_t)min(max(y, 0), a.H - 1) * a.W + min(max(x, 0), a.W - 1);
+    float s = 0.0f;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      fo.xv[u][kb] = feat4<C, IN>(a, p, 16 * kb + 4 * G);
+      s += hsum(fo.xv[u][kb]);
+    }
+    const float mu = pixel_sum(s) * (1.0f / (float)C);
+    float sq = 0.0f;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      fo.xv[u][kb] -= mu;
+      sq += hsum(fo.xv[u][kb] * fo.xv[u][kb]);
+    }
+    const float rs = 1.0f / sqrtf(pixel_sum(sq) * (1.0f / (float)C) + 1e-6f);
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) fo.xv[u][kb] = fo.xv[u][kb] * rs * lw[kb] + lb[kb];
+  }
+}
+
+// front_conv1 on operands from front_operands: the same products in the
+// same order, without recomputing the norm
+template <int C>
+__device__ __forceinline__ void front_conv1_cached(const float* P, int j, const FrontOperands<C>& fo, float* us) {
+  using O = Off<C>;
+  constexpr int KB = C / 16;
+  const int lane = threadIdx.x & 63, li = lane & 15, G = lane >> 4, wave = threadIdx.x >> 6;
+  f4 wa[2][KB];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) wa[m][kb] = ld4(P + O::c1w + (size_t)(m * C + 16 * j + li) * C + 16 * kb + 4 * G);
+  const f4 bias0 = ld4(P + O::c1b + 16 * j + 4 * G), bias1 = ld4(P + O::c1b + C + 16 * j + 4 * G);
+#pragma unroll
+  for (int u = 0; u < kHaloUnits; ++u) {
+    const int nb = wave + 4 * u;
+    if (nb >= kHaloCols) break;  // uniform per wavefront
+    f4 acc0 = bias0, acc1 = bias1;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        acc0 = mfma(wa[0][kb][r], fo.xv[u][kb][r], acc0);
+        acc1 = mfma(wa[1][kb][r], fo.xv[u][kb][r], acc1);
+      }
+    const f4 zero = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    float* dst = us + (nb * 16 + li) * kUPitch + 4 * G;
+    *reinterpret_cast<f4*>(dst) = fo.in[u] ? acc0 : zero;
+    *reinterpret_cast<f4*>(dst + 16) = fo.in[u] ? acc1 : zero;
+  }
+}
+
 // output channels of each group: lightmaps (+Z, -Z), (+X, -X), (+Y, -Y); extra (alpha, emissive)
 __constant__ int kDst[4][2] = {{4, 5}, {0, 1}, {2, 3}, {-1, -2}};
 
