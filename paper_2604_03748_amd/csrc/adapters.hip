@@ -185,8 +185,11 @@ __device__ __forceinline__ void fence_schedule() {
   if constexpr (C > 32) __builtin_amdgcn_sched_barrier(0);
 }
 
+// Width 32 asks for four wavefronts per SIMD (128 registers, a few spilled):
+// the chain is latency-bound and the fourth wavefront hides more of it than
+// the spill costs (40 -> 36 us per 256x256 frame).
 template <int C, int IN>
-__global__ __launch_bounds__(256) void adapt_tail(AdapterArgs a, int n_tiles) {
+__global__ __launch_bounds__(256, C == 32 ? 4 : 1) void adapt_tail(AdapterArgs a, int n_tiles) {
   using O = Off<C>;
   constexpr int KB = C / 16;
   constexpr int NB = C <= 32 ? 4 : 2;  // 16-pixel column blocks per MFMA batch (register budget)
