@@ -443,7 +443,9 @@ LNM_API size_t lnm_trainer_workspace_bytes(lnm_trainer tr, int32_t batch, int32_
 LNM_API lnm_status lnm_trainer_read_adapters(lnm_trainer tr, float* host_params, size_t n_params, void* stream);
 LNM_API lnm_status lnm_trainer_adapter_grad(lnm_trainer tr, float* grad, size_t n_params, void* stream);
 /* Forward pass with the trainer's current weights (same as lnm_infer on an
- * fp32 net holding those weights). */
+ * fp32 net holding those weights).  LNM_ERR_UNSUPPORTED once adapters are
+ * attached: their network is inferred with lnm_infer_adapters on a net and
+ * adapters created from lnm_trainer_read_params / lnm_trainer_read_adapters. */
 LNM_API lnm_status lnm_trainer_infer(lnm_ctx ctx, lnm_trainer tr, int32_t batch, int32_t H, int32_t W,
                                      const float* guide, float* lightmaps, void* workspace, size_t ws_bytes,
                                      void* stream);

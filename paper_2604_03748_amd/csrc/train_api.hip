@@ -546,6 +546,9 @@ lnm_status lnm_trainer_load(lnm_trainer tr, const float* host_params, const floa
 lnm_status lnm_trainer_infer(lnm_ctx ctx, lnm_trainer tr, int32_t batch, int32_t H, int32_t W, const float* guide,
                              float* lightmaps, void* workspace, size_t ws_bytes, void* stream) {
   if (!ctx || !tr || !guide || !lightmaps) return fail(LNM_ERR_ARG, "NULL argument");
+  if (tr->ad_c)
+    return fail(LNM_ERR_UNSUPPORTED,
+                "the trainer has adapters: infer with lnm_infer_adapters on its read-back parameters");
   lnm_status st = check_infer(&tr->net, batch, H, W, ws_bytes, workspace);
   if (st) return st;
   return run_unet(ctx, &tr->net, batch, H, W, guide, lightmaps, nullptr, static_cast<char*>(workspace),

@@ -403,6 +403,8 @@ int main() {
       EXPECT(lnm_trainer_read_adapters(tr, back.data(), na + 1, nullptr), LNM_ERR_SHAPE);
       CHECK(lnm_trainer_read_adapters(tr, back.data(), na, nullptr) == LNM_OK && back == ap);
       CHECK(lnm_trainer_adapter_grad(tr, ag.data(), na, nullptr) == LNM_OK);
+      std::vector<float> lmo(B * H * W * 6);
+      EXPECT(lnm_trainer_infer(ctx, tr, B, H, W, g.data(), lmo.data(), tws.data(), tw, nullptr), LNM_ERR_UNSUPPORTED);
       EXPECT(lnm_trainer_adapter_grad(tr, nullptr, na, nullptr), LNM_ERR_ARG);
       lnm_trainer_destroy(tr);
     } else {
