@@ -89,6 +89,9 @@ constexpr size_t kCounterBytes = 4 * (kZCursor + kZBuckets);
 // Bricks along an axis of n cells; bytes of a z cell's two grid planes in LDS.
 int bricks_along(int n);
 size_t cell_planes_bytes(int nx, int ny);
+// LDS the cell order's plane pairs may take (the rest of the CU's 160 KB
+// holds the kernel's own bookkeeping)
+constexpr size_t kCellLdsBytes = 160 * 1024 - 4 * 1024;
 // Capacity per pixel: the most primary samples a ray can take in the support box.
 int march_capacity(const MarchDev& m);
 // Order of a march's light marches (MarchDev::zorder) for lnm_work_order

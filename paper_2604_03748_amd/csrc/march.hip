@@ -993,21 +993,42 @@ __global__ __launch_bounds__(256) void march_lights(MarchDev m, CamDev c, MarchB
 // light of the top/bottom set except the fallback of a ray along z) read
 // LDS; others read the bricks.
 constexpr int kCellThreads = 1024, kCellRecs = kCellThreads / 2;
+constexpr int kCellEntries = (int)((kCellLdsBytes / sizeof(float2) + kCellThreads - 1) / kCellThreads);
 __global__ __launch_bounds__(kCellThreads) void march_lights_cells(MarchDev m, CamDev c, MarchBuf buf) {
   extern __shared__ float2 planes[];  // [ny + 2][nx + 2] pairs (plane below, plane above)
-  __shared__ int cnt[kZBuckets], ustart[kZBuckets + 1], rstart[kZBuckets];
-  const int tid = threadIdx.x;
-  if (tid < kZBuckets) cnt[tid] = buf.ctr[kZHist + tid];
-  __syncthreads();
-  if (tid == 0) {  // units and record offsets of the cells (exclusive prefix sums)
-    int u = 0, r = 0;
-    ustart[0] = 0;
-    for (int b = 0; b < kZBuckets; ++b) {
-      rstart[b] = r;
-      r += cnt[b];
-      u += (cnt[b] + kCellRecs - 1) / kCellRecs;
-      ustart[b + 1] = u;
+  __shared__ int cnt[kZBuckets], ustart[kZBuckets + 1], rstart[kZBuckets], wsum[2][kZBuckets / 64];
+  const int tid = threadIdx.x, lane = tid & 63;
+  // units and record offsets of the cells: exclusive prefix sums over the
+  // buckets, one lane each (scans within the wavefronts, then across them)
+  int nc = 0, nu = 0, ic = 0, iu = 0;
+  if (tid < kZBuckets) {
+    nc = buf.ctr[kZHist + tid];
+    nu = (nc + kCellRecs - 1) / kCellRecs;
+    cnt[tid] = nc;
+    ic = nc;
+    iu = nu;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int tc = __shfl_up(ic, o), tu = __shfl_up(iu, o);
+      if (lane >= o) {
+        ic += tc;
+        iu += tu;
+      }
     }
+    if (lane == 63) {
+      wsum[0][tid >> 6] = ic;
+      wsum[1][tid >> 6] = iu;
+    }
+  }
+  __syncthreads();
+  if (tid < kZBuckets) {
+    for (int w = 0; w < (tid >> 6); ++w) {
+      ic += wsum[0][w];
+      iu += wsum[1][w];
+    }
+    rstart[tid] = ic - nc;
+    ustart[tid] = iu - nu;
+    if (tid == kZBuckets - 1) ustart[kZBuckets] = iu;
   }
   __syncthreads();
   const long units = ustart[kZBuckets];
@@ -1023,17 +1044,34 @@ __global__ __launch_bounds__(kCellThreads) void march_lights_cells(MarchDev m, C
       if (b + step < kZBuckets && ustart[b + step] <= u) b += step;
     if (b != staged) {
       __syncthreads();  // every lane is done with the previous cell's planes
-      // grid planes b - 1 and b, zero outside the grid: rpp rows per pass,
-      // one lane per entry (pitch <= 160 where this order is chosen)
-      const int rpp = max(1, kCellThreads / pitch), x = tid % pitch;
-      for (int y = tid / pitch; y < m.ny + 2 && tid < rpp * pitch && x < pitch; y += rpp) {
+      // grid planes b - 1 and b, zero outside the grid: lane tid takes
+      // entries tid + kCellThreads e of the (ny + 2) x pitch table, all its
+      // loads in flight together (clamped addresses, masked values)
+      const int n_ent = (m.ny + 2) * pitch, dy = kCellThreads / pitch, dx = kCellThreads % pitch;
+      const int ps = m.nx * m.ny;
+      const int p0 = min(max(b - 1, 0), m.nz - 1) * ps, p1 = min(b, m.nz - 1) * ps;
+      const bool z0 = b - 1 >= 0 && b - 1 < m.nz, z1 = b < m.nz;
+      float v0[kCellEntries], v1[kCellEntries];
+      int y = tid / pitch, x = tid - y * pitch;
+#pragma unroll
+      for (int e = 0; e < kCellEntries; ++e) {
         const int j = y - 1, i = x - 1;
-        const bool in = j >= 0 && j < m.ny && i >= 0 && i < m.nx;
-        const bool ok0 = in && b - 1 >= 0 && b - 1 < m.nz, ok1 = in && b < m.nz;
-        const size_t col = (size_t)j * m.nx + i, ps = (size_t)m.nx * m.ny;
-        planes[y * pitch + x] = make_float2(ok0 ? m.rho[(size_t)(b - 1) * ps + col] : 0.0f,
-                                            ok1 ? m.rho[(size_t)b * ps + col] : 0.0f);
+        const bool in = tid + e * kCellThreads < n_ent && j >= 0 && j < m.ny && i >= 0 && i < m.nx;
+        const int col = in ? j * m.nx + i : 0;
+        v0[e] = m.rho[(unsigned)(p0 + col)];
+        v1[e] = m.rho[(unsigned)(p1 + col)];
+        v0[e] = in && z0 ? v0[e] : 0.0f;
+        v1[e] = in && z1 ? v1[e] : 0.0f;
+        x += dx;
+        y += dy;
+        if (x >= pitch) {
+          x -= pitch;
+          ++y;
+        }
       }
+#pragma unroll
+      for (int e = 0; e < kCellEntries; ++e)
+        if (tid + e * kCellThreads < n_ent) planes[tid + e * kCellThreads] = make_float2(v0[e], v1[e]);
       __syncthreads();
       staged = b;
     }
