@@ -122,6 +122,23 @@ __device__ __forceinline__ float trilerp(const float (&v)[8], float fx, float fy
 __device__ __forceinline__ float brick_lerp(const MarchDev& m, const BrickTap& t, const BrickVals& c) {
   return m.sigma_scale * trilerp(c.v, t.fx, t.fy, t.fz) * t.mask;
 }
+// The trilinear value on a flat light march, whose z fraction is the same at
+// every sample: the two planes are blended first, b + fz d with
+// d = above - below (one fused multiply-add per corner, the cell-order
+// planes in LDS hold d), then along x and y.  Corners (below, d) at (i, j),
+// (i + 1, j), (i, j + 1), (i + 1, j + 1).
+__device__ __forceinline__ float flat_lerp(float b00, float d00, float b10, float d10, float b01, float d01,
+                                           float b11, float d11, float fx, float fy, float fz) {
+  const float e00 = fmaf(fz, d00, b00), e10 = fmaf(fz, d10, b10);
+  const float e01 = fmaf(fz, d01, b01), e11 = fmaf(fz, d11, b11);
+  return lerp1(lerp1(e00, e10, fx), lerp1(e01, e11, fx), fy);
+}
+__device__ __forceinline__ float brick_lerp_flat(const MarchDev& m, const BrickTap& t, const BrickVals& c) {
+  const float(&v)[8] = c.v;
+  return m.sigma_scale *
+         flat_lerp(v[0], v[4] - v[0], v[1], v[5] - v[1], v[2], v[6] - v[2], v[3], v[7] - v[3], t.fx, t.fy, t.fz) *
+         t.mask;
+}
 
 __device__ __forceinline__ float sample_sigma(const MarchDev& m, float px, float py, float pz) {
   const BrickTap t = brick_tap(m, px, py, pz);
@@ -192,7 +209,7 @@ __device__ __forceinline__ void sample_batch_flat(const MarchDev& m, const float
   for (int q = 0; q < N; ++q) c[q] = brick_load(t[q]);
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int q = 0; q < N; ++q) out[q] = brick_lerp(m, t[q], c[q]);
+  for (int q = 0; q < N; ++q) out[q] = brick_lerp_flat(m, t[q], c[q]);
 }
 
 // Fill the bricked grid from the caller's linear grid (HBM-bound copy; once
@@ -321,10 +338,12 @@ __device__ __forceinline__ float light_transmittance(const MarchDev& m, V3 x, V3
 
 // Transmittance toward one light on the bricked grid: the samples of the
 // march are gathered four at a time (all loads issued before any is used)
-// and summed in order; the march stops at the termination limit.  Same
-// result as light_transmittance<true>.
+// and summed in order; the march stops at the termination limit.
 // FLAT: l has no z component, so every sample has the z of x (x.z + t * 0
-// is x.z exactly) and the z part of the taps is computed once.
+// is x.z exactly): the z part of the taps is computed once, and the
+// interpolation blends the two planes first (flat_lerp, the same arithmetic
+// as the cell order's LDS march).  Otherwise the samples are those of
+// light_transmittance<true>.
 template <bool FLAT>
 __device__ __forceinline__ float light_transmittance_batched(const MarchDev& m, V3 x, V3 l) {
   const float h = m.h, lim = m.tau_max / h;
@@ -354,26 +373,29 @@ __device__ __forceinline__ float light_transmittance_batched(const MarchDev& m, 
 }
 
 // The light march of a flat light (no z component) with the density of its
-// sample's z cell staged in LDS: pl[ny + 2][nx + 2] pairs (value of the grid
-// plane below the cell, value of the plane above), with a zero border (index
-// i + 1 holds grid column i), so one 8-byte read gives both planes' corner.
-// The taps, interpolation weights and sums are those of
-// light_transmittance_batched<true>, so the result is the same bit for bit;
-// the corners come from LDS instead of the bricks.
+// sample's z cell staged in LDS: pl[ny + 3][nx + 3] pairs (value of the grid
+// plane below the cell, value above minus value below), index i + 1 holding
+// grid column i, with a zero border (one entry before the grid, two after),
+// so one 8-byte read gives a corner of both planes.  The tap coordinates are
+// clamped to [-1, n]: a point outside the grid then reads border zeros with
+// weight one (and finite entries with weight zero), which is the zero the
+// bricked sampler's inside mask gives it.  Inside the grid the taps, weights
+// and sums are those of light_transmittance_batched<true>, so the result is
+// the same bit for bit; the corners come from LDS instead of the bricks.
 struct LdsTap {
-  int o;      // LDS pair index of corner (i, j)
-  float fx, fy, mask;
+  int o;  // LDS pair index of corner (i, j)
+  float fx, fy;
 };
-__device__ __forceinline__ LdsTap lds_tap(const MarchDev& m, float px, float py, bool zin, int pitch) {
+__device__ __forceinline__ LdsTap lds_tap(const MarchDev& m, float px, float py, int pitch) {
   const float gx = fmaf(px, (float)m.nx, -0.5f), gy = fmaf(py, (float)m.ny, -0.5f);
-  const bool inside = zin && gx > -1.0f && gy > -1.0f && gx < (float)m.nx && gy < (float)m.ny;
-  const float cx = inside ? gx : 0.0f, cy = inside ? gy : 0.0f;
+  const float cx = __builtin_amdgcn_fmed3f(gx, -1.0f, (float)m.nx);
+  const float cy = __builtin_amdgcn_fmed3f(gy, -1.0f, (float)m.ny);
   const float fx0 = floorf(cx), fy0 = floorf(cy);
   LdsTap t;
-  t.o = ((int)fy0 + 1) * pitch + (int)fx0 + 1;
+  // (fy0 + 1) pitch + fx0 + 1, exact in fp32 (under 2^24)
+  t.o = (int)fmaf(fy0, (float)pitch, fx0) + pitch + 1;
   t.fx = cx - fx0;
   t.fy = cy - fy0;
-  t.mask = inside ? 1.0f : 0.0f;
   return t;
 }
 __device__ __forceinline__ float light_transmittance_lds(const MarchDev& m, V3 x, V3 l, const float2* __restrict__ pl,
@@ -384,29 +406,24 @@ __device__ __forceinline__ float light_transmittance_lds(const MarchDev& m, V3 x
   float acc = 0.0f;
   for (int k = 1; k <= kmax; k += 4) {
     LdsTap t[4];
-    float c[4][8];
+    float2 c[4][4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const float tt = (float)(k + q) * h;
-      t[q] = lds_tap(m, fmaf(tt, l.x, x.x), fmaf(tt, l.y, x.y), fz.in, pitch);
+      t[q] = lds_tap(m, fmaf(tt, l.x, x.x), fmaf(tt, l.y, x.y), pitch);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const float2* a = pl + t[q].o;
-      const float2 v00 = a[0], v10 = a[1], v01 = a[pitch], v11 = a[pitch + 1];
-      c[q][0] = v00.x;
-      c[q][1] = v10.x;
-      c[q][2] = v01.x;
-      c[q][3] = v11.x;
-      c[q][4] = v00.y;
-      c[q][5] = v10.y;
-      c[q][6] = v01.y;
-      c[q][7] = v11.y;
+      c[q][0] = a[0];
+      c[q][1] = a[1];
+      c[q][2] = a[pitch];
+      c[q][3] = a[pitch + 1];
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const float fzz = t[q].mask != 0.0f ? fz.fz : 0.0f;
-      const float sv = m.sigma_scale * trilerp(c[q], t[q].fx, t[q].fy, fzz) * t[q].mask;
+      const float sv = m.sigma_scale * flat_lerp(c[q][0].x, c[q][0].y, c[q][1].x, c[q][1].y, c[q][2].x, c[q][2].y,
+                                                 c[q][3].x, c[q][3].y, t[q].fx, t[q].fy, fz.fz);
       acc += k + q <= kmax ? sv : 0.0f;
       if (acc > lim) return 0.0f;
     }
@@ -995,7 +1012,7 @@ __global__ __launch_bounds__(256) void march_lights(MarchDev m, CamDev c, MarchB
 constexpr int kCellThreads = 1024, kCellRecs = kCellThreads / 2;
 constexpr int kCellEntries = (int)((kCellLdsBytes / sizeof(float2) + kCellThreads - 1) / kCellThreads);
 __global__ __launch_bounds__(kCellThreads) void march_lights_cells(MarchDev m, CamDev c, MarchBuf buf) {
-  extern __shared__ float2 planes[];  // [ny + 2][nx + 2] pairs (plane below, plane above)
+  extern __shared__ float2 planes[];  // [ny + 3][nx + 3] pairs (plane below, above - below)
   __shared__ int cnt[kZBuckets], ustart[kZBuckets + 1], rstart[kZBuckets], wsum[2][kZBuckets / 64];
   const int tid = threadIdx.x, lane = tid & 63;
   // units and record offsets of the cells: exclusive prefix sums over the
@@ -1034,7 +1051,7 @@ __global__ __launch_bounds__(kCellThreads) void march_lights_cells(MarchDev m, C
   const long units = ustart[kZBuckets];
   const int G = gridDim.x, g = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
   const int u0 = (int)(units * g / G), u1 = (int)(units * (g + 1) / G);
-  const int pitch = m.nx + 2;
+  const int pitch = m.nx + 3;
   const int light = (tid >> 6) & 1, slot = ((tid >> 7) << 6) | (tid & 63);
   const float w = light ? m.wb : m.wt;
   int staged = -1;  // the cell whose planes are in LDS (the same in every lane)
@@ -1044,10 +1061,11 @@ __global__ __launch_bounds__(kCellThreads) void march_lights_cells(MarchDev m, C
       if (b + step < kZBuckets && ustart[b + step] <= u) b += step;
     if (b != staged) {
       __syncthreads();  // every lane is done with the previous cell's planes
-      // grid planes b - 1 and b, zero outside the grid: lane tid takes
-      // entries tid + kCellThreads e of the (ny + 2) x pitch table, all its
-      // loads in flight together (clamped addresses, masked values)
-      const int n_ent = (m.ny + 2) * pitch, dy = kCellThreads / pitch, dx = kCellThreads % pitch;
+      // grid planes b - 1 and b, zero outside the grid, as (below, above -
+      // below): lane tid takes entries tid + kCellThreads e of the (ny + 3) x
+      // pitch table, all its loads in flight together (clamped addresses,
+      // masked values)
+      const int n_ent = (m.ny + 3) * pitch, dy = kCellThreads / pitch, dx = kCellThreads % pitch;
       const int ps = m.nx * m.ny;
       const int p0 = min(max(b - 1, 0), m.nz - 1) * ps, p1 = min(b, m.nz - 1) * ps;
       const bool z0 = b - 1 >= 0 && b - 1 < m.nz, z1 = b < m.nz;
@@ -1071,7 +1089,7 @@ __global__ __launch_bounds__(kCellThreads) void march_lights_cells(MarchDev m, C
       }
 #pragma unroll
       for (int e = 0; e < kCellEntries; ++e)
-        if (tid + e * kCellThreads < n_ent) planes[tid + e * kCellThreads] = make_float2(v0[e], v1[e]);
+        if (tid + e * kCellThreads < n_ent) planes[tid + e * kCellThreads] = make_float2(v0[e], v1[e] - v0[e]);
       __syncthreads();
       staged = b;
     }

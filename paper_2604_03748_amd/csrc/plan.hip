@@ -46,7 +46,7 @@ size_t march_scratch_bytes(const MarchDev& m, int K, int W, int H) {
 // Cell order: the two planes of a cell in LDS, beside the kernel's own
 // arrays, within the 160 KB a gfx950 workgroup may allocate; at most 255
 // cells (z buckets).
-size_t cell_planes_bytes(int nx, int ny) { return 2 * sizeof(float) * (size_t)(nx + 2) * (ny + 2); }
+size_t cell_planes_bytes(int nx, int ny) { return 2 * sizeof(float) * (size_t)(nx + 3) * (ny + 3); }
 static bool cells_fit(int nx, int ny, int nz) { return cell_planes_bytes(nx, ny) <= kCellLdsBytes && nz < kZBuckets; }
 
 int march_order(int work_order, int light_set, int nx, int ny, int nz) {
