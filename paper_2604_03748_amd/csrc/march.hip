@@ -668,7 +668,7 @@ __device__ __forceinline__ void primary_tile(const MarchDev& m, const CamDev& c,
 // owns.  The band's blocks take its tiles in turn.
 // In z order the block also counts its records per z bucket in LDS and adds
 // them to the global counts at the end.
-__global__ __launch_bounds__(256) void march_primary(MarchDev m, CamDev c, TileMap tm, MarchBuf buf,
+__global__ __launch_bounds__(256, 4) void march_primary(MarchDev m, CamDev c, TileMap tm, MarchBuf buf,
                                                      float* __restrict__ guide) {
   __shared__ int zh[kZBuckets];
   __shared__ int agg[5];
@@ -885,27 +885,33 @@ __global__ __launch_bounds__(256) void zsort_records(MarchBuf buf) {
 // is bounded by its cell's range.
 constexpr int kSortPixels = 64;
 __global__ __launch_bounds__(256) void zsort_cells(MarchBuf buf) {
-  __shared__ int scan[2][kZBuckets];
+  __shared__ int wsum[kZBuckets / 64];
   __shared__ int bstart[kZBuckets], bend[kZBuckets], lcount[kZBuckets], lbase[kZBuckets];
   static_assert(kZBuckets == 256, "one lane per bucket");
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // the cells' ranges in the list: an inclusive scan of the histogram
+  // within each wavefront, then across the four
   const int n = buf.ctr[kZHist + tid];
-  scan[0][tid] = n;
+  int inc = n;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(inc, o);
+    if (lane >= o) inc += v;
+  }
+  if (lane == 63) wsum[tid >> 6] = inc;
   lcount[tid] = 0;
   __syncthreads();
-  int cur = 0;
-  for (int o = 1; o < kZBuckets; o <<= 1) {  // inclusive scan (Hillis-Steele)
-    scan[cur ^ 1][tid] = scan[cur][tid] + (tid >= o ? scan[cur][tid - o] : 0);
-    cur ^= 1;
-    __syncthreads();
-  }
-  bstart[tid] = scan[cur][tid] - n;
-  bend[tid] = scan[cur][tid];
-  const int p = blockIdx.x * kSortPixels + (tid & 63), k1 = tid >> 6;
+  for (int w = 0; w < (tid >> 6); ++w) inc += wsum[w];
+  bstart[tid] = inc - n;
+  bend[tid] = inc;
+  // S lanes per pixel: lane tid takes records tid / kSortPixels + S j of
+  // pixel tid % kSortPixels
+  constexpr int S = 256 / kSortPixels;
+  const int p = blockIdx.x * kSortPixels + tid % kSortPixels, k1 = tid / kSortPixels;
   const int cnt = p < buf.P ? min(buf.cnt[p], buf.K) : 0;
   // U of the lane's records at a time, their loads and LDS atomics issued
   // together (one record after the other leaves the lane waiting on each load)
-  constexpr int U = 4, S = 4;
+  constexpr int U = 4;
   for (int k0 = k1; k0 < cnt; k0 += U * S) {
     int zk[U];
 #pragma unroll
