@@ -1017,6 +1017,92 @@ __global__ __launch_bounds__(256) void march_lights(MarchDev m, CamDev c, MarchB
 // LDS; others read the bricks.
 constexpr int kCellThreads = 1024, kCellRecs = kCellThreads / 2;
 constexpr int kCellEntries = (int)((kCellLdsBytes / sizeof(float2) + kCellThreads - 1) / kCellThreads);
+constexpr int kCellQuads = (int)((kCellLdsBytes / sizeof(float2) / 4 + kCellThreads - 1) / kCellThreads);
+
+// Grid planes b - 1 and b of cell b into the LDS table, zero outside the
+// grid, as (below, above - below): lane tid takes entries tid + kCellThreads e
+// of the (ny + 3) x pitch table, border included, in two batches of loads in
+// flight together (clamped addresses, masked values).
+// The lane index is passed through an empty asm statement so that the
+// compiler recomputes the lane's entries at each staging instead of keeping
+// them in registers across the whole march loop.
+__device__ __forceinline__ int lane_index_here() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+__device__ __forceinline__ void stage_planes(const MarchDev& m, int b, float2* planes, int pitch) {
+  const int tid = lane_index_here();
+  const int n_ent = (m.ny + 3) * pitch, dy = kCellThreads / pitch, dx = kCellThreads % pitch;
+  const int ps = m.nx * m.ny;
+  const int p0 = min(max(b - 1, 0), m.nz - 1) * ps, p1 = min(b, m.nz - 1) * ps;
+  const bool z0 = b - 1 >= 0 && b - 1 < m.nz, z1 = b < m.nz;
+  constexpr int E = (kCellEntries + 1) / 2;  // entries per batch (two batches)
+  int y = tid / pitch, x = tid - y * pitch;
+  for (int e0 = 0; e0 < 2 * E; e0 += E) {
+    float v0[E], v1[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = y - 1, i = x - 1;
+      const bool in = tid + (e0 + e) * kCellThreads < n_ent && j >= 0 && j < m.ny && i >= 0 && i < m.nx;
+      const int col = in ? j * m.nx + i : 0;
+      v0[e] = m.rho[(unsigned)(p0 + col)];
+      v1[e] = m.rho[(unsigned)(p1 + col)];
+      v0[e] = in && z0 ? v0[e] : 0.0f;
+      v1[e] = in && z1 ? v1[e] : 0.0f;
+      x += dx;
+      y += dy;
+      if (x >= pitch) {
+        x -= pitch;
+        ++y;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int q = tid + (e0 + e) * kCellThreads;
+      if (q < n_ent) planes[q] = make_float2(v0[e], v1[e] - v0[e]);
+    }
+  }
+}
+// The same for rows of a multiple of four values (16-byte aligned): lane tid
+// takes the four-value groups tid + kCellThreads e of the ny x nx / 4 grid
+// part, one 16-byte load per plane each; the border is not written.
+__device__ __forceinline__ void stage_planes_vec(const MarchDev& m, int b, float2* planes, int pitch) {
+  const int tid = lane_index_here();
+  const int q4 = m.nx >> 2, n4 = m.ny * q4, dj = kCellThreads / q4, dg = kCellThreads % q4;
+  const int ps = m.nx * m.ny;
+  const float4* r0 = reinterpret_cast<const float4*>(m.rho + (size_t)min(max(b - 1, 0), m.nz - 1) * ps);
+  const float4* r1 = reinterpret_cast<const float4*>(m.rho + (size_t)min(b, m.nz - 1) * ps);
+  const bool z0 = b - 1 >= 0 && b - 1 < m.nz, z1 = b < m.nz;
+  float4 v0[kCellQuads], v1[kCellQuads];
+  int j = tid / q4, g = tid - j * q4;
+  int at[kCellQuads];
+#pragma unroll
+  for (int e = 0; e < kCellQuads; ++e) {
+    const bool in = tid + e * kCellThreads < n4;
+    const int q = in ? tid + e * kCellThreads : 0;
+    v0[e] = r0[q];
+    v1[e] = r1[q];
+    if (!(in && z0)) v0[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (!(in && z1)) v1[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    at[e] = in ? (j + 1) * pitch + 4 * g + 1 : -1;
+    g += dg;
+    j += dj;
+    if (g >= q4) {
+      g -= q4;
+      ++j;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kCellQuads; ++e) {
+    if (at[e] < 0) continue;
+    float2* d = planes + at[e];
+    d[0] = make_float2(v0[e].x, v1[e].x - v0[e].x);
+    d[1] = make_float2(v0[e].y, v1[e].y - v0[e].y);
+    d[2] = make_float2(v0[e].z, v1[e].z - v0[e].z);
+    d[3] = make_float2(v0[e].w, v1[e].w - v0[e].w);
+  }
+}
 __global__ __launch_bounds__(kCellThreads) void march_lights_cells(MarchDev m, CamDev c, MarchBuf buf) {
   extern __shared__ float2 planes[];  // [ny + 3][nx + 3] pairs (plane below, above - below)
   __shared__ int cnt[kZBuckets], ustart[kZBuckets + 1], rstart[kZBuckets], wsum[2][kZBuckets / 64];
@@ -1061,41 +1147,33 @@ __global__ __launch_bounds__(kCellThreads) void march_lights_cells(MarchDev m, C
   const int light = (tid >> 6) & 1, slot = ((tid >> 7) << 6) | (tid & 63);
   const float w = light ? m.wb : m.wt;
   int staged = -1;  // the cell whose planes are in LDS (the same in every lane)
+  // rows of four grid values as one 16-byte load when the rows allow it; the
+  // zero border is then written once here (the stagings write the interior)
+  const bool vec = (m.nx & 3) == 0 && ((uintptr_t)m.rho & 15) == 0;
+  if (vec) {
+    const int nb = 3 * pitch + 3 * m.ny;  // rows 0, ny + 1, ny + 2; columns 0, nx + 1, nx + 2
+    for (int t = tid; t < nb; t += kCellThreads) {
+      int e;
+      if (t < 3 * pitch) {
+        const int r = t / pitch, x = t - r * pitch;
+        e = (r == 0 ? 0 : m.ny + r) * pitch + x;
+      } else {
+        const int t2 = t - 3 * pitch, r = t2 / 3, cc = t2 - 3 * r;
+        e = (r + 1) * pitch + (cc == 0 ? 0 : m.nx + cc);
+      }
+      planes[e] = make_float2(0.0f, 0.0f);
+    }
+  }
   for (int u = u0; u < u1; ++u) {
     int b = 0;  // the cell of unit u: the last b with ustart[b] <= u
     for (int step = 128; step > 0; step >>= 1)
       if (b + step < kZBuckets && ustart[b + step] <= u) b += step;
     if (b != staged) {
       __syncthreads();  // every lane is done with the previous cell's planes
-      // grid planes b - 1 and b, zero outside the grid, as (below, above -
-      // below): lane tid takes entries tid + kCellThreads e of the (ny + 3) x
-      // pitch table, all its loads in flight together (clamped addresses,
-      // masked values)
-      const int n_ent = (m.ny + 3) * pitch, dy = kCellThreads / pitch, dx = kCellThreads % pitch;
-      const int ps = m.nx * m.ny;
-      const int p0 = min(max(b - 1, 0), m.nz - 1) * ps, p1 = min(b, m.nz - 1) * ps;
-      const bool z0 = b - 1 >= 0 && b - 1 < m.nz, z1 = b < m.nz;
-      float v0[kCellEntries], v1[kCellEntries];
-      int y = tid / pitch, x = tid - y * pitch;
-#pragma unroll
-      for (int e = 0; e < kCellEntries; ++e) {
-        const int j = y - 1, i = x - 1;
-        const bool in = tid + e * kCellThreads < n_ent && j >= 0 && j < m.ny && i >= 0 && i < m.nx;
-        const int col = in ? j * m.nx + i : 0;
-        v0[e] = m.rho[(unsigned)(p0 + col)];
-        v1[e] = m.rho[(unsigned)(p1 + col)];
-        v0[e] = in && z0 ? v0[e] : 0.0f;
-        v1[e] = in && z1 ? v1[e] : 0.0f;
-        x += dx;
-        y += dy;
-        if (x >= pitch) {
-          x -= pitch;
-          ++y;
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < kCellEntries; ++e)
-        if (tid + e * kCellThreads < n_ent) planes[tid + e * kCellThreads] = make_float2(v0[e], v1[e] - v0[e]);
+      if (vec)
+        stage_planes_vec(m, b, planes, pitch);
+      else
+        stage_planes(m, b, planes, pitch);
       __syncthreads();
       staged = b;
     }

@@ -162,6 +162,11 @@ def test_prebuilt_bricks(ctx, orc):
         assert ctx.march_workspace_bytes(dens, 6.0, cam, p, bricks=br) < ctx.march_workspace_bytes(dens, 6.0, cam, p)
 
 
+def cases_cam_odd():
+    return Camera(PERSPECTIVE, (1.9, -1.2, 1.4), target=(0.5, 0.5, 0.45), up=(0.0, 0.0, 1.0), fov_y_deg=50.0,
+                  width=41, height=35)
+
+
 def test_work_orders_agree(ctx, orc):
     """The light marches' work order (screen bands, records sorted by brick
     layer and taken by each XCD in turn, or records sorted by z cell with the
@@ -182,6 +187,9 @@ def test_work_orders_agree(ctx, orc):
         ("left_right", ragged, 6.0, Camera(ORTHOGRAPHIC, (0.4, -2.0, 0.7), up=(0.0, 0.0, 1.0), ortho_half_extent=0.8,
                                            width=33, height=50), 0.75, {"light_set": 1, "seed": 9}),
         ("dense_riemann", small_ortho().volume() * 6.0, 8.0, small_ortho().camera, 1.0, {"quadrature": 1}),
+        # no axis a multiple of four: the cell order stages its planes value
+        # by value instead of in groups of four
+        ("odd_rows", make_volume((19, 26, 33), 4, 11, noise_amp=0.3), 6.0, cases_cam_odd(), 1.25, {"seed": 2}),
     ]
     for what, vol, ss, cam, step, kw in cases:
         log(f"work orders: {what}")
