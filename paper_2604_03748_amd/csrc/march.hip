@@ -557,67 +557,59 @@ __device__ __forceinline__ void primary_tile(const MarchDev& m, const CamDev& c,
   }
   // Lane s of the quad takes samples n = n0 + 4g + s of group g, so the four
   // lanes gather four consecutive samples and a wave's loads stay in a
-  // compact part of the volume.  Four groups' loads are issued together;
-  // then, group by group, the optical depth runs through the quad in sample
-  // order (tau_n = tau_{n-1} + sigma_n h, handed from lane to lane, the same
-  // float sums as one lane walking the ray), each lane forms T_{n-1}, A_n,
-  // its record index (records of the lower lanes counted by a ballot) and
-  // the depth test, and the quad stops after the group in which the depth
-  // first passes tau_max.  A sample is taken only if the depth before it is
-  // still within tau_max.
+  // compact part of the volume.  Group by group, the optical depth runs
+  // through the quad in sample order (tau_n = tau_{n-1} + sigma_n h, handed
+  // from lane to lane, the same float sums as one lane walking the ray),
+  // each lane forms T_{n-1}, A_n, its record index (records of the lower
+  // lanes counted by a ballot) and the depth test, and the quad stops after
+  // the group in which the depth first passes tau_max.  A sample is taken
+  // only if the depth before it is still within tau_max.  (Issuing the loads
+  // of two or four groups before their sums was slower: 19.3 and 20.9 us
+  // against 18.2 per headline march, the extra groups mostly wasted past
+  // the termination and their registers costing waves.)
   const bool riemann = m.quadrature == LNM_QUAD_RIEMANN;
   const int lane = threadIdx.x & 63, qbase = lane & ~3;
   float tau = 0.0f;  // depth before the current group (equal in the quad)
   int k = 0, dn = 0;  // records so far (equal in the quad), this lane's first sample over depth_tau
   bool term = false;
-  for (int nb = n0; nb <= n1 && !term; nb += 16) {
-    float px[4], py[4], pz[4], sg[4];
+  for (int nb = n0; nb <= n1 && !term; nb += 4) {
+    const int n = nb + s;
+    const float t = ((float)n + u) * h;
+    const float pz = o.z + t * d.z;
+    const float sg = sample_sigma(m, o.x + t * d.x, o.y + t * d.y, pz);
+    const bool valid = n <= n1;
+    const float sig = valid ? sg : 0.0f;
+    // running depth through the quad: lane s ends with tau_n
+    float x = s == 0 ? depth_step(tau, sig, h) : 0.0f;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float t = ((float)(nb + 4 * q + s) + u) * h;
-      px[q] = o.x + t * d.x;
-      py[q] = o.y + t * d.y;
-      pz[q] = o.z + t * d.z;
+    for (int r = 1; r < 4; ++r) {
+      const float v = __shfl_up(x, 1, 4);
+      if (s == r) x = depth_step(v, sig, h);
     }
-    sample_batch<4>(m, px, py, pz, sg);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (term) break;
-      const int n = nb + 4 * q + s;
-      const bool valid = n <= n1;
-      const float sig = valid ? sg[q] : 0.0f;
-      // running depth through the quad: lane s ends with tau_n
-      float x = s == 0 ? depth_step(tau, sig, h) : 0.0f;
-#pragma unroll
-      for (int r = 1; r < 4; ++r) {
-        const float v = __shfl_up(x, 1, 4);
-        if (s == r) x = depth_step(v, sig, h);
+    float before = __shfl_up(x, 1, 4);
+    if (s == 0) before = tau;
+    const bool active = valid && before <= m.tau_max;
+    const float alpha = riemann ? sig * h : -expm1f(-sig * h);
+    const bool rec = active && alpha != 0.0f;
+    const unsigned quad = (unsigned)(__ballot(rec) >> qbase) & 0xfu;
+    const int kr = k + __popc(quad & ((1u << s) - 1u));
+    if (rec && kr < buf.K) {
+      const float Tprev = expf(-before);
+      const size_t r = (size_t)kr * buf.P + pix;
+      buf.t[r] = t;
+      buf.a[r] = Tprev * alpha;
+      buf.tp[r] = Tprev;
+      if (m.zorder) {
+        const int zk = z_bucket(m, pz);
+        buf.zb[r] = (uint8_t)zk;
+        atomicAdd(&zh[zk], 1);
       }
-      float before = __shfl_up(x, 1, 4);
-      if (s == 0) before = tau;
-      const bool active = valid && before <= m.tau_max;
-      const float alpha = riemann ? sig * h : -expm1f(-sig * h);
-      const bool rec = active && alpha != 0.0f;
-      const unsigned quad = (unsigned)(__ballot(rec) >> qbase) & 0xfu;
-      const int kr = k + __popc(quad & ((1u << s) - 1u));
-      if (rec && kr < buf.K) {
-        const float Tprev = expf(-before);
-        const size_t r = (size_t)kr * buf.P + pix;
-        buf.t[r] = ((float)n + u) * h;
-        buf.a[r] = Tprev * alpha;
-        buf.tp[r] = Tprev;
-        if (m.zorder) {
-          const int zk = z_bucket(m, pz[q]);
-          buf.zb[r] = (uint8_t)zk;
-          atomicAdd(&zh[zk], 1);
-        }
-      }
-      if (active && dn == 0 && sig > m.depth_tau) dn = n;
-      k = min(k + __popc(quad), buf.K);
-      const unsigned over = (unsigned)(__ballot(active && x > m.tau_max) >> qbase) & 0xfu;
-      tau = __shfl(x, 3, 4);
-      term = over != 0u;
     }
+    if (active && dn == 0 && sig > m.depth_tau) dn = n;
+    k = min(k + __popc(quad), buf.K);
+    const unsigned over = (unsigned)(__ballot(active && x > m.tau_max) >> qbase) & 0xfu;
+    tau = __shfl(x, 3, 4);
+    term = over != 0u;
   }
   // quad results: records, depth, transmittance
   const int cnt = k;
