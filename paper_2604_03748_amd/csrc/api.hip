@@ -351,7 +351,8 @@ Plan plan_workspace(const lnm_net_s* net, int B, int H, int W) {
 }
 
 lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, const float* guide, float* lm,
-                    float* logits, char* ws, hipStream_t s, const CompositeArgs* comp, bool fuse_head) {
+                    float* logits, char* ws, hipStream_t s, const CompositeArgs* comp, bool fuse_head,
+                    bool fuse_first) {
   const Plan p = plan_workspace(net, B, H, W);
   const int L = net->levels;
   auto buf = [&](int i) { return static_cast<void*>(ws + p.out_off[i]); };
@@ -380,6 +381,11 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
       a.w_scale = d.s_off ? reinterpret_cast<const float*>(net->dev + d.s_off) : nullptr;
       a.out_inv_scale = 1.0f / net->act_scale[li];
       a.out_bf16 = d.out_es == 2;
+    }
+    if (mode == G_FIRST) {
+      const LayerDesc& d0 = net->layers[0];
+      a.w0 = reinterpret_cast<const float*>(net->dev + d0.w_off);
+      a.b0 = reinterpret_cast<const float*>(net->dev + d0.b_off);
     }
     a.n_tiles = d.co_pad / kBN;
     const LayerTiling tl = conv_layer_tiling(net, li, B, a.H, a.W);
@@ -418,11 +424,26 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
   hf.in_scale = last_e4m3 ? net->act_scale[n_conv - 1] : 1.0f;
   const bool fused = fuse_head && lm && !logits && net->layers[n_conv - 1].co <= kBN &&
                      layer_splits(net, n_conv - 1, B, H, W) == 1;
+  // the first two fp32 layers in one launch: the second recomputes the
+  // first's outputs on its tiles (their halo included) from the guide, so
+  // the first layer's output is neither stored nor read
+  const bool first = fuse_first && net->layers[0].prec == LNM_FP32 && net->layers[1].prec == LNM_FP32 &&
+                     net->layers[0].ck == 4 && net->layers[1].ck == 16;
   hipError_t e;
   const void* x = guide;
   int cx = 3;
   for (int l = 0; l < L; ++l) {
     const int mode = l == 0 ? G_GUIDE : G_POOL;
+    if (l == 0 && first) {
+      ++li;
+      cx = net->layers[0].co;
+      if ((e = conv(0, G_FIRST, -1, guide, cx, nullptr, 0)) != hipSuccess)
+        return fail(LNM_ERR_DEVICE, hipGetErrorString(e));
+      x = buf(li - 1);
+      cx = net->layers[li - 1].co;
+      skip[0] = li - 1;
+      continue;
+    }
     if ((e = conv(l, mode, l == 0 ? -1 : skip[l - 1], x, cx, nullptr, 0)) != hipSuccess)
       return fail(LNM_ERR_DEVICE, hipGetErrorString(e));
     x = buf(li - 1);
@@ -520,7 +541,7 @@ lnm_status frame_impl(lnm_ctx_s* ctx, const lnm_net_s* net, const lnm_volume* vo
   a.rgba = rgba;
   a.P = c.H * c.W;
   return run_unet(ctx, net, 1, c.H, c.W, guide, lightmaps, nullptr, static_cast<char*>(workspace), s,
-                  rgba ? &a : nullptr, true);
+                  rgba ? &a : nullptr, true, true);
 }
 
 size_t frame_workspace_bytes(const lnm_net_s* net, const lnm_volume* vol, const lnm_camera* cam,
@@ -828,7 +849,7 @@ lnm_status lnm_infer(lnm_ctx ctx, lnm_net net, int32_t batch, int32_t H, int32_t
   lnm_status st = check_infer(net, batch, H, W, ws_bytes, workspace);
   if (st) return st;
   return run_unet(ctx, net, batch, H, W, guide, lightmaps, logits, static_cast<char*>(workspace),
-                  (hipStream_t)stream, nullptr, true);
+                  (hipStream_t)stream, nullptr, true, true);
 }
 
 lnm_status lnm_composite(lnm_ctx ctx, const lnm_camera* cam, const lnm_light* lights, int32_t n_lights,
@@ -957,7 +978,7 @@ lnm_status lnm_infer_adapters(lnm_ctx ctx, lnm_adapters ad, int32_t batch, int32
   if (ws_bytes < ap.bytes) return fail(LNM_ERR_SHAPE, "workspace too small: need " + std::to_string(ap.bytes));
   char* ws = static_cast<char*>(workspace);
   hipStream_t s = (hipStream_t)stream;
-  st = run_unet(ctx, ad->net, batch, H, W, guide, nullptr, nullptr, ws, s);  // trunk only
+  st = run_unet(ctx, ad->net, batch, H, W, guide, nullptr, nullptr, ws, s, nullptr, false, true);  // trunk only
   if (st) return st;
   const lnm_net_s* net = ad->net;
   const int n_conv = (int)net->layers.size() - 1;

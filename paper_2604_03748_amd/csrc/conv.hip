@@ -50,7 +50,9 @@ template <int MODE>
 __device__ __forceinline__ Halo<MODE> halo_load(const ConvArgs& a, int b, int y, int x, int c) {
   const float* s0 = static_cast<const float*>(a.src0);
   Halo<MODE> h;
-  if constexpr (MODE == G_GUIDE) {
+  if constexpr (MODE == G_FIRST) {
+    h.v[0] = f4{0.f, 0.f, 0.f, 0.f};
+  } else if constexpr (MODE == G_GUIDE) {
     const float* g = s0 + ((size_t)(b * a.H + y) * a.W + x) * 3;
     h.v[0] = f4{g[0], g[1], g[2], 0.0f};
   } else if constexpr (MODE == G_PLAIN) {
@@ -109,6 +111,60 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a, HeadFuse hf) {
 #pragma unroll
     for (int nf = 0; nf < NF; ++nf) acc[mf][nf] = f4{0.f, 0.f, 0.f, 0.f};
 
+  // G_FIRST: the guide over the (TH+4) x 20 pixels that the first layer's
+  // outputs on this tile's halo read, zero outside the image; per chunk the
+  // first layer's outputs at the HP halo pixels are a K = 27 product on the
+  // matrix cores (A: the pixels' 3x3 x 3 guide values from LDS, B: the
+  // chunk's 16 channels of first-layer weights), 16-pixel blocks spread over
+  // the four waves, then bias and ReLU
+  constexpr int GW = kTW + 4, NG = MODE == G_FIRST ? (TH + 4) * GW : 1;
+  constexpr int HP = (TH + 2) * kHW, HB = (HP + 15) / 16, BPW = (HB + 3) / 4;
+  __shared__ f4 s_g[NG];
+  float fr[MODE == G_FIRST ? 4 * BPW : 1];
+  auto stage_guide = [&]() {
+    const float* gs = static_cast<const float*>(a.src0);
+    for (int p = tid; p < NG; p += 256) {
+      const int y = y0 + p / GW - 2, x = x0 + p % GW - 2;
+      f4 v = f4{0.f, 0.f, 0.f, 0.f};
+      if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
+        const float* q = gs + ((size_t)(b * a.H + y) * a.W + x) * 3;
+        v = f4{q[0], q[1], q[2], 0.0f};
+      }
+      s_g[p] = v;
+    }
+  };
+  auto first_layer = [&](int ch) {
+    // B: W0[k][n] for k = 4 s + g (tap k / 3, guide channel k % 3; k = 27 is
+    // padding), n = ch * 16 + li, from the packed [n / 32][tap][n % 32][c (4)]
+    const int n = ch * CK + li;
+    const float* w = a.w0 + (size_t)(n / kBN) * 9 * kBN * 4 + (n % kBN) * 4;
+    float bk[7];
+#pragma unroll
+    for (int st = 0; st < 7; ++st) {
+      const int k = 4 * st + g;
+      bk[st] = k < 27 ? w[(k / 3) * kBN * 4 + k % 3] : 0.0f;
+    }
+    const float bias = a.b0[n];
+    const float* sg = reinterpret_cast<const float*>(s_g);
+#pragma unroll
+    for (int bb = 0; bb < BPW; ++bb) {
+      const int blk = wave * BPW + bb;
+      if (blk >= HB) break;
+      // A: row li of the block is halo pixel p (clamped into the halo)
+      const int p = min(blk * 16 + li, HP - 1), py = p / kHW, px = p - py * kHW;
+      f4 d = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int st = 0; st < 7; ++st) {
+        const int k = 4 * st + g, tap = k / 3;
+        const float av = k < 27 ? sg[((py + tap / 3) * GW + px + tap % 3) * 4 + k % 3] : 0.0f;
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bk[st], d, 0, 0, 0);
+      }
+      // D: rows 4g + r of the block (pixels), column li (channel)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) fr[4 * bb + r] = fmaxf(d[r] + bias, 0.0f);
+    }
+  };
+
   // per chunk: the (TH+2) x 18 input halo and the weight slab [tap][n][c];
   // every load is unconditional (clamped index), masks apply at commit
   constexpr int NQ = (TH + 2) * kHW * (CK / 4), NW = 9 * kBN * CK / 4;
@@ -116,10 +172,15 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a, HeadFuse hf) {
   Halo<MODE> rq[RQ];
   f4 rw[RW];
   unsigned ok = 0;
+  auto fetch_w = [&](int ch) {
+    const float* wsrc = wblk + (size_t)ch * 9 * kBN * CK;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) rw[r] = *reinterpret_cast<const f4*>(wsrc + 4 * min(tid + 256 * r, NW - 1));
+  };
   auto fetch = [&](int ch) {
     ok = 0;
 #pragma unroll
-    for (int r = 0; r < RQ; ++r) {
+    for (int r = 0; r < (MODE == G_FIRST ? 0 : RQ); ++r) {
       const int q = min(tid + 256 * r, NQ - 1);
       const int c4 = q % (CK / 4), p = q / (CK / 4);
       const int y = y0 + p / kHW - 1, x = x0 + p % kHW - 1;
@@ -127,13 +188,29 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a, HeadFuse hf) {
       ok |= (unsigned)in << r;
       rq[r] = halo_load<MODE>(a, b, min(max(y, 0), a.H - 1), min(max(x, 0), a.W - 1), ch * CK + 4 * c4);
     }
-    const float* wsrc = wblk + (size_t)ch * 9 * kBN * CK;
-#pragma unroll
-    for (int r = 0; r < RW; ++r) rw[r] = *reinterpret_cast<const f4*>(wsrc + 4 * min(tid + 256 * r, NW - 1));
+    fetch_w(ch);
+    if constexpr (MODE == G_FIRST) first_layer(ch);
   };
   auto commit = [&](int buf) {
+    if constexpr (MODE == G_FIRST) {
+      // this lane's first-layer outputs: channel li at halo pixels
+      // 16 blk + 4g + r (zero padding outside the image)
 #pragma unroll
-    for (int r = 0; r < RQ; ++r) {
+      for (int bb = 0; bb < BPW; ++bb) {
+        const int blk = wave * BPW + bb;
+        if (blk >= HB) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = blk * 16 + 4 * g + r;
+          if (q >= HP) continue;
+          const int py = q / kHW, y = y0 + py - 1, x = x0 + q - py * kHW - 1;
+          const bool in = y >= 0 && y < a.H && x >= 0 && x < a.W;
+          s_in[buf][q * PIN + li] = in ? fr[4 * bb + r] : 0.0f;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < (MODE == G_FIRST ? 0 : RQ); ++r) {
       const int q = tid + 256 * r;
       if (q < NQ)
         *reinterpret_cast<f4*>(&s_in[buf][(q / (CK / 4)) * PIN + 4 * (q % (CK / 4))]) =
@@ -146,7 +223,16 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a, HeadFuse hf) {
     }
   };
 
-  if (ch_lo < ch_hi) {
+  if constexpr (MODE == G_FIRST) {
+    // the first chunk's weights in flight while the guide is staged
+    if (ch_lo < ch_hi) fetch_w(ch_lo);
+    stage_guide();
+    __syncthreads();
+    if (ch_lo < ch_hi) {
+      first_layer(ch_lo);
+      commit(0);
+    }
+  } else if (ch_lo < ch_hi) {
     fetch(ch_lo);
     commit(0);
   }
@@ -476,6 +562,9 @@ hipError_t launch_conv3x3_f32(int mode, int ck, const ConvArgs& a, hipStream_t s
   if (mode == G_GUIDE && ck == 4) return launch_tile<4, G_GUIDE>(a, s, head);
   if (ck != 16) return hipErrorInvalidValue;
   switch (mode) {
+    case G_FIRST:
+      if (!a.w0 || !a.b0) return hipErrorInvalidValue;
+      return launch_tile<16, G_FIRST>(a, s, head);
     case G_PLAIN: return launch_tile<16, G_PLAIN>(a, s, head);
     case G_POOL: return launch_tile<16, G_POOL>(a, s, head);
     case G_CONCAT_UP: return launch_tile<16, G_CONCAT_UP>(a, s, head);

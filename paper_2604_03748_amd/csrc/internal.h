@@ -111,7 +111,7 @@ hipError_t launch_reference(const MarchDev& m, const CamDev& cam, int srgb, floa
 // ---------------------------------------------------------------- network
 constexpr int kBN = 32;  // output-channel tile of the conv kernels
 
-enum Gather : int { G_GUIDE = 0, G_PLAIN = 1, G_POOL = 2, G_CONCAT_UP = 3 };
+enum Gather : int { G_GUIDE = 0, G_PLAIN = 1, G_POOL = 2, G_CONCAT_UP = 3, G_FIRST = 4 };
 
 struct LayerDesc {
   int ci, co, k;
@@ -148,6 +148,10 @@ struct ConvArgs {
            // bf16 large-layer form (kBf16LargeRows rows x 64 channels per workgroup; n_tiles >= 2,
            // no head)
   int out_bf16;  // fp8 layers: store max(y, 0) as bf16 (unscaled) instead of e4m3
+  // G_FIRST (fp32): src0 is the guide and the layer's input is the network's
+  // first layer, recomputed per tile from its packed weights and bias
+  const float* w0;
+  const float* b0;
 };
 // Sum the split partials in split order, then bias, (scale,) ReLU and the
 // output conversion of out_type (0 fp32, 1 bf16, 2 fp8; 3: fp8 partials,
@@ -355,7 +359,7 @@ Plan plan_workspace(const lnm_net_s* net, int B, int H, int W);
 // layer's output is then not stored; callers that read it pass false)
 lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, const float* guide, float* lm,
                     float* logits, char* ws, hipStream_t s, const CompositeArgs* comp = nullptr,
-                    bool fuse_head = false);
+                    bool fuse_head = false, bool fuse_first = false);
 lnm_status check_infer(const lnm_net_s* net, int B, int H, int W, size_t ws_bytes, const void* ws);
 // lnm_frame on a caller's (or the library's static) workspace, and its size
 lnm_status frame_impl(lnm_ctx_s* ctx, const lnm_net_s* net, const lnm_volume* vol, const lnm_camera* cam,

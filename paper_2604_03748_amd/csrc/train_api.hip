@@ -552,7 +552,7 @@ lnm_status lnm_trainer_infer(lnm_ctx ctx, lnm_trainer tr, int32_t batch, int32_t
   lnm_status st = check_infer(&tr->net, batch, H, W, ws_bytes, workspace);
   if (st) return st;
   return run_unet(ctx, &tr->net, batch, H, W, guide, lightmaps, nullptr, static_cast<char*>(workspace),
-                  (hipStream_t)stream);
+                  (hipStream_t)stream, nullptr, false, true);
 }
 
 }  // extern "C"
