@@ -424,11 +424,15 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
   hf.in_scale = last_e4m3 ? net->act_scale[n_conv - 1] : 1.0f;
   const bool fused = fuse_head && lm && !logits && net->layers[n_conv - 1].co <= kBN &&
                      layer_splits(net, n_conv - 1, B, H, W) == 1;
-  // the first two fp32 layers in one launch: the second recomputes the
-  // first's outputs on its tiles (their halo included) from the guide, so
-  // the first layer's output is neither stored nor read
-  const bool first = fuse_first && net->layers[0].prec == LNM_FP32 && net->layers[1].prec == LNM_FP32 &&
-                     net->layers[0].ck == 4 && net->layers[1].ck == 16;
+  // the first two layers in one launch (fp32, or bf16 in the default tile
+  // form): the second recomputes the first's outputs on its tiles (their
+  // halo included) from the guide, so the first layer's output is neither
+  // stored nor read
+  const LayerDesc &d0 = net->layers[0], &d1 = net->layers[1];
+  const bool first =
+      fuse_first && ((d0.prec == LNM_FP32 && d1.prec == LNM_FP32 && d0.ck == 4 && d1.ck == 16) ||
+                     (d0.prec == LNM_BF16 && d1.prec == LNM_BF16 &&
+                      conv_layer_tiling(net, 1, B, H, W).th != kBf16Large));
   hipError_t e;
   const void* x = guide;
   int cx = 3;

@@ -116,7 +116,9 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a, HeadFuse hf) {
   // first layer's outputs at the HP halo pixels are a K = 27 product on the
   // matrix cores (A: the pixels' 3x3 x 3 guide values from LDS, B: the
   // chunk's 16 channels of first-layer weights), 16-pixel blocks spread over
-  // the four waves, then bias and ReLU
+  // the four waves, then bias and ReLU.  The products are taken in the first
+  // layer's own K order (tap, then guide channel), and the outputs matched
+  // the separate first layer's bit for bit wherever they were compared
   constexpr int GW = kTW + 4, NG = MODE == G_FIRST ? (TH + 4) * GW : 1;
   constexpr int HP = (TH + 2) * kHW, HB = (HP + 15) / 16, BPW = (HB + 3) / 4;
   __shared__ f4 s_g[NG];
