@@ -505,19 +505,23 @@ def measured_traffic(dtype):
 
 
 def conv_roofline(wl, stage, dtype):
-    from synth.weights import unet_flops, unet_layers
+    from synth.weights import unet_flops
 
     H, W = wl.camera.height, wl.camera.width
-    n_conv = sum(1 for l in unet_layers(wl.levels, wl.base) if l[3] == 3)
     conv_flops = unet_flops(wl.levels, wl.base, 1, H, W) - 2.0 * H * W * 6 * wl.base  # 3x3 layers only
+    # the 3x3 layers' algorithmic FLOPs over their time per frame; the
+    # launches are counted as made (fp32 and bf16 run the first two layers
+    # as one)
+    n_conv = stage["conv3x3"]["launches_per_frame"]
+    us = stage["conv3x3"]["us_per_frame"] / n_conv
     per_launch = conv_flops / n_conv
-    us = stage["conv3x3"]["us_per_launch"]
     achieved = per_launch / (us * 1e-6) / 1e12
     kern = {"fp32": "conv3x3_f32 (v_mfma_f32_16x16x4_f32)", "bf16": "conv3x3_bf16 (v_mfma_f32_16x16x32_bf16)",
             "fp8": "conv3x3_fp8 (v_mfma_f32_16x16x32_fp8_fp8)"}[dtype]
     return {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_TFLOPS[dtype], 5), "traffic": measured_traffic(dtype), "kernel": kern,
-            "flops_per_launch": round(per_launch), "us_per_launch": round(us, 3), "launches_per_frame": n_conv}
+            "flops_per_launch": round(per_launch), "us_per_launch": round(us, 3),
+            "launches_per_frame": round(n_conv, 3)}
 
 
 def main():
