@@ -384,8 +384,9 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
     }
     if (mode == G_FIRST) {
       const LayerDesc& d0 = net->layers[0];
-      a.w0 = reinterpret_cast<const float*>(net->dev + d0.w_off);
+      a.w0 = net->dev + d0.w_off;
       a.b0 = reinterpret_cast<const float*>(net->dev + d0.b_off);
+      if (d0.prec == LNM_FP8_E4M3) a.w0_out_inv = 1.0f / net->act_scale[0];
     }
     a.n_tiles = d.co_pad / kBN;
     const LayerTiling tl = conv_layer_tiling(net, li, B, a.H, a.W);
@@ -424,15 +425,16 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
   hf.in_scale = last_e4m3 ? net->act_scale[n_conv - 1] : 1.0f;
   const bool fused = fuse_head && lm && !logits && net->layers[n_conv - 1].co <= kBN &&
                      layer_splits(net, n_conv - 1, B, H, W) == 1;
-  // the first two layers in one launch (fp32, or bf16 in the default tile
-  // form): the second recomputes the first's outputs on its tiles (their
-  // halo included) from the guide, so the first layer's output is neither
-  // stored nor read
+  // the first two layers in one launch (fp32, fp8, or bf16 in the default
+  // tile form): the second recomputes the first's outputs on its tiles
+  // (their halo included) from the guide, so the first layer's output is
+  // neither stored nor read
   const LayerDesc &d0 = net->layers[0], &d1 = net->layers[1];
   const bool first =
       fuse_first && ((d0.prec == LNM_FP32 && d1.prec == LNM_FP32 && d0.ck == 4 && d1.ck == 16) ||
                      (d0.prec == LNM_BF16 && d1.prec == LNM_BF16 &&
-                      conv_layer_tiling(net, 1, B, H, W).th != kBf16Large));
+                      conv_layer_tiling(net, 1, B, H, W).th != kBf16Large) ||
+                     (d0.prec == LNM_FP8_E4M3 && d1.prec == LNM_FP8_E4M3 && d0.out_es == 1));
   hipError_t e;
   const void* x = guide;
   int cx = 3;
@@ -441,7 +443,7 @@ lnm_status run_unet(lnm_ctx_s* ctx, const lnm_net_s* net, int B, int H, int W, c
     if (l == 0 && first) {
       ++li;
       cx = net->layers[0].co;
-      if ((e = conv(0, G_FIRST, -1, guide, cx, nullptr, 0)) != hipSuccess)
+      if ((e = conv(0, G_FIRST, 0, guide, cx, nullptr, 0)) != hipSuccess)
         return fail(LNM_ERR_DEVICE, hipGetErrorString(e));
       x = buf(li - 1);
       cx = net->layers[li - 1].co;

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a, HeadFuse hf) {
     // B: W0[k][n] for k = 4 s + g (tap k / 3, guide channel k % 3; k = 27 is
     // padding), n = ch * 16 + li, from the packed [n / 32][tap][n % 32][c (4)]
     const int n = ch * CK + li;
-    const float* w = a.w0 + (size_t)(n / kBN) * 9 * kBN * 4 + (n % kBN) * 4;
+    const float* w = static_cast<const float*>(a.w0) + (size_t)(n / kBN) * 9 * kBN * 4 + (n % kBN) * 4;
     float bk[7];
 #pragma unroll
     for (int st = 0; st < 7; ++st) {

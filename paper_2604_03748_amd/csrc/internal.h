@@ -148,10 +148,12 @@ struct ConvArgs {
            // bf16 large-layer form (kBf16LargeRows rows x 64 channels per workgroup; n_tiles >= 2,
            // no head)
   int out_bf16;  // fp8 layers: store max(y, 0) as bf16 (unscaled) instead of e4m3
-  // G_FIRST (fp32): src0 is the guide and the layer's input is the network's
-  // first layer, recomputed per tile from its packed weights and bias
-  const float* w0;
+  // G_FIRST: src0 is the guide and the layer's input is the network's first
+  // layer, recomputed per tile from its packed weights and bias (fp8: stored
+  // as e4m3 of y * w0_out_inv, the first layer's output scale)
+  const void* w0;
   const float* b0;
+  float w0_out_inv;
 };
 // Sum the split partials in split order, then bias, (scale,) ReLU and the
 // output conversion of out_type (0 fp32, 1 bf16, 2 fp8; 3: fp8 partials,
