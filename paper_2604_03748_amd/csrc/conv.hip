@@ -20,6 +20,7 @@
 // channel 4g + jj for both operands, so each lane fetches its four channels of
 // A and of B with one 16-byte LDS read.
 #include "internal.h"
+#include "first_layer.h"
 #include "head.h"
 
 namespace lnm {
@@ -111,33 +112,18 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a, HeadFuse hf) {
 #pragma unroll
     for (int nf = 0; nf < NF; ++nf) acc[mf][nf] = f4{0.f, 0.f, 0.f, 0.f};
 
-  // G_FIRST: the guide over the (TH+4) x 20 pixels that the first layer's
-  // outputs on this tile's halo read, zero outside the image; per chunk the
-  // first layer's outputs at the HP halo pixels are a K = 27 product on the
-  // matrix cores (A: the pixels' 3x3 x 3 guide values from LDS, B: the
-  // chunk's 16 channels of first-layer weights), 16-pixel blocks spread over
-  // the four waves, then bias and ReLU.  The products are taken in the first
-  // layer's own K order (tap, then guide channel), and the outputs matched
-  // the separate first layer's bit for bit wherever they were compared
-  constexpr int GW = kTW + 4, NG = MODE == G_FIRST ? (TH + 4) * GW : 1;
-  constexpr int HP = (TH + 2) * kHW, HB = (HP + 15) / 16, BPW = (HB + 3) / 4;
-  __shared__ f4 s_g[NG];
-  float fr[MODE == G_FIRST ? 4 * BPW : 1];
-  auto stage_guide = [&]() {
-    const float* gs = static_cast<const float*>(a.src0);
-    for (int p = tid; p < NG; p += 256) {
-      const int y = y0 + p / GW - 2, x = x0 + p % GW - 2;
-      f4 v = f4{0.f, 0.f, 0.f, 0.f};
-      if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
-        const float* q = gs + ((size_t)(b * a.H + y) * a.W + x) * 3;
-        v = f4{q[0], q[1], q[2], 0.0f};
-      }
-      s_g[p] = v;
-    }
-  };
+  // G_FIRST: per chunk, the first layer's outputs at the halo pixels are a
+  // K = 27 product on the matrix cores (A: the pixels' 3x3 x 3 staged guide
+  // values, B: the chunk's 16 channels of first-layer weights), then bias
+  // and ReLU.  The products are taken in the first layer's own K order (tap,
+  // then guide channel), and the outputs matched the separate first layer's
+  // bit for bit wherever they were compared.
+  using FT = first::Tile<TH>;
+  __shared__ f4 s_g[MODE == G_FIRST ? FT::NG : 1];
+  float fr[MODE == G_FIRST ? 4 * FT::BPW : 1];
   auto first_layer = [&](int ch) {
-    // B: W0[k][n] for k = 4 s + g (tap k / 3, guide channel k % 3; k = 27 is
-    // padding), n = ch * 16 + li, from the packed [n / 32][tap][n % 32][c (4)]
+    // B: W0[k][n] for k = 4 s + g, n = ch * 16 + li, from the packed
+    // [n / 32][tap][n % 32][c (4)]
     const int n = ch * CK + li;
     const float* w = static_cast<const float*>(a.w0) + (size_t)(n / kBN) * 9 * kBN * 4 + (n % kBN) * 4;
     float bk[7];
@@ -147,20 +133,16 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a, HeadFuse hf) {
       bk[st] = k < 27 ? w[(k / 3) * kBN * 4 + k % 3] : 0.0f;
     }
     const float bias = a.b0[n];
-    const float* sg = reinterpret_cast<const float*>(s_g);
 #pragma unroll
-    for (int bb = 0; bb < BPW; ++bb) {
-      const int blk = wave * BPW + bb;
-      if (blk >= HB) break;
+    for (int bb = 0; bb < FT::BPW; ++bb) {
+      const int blk = wave * FT::BPW + bb;
+      if (blk >= FT::HB) break;
       // A: row li of the block is halo pixel p (clamped into the halo)
-      const int p = min(blk * 16 + li, HP - 1), py = p / kHW, px = p - py * kHW;
+      const int p = min(blk * 16 + li, FT::HP - 1);
       f4 d = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int st = 0; st < 7; ++st) {
-        const int k = 4 * st + g, tap = k / 3;
-        const float av = k < 27 ? sg[((py + tap / 3) * GW + px + tap % 3) * 4 + k % 3] : 0.0f;
-        d = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bk[st], d, 0, 0, 0);
-      }
+      for (int st = 0; st < 7; ++st)
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(first::guide_slot(s_g, p, 4 * st + g), bk[st], d, 0, 0, 0);
       // D: rows 4g + r of the block (pixels), column li (channel)
 #pragma unroll
       for (int r = 0; r < 4; ++r) fr[4 * bb + r] = fmaxf(d[r] + bias, 0.0f);
@@ -198,16 +180,13 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a, HeadFuse hf) {
       // this lane's first-layer outputs: channel li at halo pixels
       // 16 blk + 4g + r (zero padding outside the image)
 #pragma unroll
-      for (int bb = 0; bb < BPW; ++bb) {
-        const int blk = wave * BPW + bb;
-        if (blk >= HB) break;
+      for (int bb = 0; bb < FT::BPW; ++bb) {
+        const int blk = wave * FT::BPW + bb;
+        if (blk >= FT::HB) break;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int q = blk * 16 + 4 * g + r;
-          if (q >= HP) continue;
-          const int py = q / kHW, y = y0 + py - 1, x = x0 + q - py * kHW - 1;
-          const bool in = y >= 0 && y < a.H && x >= 0 && x < a.W;
-          s_in[buf][q * PIN + li] = in ? fr[4 * bb + r] : 0.0f;
+          if (q < FT::HP) s_in[buf][q * PIN + li] = first::halo_inside(a, y0, x0, q) ? fr[4 * bb + r] : 0.0f;
         }
       }
     }
@@ -228,7 +207,7 @@ __global__ __launch_bounds__(256) void conv3x3_f32(ConvArgs a, HeadFuse hf) {
   if constexpr (MODE == G_FIRST) {
     // the first chunk's weights in flight while the guide is staged
     if (ch_lo < ch_hi) fetch_w(ch_lo);
-    stage_guide();
+    first::stage_guide<TH>(a, b, y0, x0, s_g);
     __syncthreads();
     if (ch_lo < ch_hi) {
       first_layer(ch_lo);

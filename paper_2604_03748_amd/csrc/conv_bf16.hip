@@ -16,6 +16,7 @@
 // The 3-channel input layer packs all 27 (tap, channel) pairs of its 3x3
 // window into one 32-wide K step instead of padding each tap to 32 channels.
 #include "internal.h"
+#include "first_layer.h"
 #include "head.h"
 
 namespace lnm {
@@ -158,61 +159,17 @@ __global__ __launch_bounds__(256) void conv3x3_bf16(ConvArgs a, HeadFuse hf) {
 #pragma unroll
     for (int nf = 0; nf < NF; ++nf) acc[mf][nf] = f4{0.f, 0.f, 0.f, 0.f};
 
-  // G_FIRST: the guide over the (TH+4) x 20 pixels that the first layer's
-  // outputs on this tile's halo read, zero outside the image; per chunk the
-  // first layer's 32 outputs at the HP halo pixels are one K = 32 product
-  // per 16-pixel block and 16 channels, formed exactly as the first layer's
-  // own kernel forms them (the same bf16 operands in the same K slots, bias,
-  // ReLU, one rounding to bf16), so the result is the same bit for bit
-  constexpr int GW = kTW + 4, NG = MODE == G_FIRST ? (TH + 4) * GW : 1;
-  constexpr int HP = (TH + 2) * kHW, HB = (HP + 15) / 16, BPW = (HB + 3) / 4;
-  __shared__ f4 s_g[NG];
-  uint16_t fr[MODE == G_FIRST ? 8 * BPW : 1];
-  auto stage_guide = [&]() {
-    const float* gs = static_cast<const float*>(a.src0);
-    for (int p = tid; p < NG; p += 256) {
-      const int y = y0 + p / GW - 2, x = x0 + p % GW - 2;
-      f4 v = f4{0.f, 0.f, 0.f, 0.f};
-      if (y >= 0 && y < a.H && x >= 0 && x < a.W) {
-        const float* q = gs + ((size_t)(b * a.H + y) * a.W + x) * 3;
-        v = f4{q[0], q[1], q[2], 0.0f};
-      }
-      s_g[p] = v;
-    }
-  };
+  // G_FIRST: the first layer's outputs on the halo, formed from the staged
+  // guide as the first layer's own kernel forms them (the same bf16
+  // operands in the same K slots, bias, ReLU, one rounding to bf16), so the
+  // result is the same bit for bit
+  using FT = first::Tile<TH>;
+  __shared__ f4 s_g[MODE == G_FIRST ? FT::NG : 1];
+  uint16_t fr[MODE == G_FIRST ? 8 * FT::BPW : 1];
   auto first_layer = [&](int ch) {
-    // B: the first layer's packed weights [n-tile][n (32)][k = 3 tap + c (32)]
-    const uint16_t* w0 = reinterpret_cast<const uint16_t*>(a.w0) + (size_t)ch * kBN * 32;
-    bf16x8 bv[2];
-    float bias[2];
-#pragma unroll
-    for (int nf = 0; nf < 2; ++nf) {
-      bv[nf] = *reinterpret_cast<const bf16x8*>(w0 + (nf * 16 + li) * 32 + 8 * g);
-      bias[nf] = a.b0[ch * kBN + nf * 16 + li];
-    }
-    const float* sg = reinterpret_cast<const float*>(s_g);
-#pragma unroll
-    for (int bb = 0; bb < BPW; ++bb) {
-      const int blk = wave * BPW + bb;
-      if (blk >= HB) break;
-      // A: row li of the block is halo pixel p (clamped into the halo), K
-      // slot k = 8g + s the guide value of tap k / 3, channel k % 3
-      const int p = min(blk * 16 + li, HP - 1), py = p / kHW, px = p - py * kHW;
-      bf16x8 av;
-#pragma unroll
-      for (int s8 = 0; s8 < 8; ++s8) {
-        const int k = 8 * g + s8, tap = k / 3;
-        const float v = k < 27 ? sg[((py + tap / 3) * GW + px + tap % 3) * 4 + k % 3] : 0.0f;
-        av[s8] = __builtin_bit_cast(__bf16, f2bf(v));
-      }
-#pragma unroll
-      for (int nf = 0; nf < 2; ++nf) {
-        const f4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nf], f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-        // D: rows 4g + r of the block (pixels), column li of channel block nf
-#pragma unroll
-        for (int r = 0; r < 4; ++r) fr[8 * bb + 4 * nf + r] = f2bf(fmaxf(d[r] + bias[nf], 0.0f));
-      }
-    }
+    first::first_layer_bf16<TH>(a, ch, s_g, [&](int bb, int nf, int r, float v) {
+      fr[8 * bb + 4 * nf + r] = f2bf(fmaxf(v, 0.0f));
+    });
   };
 
   constexpr int NQ = (TH + 2) * kHW * (kCK / 8), NW = 9 * BN * kCK / 8;
@@ -250,15 +207,14 @@ __global__ __launch_bounds__(256) void conv3x3_bf16(ConvArgs a, HeadFuse hf) {
       // this lane's first-layer outputs: channels 16 nf + li at halo pixels
       // 16 blk + 4g + r (zero padding outside the image)
 #pragma unroll
-      for (int bb = 0; bb < BPW; ++bb) {
-        const int blk = wave * BPW + bb;
-        if (blk >= HB) break;
+      for (int bb = 0; bb < FT::BPW; ++bb) {
+        const int blk = wave * FT::BPW + bb;
+        if (blk >= FT::HB) break;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int q = blk * 16 + 4 * g + r;
-          if (q >= HP) continue;
-          const int py = q / kHW, y = y0 + py - 1, x = x0 + q - py * kHW - 1;
-          const bool in = y >= 0 && y < a.H && x >= 0 && x < a.W;
+          if (q >= FT::HP) continue;
+          const bool in = first::halo_inside(a, y0, x0, q);
 #pragma unroll
           for (int nf = 0; nf < 2; ++nf) s_in[buf][q * kPad + nf * 16 + li] = in ? fr[8 * bb + 4 * nf + r] : 0;
         }
@@ -278,7 +234,7 @@ __global__ __launch_bounds__(256) void conv3x3_bf16(ConvArgs a, HeadFuse hf) {
   };
 
   if constexpr (MODE == G_FIRST) {
-    stage_guide();
+    first::stage_guide<TH>(a, b, y0, x0, s_g);
     __syncthreads();
   }
   if (ch_lo < ch_hi) {
