@@ -375,7 +375,7 @@ def precision_report(lnm, ctx, wl, params, dens, weights="He-normal seed 0 (untr
 # and buffers (plan.hip)
 CONV_SOURCES = ("paper_2604_03748_amd/csrc/conv.hip", "paper_2604_03748_amd/csrc/conv_bf16.hip",
                 "paper_2604_03748_amd/csrc/conv_fp8.hip", "paper_2604_03748_amd/csrc/head.h",
-                "paper_2604_03748_amd/csrc/plan.hip")
+                "paper_2604_03748_amd/csrc/first_layer.h", "paper_2604_03748_amd/csrc/plan.hip")
 MARCH_SOURCES = ("paper_2604_03748_amd/csrc/march.hip", "paper_2604_03748_amd/csrc/ray.h",
                  "paper_2604_03748_amd/csrc/plan.hip")
 
