@@ -363,11 +363,14 @@ __device__ __forceinline__ float light_transmittance_batched(const MarchDev& m, 
       sample_batch_flat<4>(m, px, py, fz, sv);
     else
       sample_batch<4>(m, px, py, pz, sv);
+    // the depth is tested after each sample, the branch taken once per batch
+    bool over = false;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       acc += k + q <= kmax ? sv[q] : 0.0f;
-      if (acc > lim) return 0.0f;
+      over |= acc > lim;
     }
+    if (over) return 0.0f;
   }
   return expf(-acc * h);
 }
@@ -420,13 +423,16 @@ __device__ __forceinline__ float light_transmittance_lds(const MarchDev& m, V3 x
       c[q][2] = a[pitch];
       c[q][3] = a[pitch + 1];
     }
+    // the depth is tested after each sample, the branch taken once per batch
+    bool over = false;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const float sv = m.sigma_scale * flat_lerp(c[q][0].x, c[q][0].y, c[q][1].x, c[q][1].y, c[q][2].x, c[q][2].y,
                                                  c[q][3].x, c[q][3].y, t[q].fx, t[q].fy, fz.fz);
       acc += k + q <= kmax ? sv : 0.0f;
-      if (acc > lim) return 0.0f;
+      over |= acc > lim;
     }
+    if (over) return 0.0f;
   }
   return expf(-acc * h);
 }
