@@ -213,13 +213,17 @@ __device__ __forceinline__ void sample_batch_flat(const MarchDev& m, const float
 }
 
 // Fill the bricked grid from the caller's linear grid (HBM-bound copy; once
-// per march, or once per grid with lnm_make_bricks).  Workgroup = 31
+// per march, or once per grid with lnm_make_bricks).  Workgroup = up to 17
 // consecutive bricks along x at one (by, bz): it stages the 25 source rows
-// they cover (5 y x 5 z rows of 4*31+1 = 125 floats) in LDS, each lane
+// they cover (5 y x 5 z rows of 4*17+1 = 69 floats) in LDS, each lane
 // issuing its 12 or 13 row loads together (out-of-grid entries read a valid
-// address and are zeroed), then writes the 31 slots (15.5 KB, contiguous)
-// with coalesced stores.  Slot entries 125..127 are zero padding.
-constexpr int kRelayBricks = 31, kRelayRow = 4 * kRelayBricks + 1;
+// address and are zeroed), then writes the slots (8.5 KB, contiguous) with
+// coalesced stores.  Slot entries 125..127 are zero padding.  (17 splits a
+// row of 33 bricks, the 128^3 grid's, into 17 + 16, and 65 into
+// 17 + 17 + 17 + 14: runs of 31 left a second workgroup of 2 bricks per
+// row, 10.4 us per relayout at 128^3 against 9.3.)
+constexpr int kRelayBricks = 17, kRelayRow = 4 * kRelayBricks + 1;
+static_assert(kRelayRow <= 128, "a staged row is one pass of 128 lanes");
 __device__ __forceinline__ void relayout_block(const float* __restrict__ rho, int nx, int ny, int nz, int nbx, int nby,
                                                float* __restrict__ brick, float (&rows)[25][kRelayRow], int bxb,
                                                int by, int bz) {
