@@ -213,53 +213,57 @@ __device__ __forceinline__ void sample_batch_flat(const MarchDev& m, const float
 }
 
 // Fill the bricked grid from the caller's linear grid (HBM-bound copy; once
-// per march, or once per grid with lnm_make_bricks).  Workgroup = up to 17
-// consecutive bricks along x at one (by, bz): it stages the 25 source rows
-// they cover (5 y x 5 z rows of 4*17+1 = 69 floats) in LDS, each lane
-// issuing its 12 or 13 row loads together (out-of-grid entries read a valid
-// address and are zeroed), then writes the slots (8.5 KB, contiguous) with
-// coalesced stores.  Slot entries 125..127 are zero padding.  (17 splits a
-// row of 33 bricks, the 128^3 grid's, into 17 + 16, and 65 into
-// 17 + 17 + 17 + 14: runs of 31 left a second workgroup of 2 bricks per
-// row, 10.4 us per relayout at 128^3 against 9.3.)
-constexpr int kRelayBricks = 17, kRelayRow = 4 * kRelayBricks + 1;
-static_assert(kRelayRow <= 128, "a staged row is one pass of 128 lanes");
+// per march, or once per grid with lnm_make_bricks).  Workgroup = up to
+// kRelayBricks consecutive bricks along x in kRelayY brick rows at one bz:
+// it stages the source rows they cover (4 kRelayY + 1 y rows x 5 z planes
+// of 4 kRelayBricks + 1 floats) in LDS, the rows read as one flat run of
+// entries so every lane issues all its loads together (out-of-grid entries
+// read a valid address and are zeroed), then writes each brick row's slots
+// (contiguous) with coalesced stores.  Slot entries 125..127 are zero
+// padding.  Runs of 11 bricks split a row of 33 (the 128^3 grid's) evenly;
+// at 128^3 the relayout took 8.4 us against 8.9 with runs of 17 (and 10.4
+// with runs of 31, which left a 2-brick workgroup per row); two brick rows
+// per workgroup took 9.1.
+constexpr int kRelayBricks = 11, kRelayRow = 4 * kRelayBricks + 1, kRelayY = 1;
+constexpr int kRelayRows = 5 * (4 * kRelayY + 1), kRelayLoads = (kRelayRows * kRelayRow + 255) / 256;
 __device__ __forceinline__ void relayout_block(const float* __restrict__ rho, int nx, int ny, int nz, int nbx, int nby,
-                                               float* __restrict__ brick, float (&rows)[25][kRelayRow], int bxb,
-                                               int by, int bz) {
-  const int bx0 = bxb * kRelayBricks;
-  const int x = threadIdx.x & 127, r0 = threadIdx.x >> 7;  // column, first row (rows r0, r0 + 2, ...)
-  const int i = 4 * bx0 + x - 1;
-  float v[13];
+                                               float* __restrict__ brick, float (&rows)[kRelayRows][kRelayRow],
+                                               int bxb, int byb, int bz) {
+  constexpr int RY = 4 * kRelayY + 1;  // staged y rows per z plane
+  const int bx0 = bxb * kRelayBricks, by0 = byb * kRelayY;
+  float* flat = &rows[0][0];
+  float v[kRelayLoads];
 #pragma unroll
-  for (int q = 0; q < 13; ++q) {
-    const int r = r0 + 2 * q;
-    const int j = 4 * by + r % 5 - 1, k = 4 * bz + r / 5 - 1;
-    const bool ok = x < kRelayRow && r < 25 && i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
+  for (int q = 0; q < kRelayLoads; ++q) {
+    const int e = (int)threadIdx.x + 256 * q, r = e / kRelayRow, x = e - r * kRelayRow;
+    const int i = 4 * bx0 + x - 1, j = 4 * by0 + r % RY - 1, k = 4 * bz + r / RY - 1;
+    const bool ok = e < kRelayRows * kRelayRow && i < nx && j < ny && k < nz && i >= 0 && j >= 0 && k >= 0;
     const size_t src = ok ? ((size_t)k * ny + j) * nx + i : 0;
     v[q] = rho[src] * (ok ? 1.0f : 0.0f);
   }
 #pragma unroll
-  for (int q = 0; q < 13; ++q) {
-    const int r = r0 + 2 * q;
-    if (x < kRelayRow && r < 25) rows[r][x] = v[q];
+  for (int q = 0; q < kRelayLoads; ++q) {
+    const int e = (int)threadIdx.x + 256 * q;
+    if (e < kRelayRows * kRelayRow) flat[e] = v[q];
   }
   __syncthreads();
-  const int nb = min(kRelayBricks, nbx - bx0);
-  float* out = brick + (((size_t)bz * nby + by) * nbx + bx0) * kBrickSlot;
+  const int nb = min(kRelayBricks, nbx - bx0), nyb = min(kRelayY, nby - by0);
   // a thread keeps one slot entry s of every brick it writes (256 threads,
   // 128-entry slots), so its row and column in the staged rows are fixed
   static_assert(256 % kBrickSlot == 0, "slot entries per thread");
   const int s = threadIdx.x & (kBrickSlot - 1);
   const bool live = s < 125;
-  const int rr = live ? (s / 25) * 5 + (s / 5) % 5 : 0, cc = s % 5;
-  for (int b = threadIdx.x / kBrickSlot; b < nb; b += 256 / kBrickSlot)
-    out[b * kBrickSlot + s] = live ? rows[rr][4 * b + cc] : 0.0f;
+  const int rr = live ? (s / 25) * RY + (s / 5) % 5 : 0, cc = s % 5;
+  for (int yb = 0; yb < nyb; ++yb) {
+    float* out = brick + (((size_t)bz * nby + by0 + yb) * nbx + bx0) * kBrickSlot;
+    for (int b = threadIdx.x / kBrickSlot; b < nb; b += 256 / kBrickSlot)
+      out[b * kBrickSlot + s] = live ? rows[rr + 4 * yb][4 * b + cc] : 0.0f;
+  }
 }
 
 __global__ __launch_bounds__(256) void relayout_bricks(const float* __restrict__ rho, int nx, int ny, int nz, int nbx,
                                                        int nby, float* __restrict__ brick) {
-  __shared__ float rows[25][kRelayRow];
+  __shared__ float rows[kRelayRows][kRelayRow];
   relayout_block(rho, nx, ny, nz, nbx, nby, brick, rows, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
@@ -775,7 +779,7 @@ __global__ __launch_bounds__(256) void march_balance(MarchDev m, CamDev c, TileM
 __global__ __launch_bounds__(256) void relayout_balance(MarchDev m, CamDev c, TileMap tm, int* __restrict__ ctr,
                                                         float* __restrict__ brick) {
   __shared__ union {
-    float rows[25][kRelayRow];
+    float rows[kRelayRows][kRelayRow];
     BalanceLds bal;
   } sh;
   if (blockIdx.z == 0) {
@@ -1284,8 +1288,9 @@ constexpr size_t kLightSlots = 512;  // workgroups per band in march_lights (ban
 
 hipError_t launch_relayout(const MarchDev& m, float* bricks, hipStream_t s) {
   const int nbx = bricks_along(m.nx), nby = bricks_along(m.ny), nbz = bricks_along(m.nz);
-  hipLaunchKernelGGL(relayout_bricks, dim3((nbx + kRelayBricks - 1) / kRelayBricks, nby, nbz), dim3(256), 0, s, m.rho,
-                     m.nx, m.ny, m.nz, nbx, nby, bricks);
+  hipLaunchKernelGGL(relayout_bricks,
+                     dim3((nbx + kRelayBricks - 1) / kRelayBricks, (nby + kRelayY - 1) / kRelayY, nbz), dim3(256), 0, s,
+                     m.rho, m.nx, m.ny, m.nz, nbx, nby, bricks);
   return hipGetLastError();
 }
 
@@ -1346,8 +1351,9 @@ hipError_t launch_march(const MarchDev& m0, const CamDev& cam, const MarchBuf& b
   const TileMap tm = tile_map(cam);
   if (!m.brick) {  // build the bricks in the scratch; one extra block balances the bands
     m.brick = buf.brick;
-    hipLaunchKernelGGL(relayout_balance, dim3((m.nbx + kRelayBricks - 1) / kRelayBricks, m.nby, m.nbz + 1), dim3(256),
-                       0, s, m, cam, tm, buf.ctr, buf.brick);
+    hipLaunchKernelGGL(relayout_balance,
+                       dim3((m.nbx + kRelayBricks - 1) / kRelayBricks, (m.nby + kRelayY - 1) / kRelayY, m.nbz + 1),
+                       dim3(256), 0, s, m, cam, tm, buf.ctr, buf.brick);
   } else {
     hipLaunchKernelGGL(march_balance, dim3(1), dim3(kBalanceThreads), 0, s, m, cam, tm, buf.ctr);
   }
